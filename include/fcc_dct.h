@@ -1,0 +1,149 @@
+/*
+ * fcc_dct.h -- C ABI of the MI355X (gfx950) fast FCC cosine transform.
+ *
+ * The transform (Seifert, Hueper, Uhl, "Fast cosine transform for FCC
+ * lattices", Sec. IV-A, Definition 2 and eq. SU4ChebyshevTransformExplicitForm):
+ *
+ *     X[j] = sum_{k in [0,n)^3} T_k(theta_j) x[k],   theta_j = ((r,s,t) + j) / n,
+ *
+ * where T_k are the three-variable Chebyshev polynomials of the Weyl group
+ * S_4 (Sec. III, Definition 1) and the rows j are the common zeros of the
+ * skew ideal (Lemma 2).  The default skew (r,s,t) = (1/8, 0, 3/8) gives the
+ * FCC cosine transform DCT_{n x n x n}.  Input x holds the coefficients of the
+ * basis b_n = (T_k | k in [0,n)^3) (eq. ZTransformFCC); output X holds the
+ * values at the zeros.  Both are flattened lexicographically:
+ * (a,b,c) -> (a*n + b)*n + c.  No normalisation is applied; the inverse is the
+ * exact matrix inverse (the matrix is not unitary).
+ *
+ * The fast path is the radix-2x2x2 factorisation of Sec. IV-B (eq.
+ * FastAlgorithm), applied level by level:
+ *     DCT_n(r,s,t) = P_n (+)_i DCT_{n/2}(((r,s,t)+i)/2) (DCT_2(r,s,t) (x) I) B_n(r,s,t).
+ * It needs n = 2^d (Sec. IV-B).
+ *
+ * Conventions for every call:
+ *   - Data pointers are DEVICE pointers (hipMalloc'd memory or torch tensors),
+ *     at least 16-byte aligned, owned by the caller.  Calls are out of place:
+ *     input and output must not overlap.
+ *   - Real arrays hold n^3 elements; complex arrays hold n^3 interleaved
+ *     (re, im) pairs.  The element type is set by the plan's precision:
+ *       FCC_PREC_FP64                    : double / double2
+ *       FCC_PREC_FP32, FCC_PREC_SPLIT_*  : float  / float2
+ *   - `hip_stream` is a hipStream_t (NULL = the default stream).  Calls only
+ *     enqueue work on it and never synchronise; errors raised by kernels show
+ *     up at the caller's next synchronisation.
+ *   - Every call returns a status and never throws.  A plan executes on one
+ *     stream at a time (it owns scratch buffers).
+ */
+#ifndef FCC_DCT_H
+#define FCC_DCT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fcc_plan_s* fcc_plan_t;
+
+typedef enum {
+  FCC_OK = 0,
+  FCC_ERR_INVALID_ARG = 1,   /* null or misaligned pointer, bad count/direction   */
+  FCC_ERR_NOT_POW2 = 2,      /* n is not a power of two in [1, 1024]              */
+  FCC_ERR_SINGULAR_SKEW = 3, /* (r,s,t) gives coinciding zeros somewhere in the tree */
+  FCC_ERR_OOM = 4,           /* device or host allocation failed                   */
+  FCC_ERR_HIP = 5,           /* a HIP runtime call failed                          */
+  FCC_ERR_UNSUPPORTED = 6    /* valid request this build does not serve            */
+} fcc_status;
+
+typedef enum {
+  FCC_PREC_FP64 = 0,       /* FP64 data, FP64 stages                                */
+  FCC_PREC_FP32 = 1,       /* FP32 data; stage precision chosen by the plan (below) */
+  FCC_PREC_SPLIT_BF16 = 2, /* FP32 data; dense base on MFMA, split hi+lo BF16, FP32 acc */
+  FCC_PREC_SPLIT_FP16 = 3  /* FP32 data; dense base on MFMA, split hi+lo FP16, FP32 acc */
+} fcc_precision;
+
+enum {
+  /* Forward input is real (n^3 reals); the inverse then writes the real part. */
+  FCC_REAL_INPUT = 1u << 0,
+  /* Force FP32 intermediate stages for FCC_PREC_FP32 (fast, but the skew
+   * sub-transforms lose accuracy with depth; see the plan's error model).      */
+  FCC_STAGES_FP32 = 1u << 1,
+  /* Force FP64 intermediate stages for FCC_PREC_FP32.                          */
+  FCC_STAGES_FP64 = 1u << 2
+};
+
+/* Build a plan for DCT_{n x n x n}(r,s,t) (Definition 2).
+ *   plan  : receives the new plan (set to NULL on failure).
+ *   n     : size parameter, a power of two in [1, 1024] (fast algorithm, Sec. IV-B).
+ *   rst   : host pointer to the skew (r,s,t), or NULL for (1/8, 0, 3/8).
+ *   prec  : data/compute precision (fcc_precision).  The split-MFMA precisions
+ *           apply the dense transform matrix and need n <= 8.
+ *   flags : FCC_REAL_INPUT | FCC_STAGES_FP32 | FCC_STAGES_FP64.
+ * Derives the basis-change patterns on the host (cached per node size),
+ * uploads them, generates FP64 tables on the GPU on `hip_stream`, allocates
+ * scratch, and synchronises `hip_stream` once before returning.
+ * Errors: FCC_ERR_NOT_POW2, FCC_ERR_SINGULAR_SKEW, FCC_ERR_INVALID_ARG,
+ * FCC_ERR_UNSUPPORTED, FCC_ERR_OOM, FCC_ERR_HIP. */
+fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precision prec,
+                        unsigned flags, void* hip_stream);
+
+/* X = DCT_n(r,s,t) x  (eq. FastAlgorithm applied recursively, output
+ * permutation P_n folded into the addressing).
+ *   x : n^3 reals (FCC_REAL_INPUT) or complex; X : n^3 complex. */
+fcc_status fcc_dct_forward(fcc_plan_t plan, const void* x, void* X, void* hip_stream);
+
+/* x = DCT_n(r,s,t)^{-1} X: the factors of eq. FastAlgorithm inverted in reverse
+ * order (P_n^T, inverse skew sub-transforms, DCT_2^{-1} (x) I, then the
+ * product expansion C_n = B_n^{-1}).
+ *   X : n^3 complex; x : n^3 complex, or the real part only (FCC_REAL_INPUT). */
+fcc_status fcc_dct_inverse(fcc_plan_t plan, const void* X, void* x, void* hip_stream);
+
+/* Many independent transforms in one call; plans may differ in n.
+ *   plans[i], in[i], out[i] for i < count; direction +1 forward (in -> out),
+ *   -1 inverse (in -> out), 0 forward then inverse (in -> out, then out -> in,
+ *   overwriting in[i] with the round trip).
+ * The first call with a given (plans, pointers, direction) records the launch
+ * sequence into a HIP graph; later identical calls replay it.  Volumes with
+ * the same plan configuration share each level launch.
+ * Errors: FCC_ERR_INVALID_ARG (count < 1, null entries, direction), plus the
+ * errors of the single-volume calls. */
+fcc_status fcc_dct_batched(const fcc_plan_t* plans, int count, const void* const* in,
+                           void* const* out, int direction, void* hip_stream);
+
+/* Free the plan's device tables, scratch and cached graphs.  NULL is a no-op. */
+fcc_status fcc_dct_destroy(fcc_plan_t plan);
+
+/* Static description of a status code. */
+const char* fcc_status_string(fcc_status s);
+
+/* ---- introspection (host logic; no GPU needed) ------------------------- */
+
+/* Host view of the basis-change tables for one node size nl = 2m (2 <= nl <= 1024).
+ * Gather form, grouped by 2x2x2 cube:
+ *   forward (B_nl): row r = cube*8 + d, cube = (a*m+b)*m+c for abc in [0,m)^3,
+ *     d = (d0*2+d1)*2+d2 for def in {0,1}^3; the row yields the coordinate of
+ *     b~_(def,abc) = T_abc * T_{m*def}, stored at node-local position def + 2*abc.
+ *     Entries: source node-local index kappa packed as (kx<<20)|(ky<<10)|kz and a
+ *     coefficient-polynomial id.
+ *   inverse (C_nl): row r = cube*8 + i, for node-local kappa = i + 2*abc; entries
+ *     name the source position def + 2*abc (packed the same way).
+ *   Polynomial p has coefficients poly[p*nmono + q] of the monomial
+ *     c1^e1 c2^e2 c3^e3 with (e1,e2,e3) = mono[3q..3q+2], c = (sigma,tau,rho)(node).
+ * Pointers stay valid until the process ends.  Returns FCC_ERR_NOT_POW2 for a
+ * bad nl, FCC_ERR_OOM if the derivation cannot allocate. */
+typedef struct {
+  int nl, m, nmono, npoly;
+  const int* mono;       /* 3*nmono exponents                      */
+  const double* poly;    /* npoly*nmono coefficients               */
+  const int* b_rowptr;   /* 8*m^3 + 1                              */
+  const unsigned* b_src; /* b_rowptr[8 m^3] packed source indices  */
+  const unsigned short* b_pid;
+  const int* c_rowptr;   /* 8*m^3 + 1                              */
+  const unsigned* c_src;
+  const unsigned short* c_pid;
+} fcc_level_tables;
+
+fcc_status fcc_asp_tables(int nl, fcc_level_tables* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FCC_DCT_H */

@@ -1,0 +1,13 @@
+"""MI355X-native fast FCC cosine transform (Seifert, Hueper, Uhl, Sec. IV-B).
+
+The transform runs in the HIP library ``libfccdct.so`` (built by
+``paper_1807_10058_amd.build``); this package only marshals arguments to its
+C ABI (``include/fcc_dct.h``).  There is no CPU fallback: importing the
+binding raises if the library is missing.
+"""
+from .binding import (  # noqa: F401
+    FCC_PREC_FP32, FCC_PREC_FP64, FCC_PREC_SPLIT_BF16, FCC_PREC_SPLIT_FP16,
+    FCC_REAL_INPUT, FCC_STAGES_FP32, FCC_STAGES_FP64, FccError, fcc_asp_tables,
+    fcc_dct_batched, fcc_dct_destroy, fcc_dct_forward, fcc_dct_inverse,
+    fcc_dct_plan, fcc_status_string, lib_path,
+)

@@ -1,0 +1,153 @@
+"""ctypes binding of include/fcc_dct.h.  Same names as the C ABI; the only work
+done here is argument marshalling (torch tensors or raw device pointers to
+integers, status codes to exceptions)."""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libfccdct.so")
+
+FCC_OK = 0
+FCC_PREC_FP64, FCC_PREC_FP32, FCC_PREC_SPLIT_BF16, FCC_PREC_SPLIT_FP16 = 0, 1, 2, 3
+FCC_REAL_INPUT, FCC_STAGES_FP32, FCC_STAGES_FP64 = 1, 2, 4
+
+if not os.path.exists(_LIB_PATH):
+    raise ImportError("libfccdct.so is not built: run `python -m paper_1807_10058_amd.build` "
+                      "(or __graft_entry__.build())")
+_lib = ctypes.CDLL(_LIB_PATH)
+
+
+class _LevelTables(ctypes.Structure):
+    _fields_ = [("nl", ctypes.c_int), ("m", ctypes.c_int), ("nmono", ctypes.c_int), ("npoly", ctypes.c_int),
+                ("mono", ctypes.POINTER(ctypes.c_int)), ("poly", ctypes.POINTER(ctypes.c_double)),
+                ("b_rowptr", ctypes.POINTER(ctypes.c_int)), ("b_src", ctypes.POINTER(ctypes.c_uint)),
+                ("b_pid", ctypes.POINTER(ctypes.c_ushort)),
+                ("c_rowptr", ctypes.POINTER(ctypes.c_int)), ("c_src", ctypes.POINTER(ctypes.c_uint)),
+                ("c_pid", ctypes.POINTER(ctypes.c_ushort))]
+
+
+_vp = ctypes.c_void_p
+_lib.fcc_dct_plan.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                              ctypes.c_uint, _vp]
+_lib.fcc_dct_forward.argtypes = [_vp, _vp, _vp, _vp]
+_lib.fcc_dct_inverse.argtypes = [_vp, _vp, _vp, _vp]
+_lib.fcc_dct_batched.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                 ctypes.c_int, _vp]
+_lib.fcc_dct_destroy.argtypes = [_vp]
+_lib.fcc_status_string.argtypes = [ctypes.c_int]
+_lib.fcc_status_string.restype = ctypes.c_char_p
+_lib.fcc_asp_tables.argtypes = [ctypes.c_int, ctypes.POINTER(_LevelTables)]
+for _f in ("fcc_dct_plan", "fcc_dct_forward", "fcc_dct_inverse", "fcc_dct_batched", "fcc_dct_destroy",
+           "fcc_asp_tables"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+def lib_path():
+    return _LIB_PATH
+
+
+class FccError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__("%s: %s" % (where, fcc_status_string(status)))
+
+
+def fcc_status_string(status):
+    return _lib.fcc_status_string(int(status)).decode()
+
+
+def _check(status, where):
+    if status != FCC_OK:
+        raise FccError(status, where)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()  # torch tensor
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Plan:
+    """Owns an fcc_plan_t; destroyed with fcc_dct_destroy."""
+
+    def __init__(self, handle, n, prec, flags):
+        self.handle, self.n, self.prec, self.flags = handle, n, prec, flags
+
+    def __del__(self):
+        try:
+            if self.handle:
+                _lib.fcc_dct_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+def fcc_dct_plan(n, rst=None, prec=FCC_PREC_FP32, flags=FCC_REAL_INPUT, stream=None):
+    h = _vp()
+    r = None if rst is None else (ctypes.c_double * 3)(*[float(v) for v in rst])
+    st = _stream(stream) if stream is not None or _torch_cuda() else None
+    _check(_lib.fcc_dct_plan(ctypes.byref(h), int(n), r, int(prec), int(flags), st), "fcc_dct_plan")
+    return Plan(h.value, int(n), int(prec), int(flags))
+
+
+def _torch_cuda():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def fcc_dct_forward(plan, x, X, stream=None):
+    _check(_lib.fcc_dct_forward(plan.handle, _ptr(x), _ptr(X), _stream(stream)), "fcc_dct_forward")
+
+
+def fcc_dct_inverse(plan, X, x, stream=None):
+    _check(_lib.fcc_dct_inverse(plan.handle, _ptr(X), _ptr(x), _stream(stream)), "fcc_dct_inverse")
+
+
+def fcc_dct_batched(plans, ins, outs, direction, stream=None):
+    cnt = len(plans)
+    P = (_vp * cnt)(*[p.handle for p in plans])
+    I = (_vp * cnt)(*[_ptr(t) for t in ins])
+    O = (_vp * cnt)(*[_ptr(t) for t in outs])
+    _check(_lib.fcc_dct_batched(P, cnt, I, O, int(direction), _stream(stream)), "fcc_dct_batched")
+
+
+def fcc_dct_destroy(plan):
+    if plan.handle:
+        _check(_lib.fcc_dct_destroy(plan.handle), "fcc_dct_destroy")
+        plan.handle = None
+
+
+def fcc_asp_tables(nl):
+    """Host copies of the basis-change gather tables for node size nl."""
+    t = _LevelTables()
+    _check(_lib.fcc_asp_tables(int(nl), ctypes.byref(t)), "fcc_asp_tables")
+    rows = 8 * t.m ** 3
+
+    def arr(p, k, dt):
+        return np.ctypeslib.as_array(p, shape=(k,)).astype(dt).copy()
+
+    out = {"nl": t.nl, "m": t.m, "nmono": t.nmono, "npoly": t.npoly,
+           "mono": arr(t.mono, 3 * t.nmono, np.int64).reshape(-1, 3),
+           "poly": arr(t.poly, t.npoly * t.nmono, np.float64).reshape(t.npoly, t.nmono)}
+    for side in ("b", "c"):
+        rp = arr(getattr(t, side + "_rowptr"), rows + 1, np.int64)
+        out[side + "_rowptr"] = rp
+        out[side + "_src"] = arr(getattr(t, side + "_src"), int(rp[-1]), np.int64)
+        out[side + "_pid"] = arr(getattr(t, side + "_pid"), int(rp[-1]), np.int64)
+    return out

@@ -1,0 +1,821 @@
+// MI355X (gfx950) implementation of the C ABI in include/fcc_dct.h: the
+// radix-2x2x2 fast FCC cosine transform of Sec. IV-B (eq. FastAlgorithm) and
+// its inverse, one launch per level (two for the inverse), FP64 or FP32
+// stages.  Layout and per-thread work are described in kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "asp_tables.hpp"
+#include "fcc_dct.h"
+#include "kernels.hpp"
+
+namespace fcc {
+
+__constant__ OrbitTerm c_dct2[kDct2Terms];
+__constant__ CTerm c_cterm[kCTerms];
+
+// ---------------------------------------------------------------------------
+// Per-node constants
+// ---------------------------------------------------------------------------
+
+// Powers h_d^k, k = -3..3, of the half phases h_d = exp(i pi phi_d) of node J
+// at level L (phi = ((r,s,t) + J) / 2^L); hph holds h_d for every J_d.
+template <typename R>
+__device__ __forceinline__ void node_powers(const double2* __restrict__ hph, int L, const int J[3],
+                                            cx<R> P[3][7]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double2 hv = hph[(d << L) + J[d]];
+    cx<R> h{R(hv.x), R(hv.y)};
+    cx<R> h2 = h * h;
+    cx<R> h3 = h2 * h;
+    P[d][3] = {R(1), R(0)};
+    P[d][4] = h;
+    P[d][5] = h2;
+    P[d][6] = h3;
+    P[d][2] = conj(h);
+    P[d][1] = conj(h2);
+    P[d][0] = conj(h3);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> phase(const cx<R> P[3][7], int l0, int l1, int l2) {
+  return P[0][l0 + 3] * P[1][l1 + 3] * P[2][l2 + 3];
+}
+
+// c = (sigma, tau, rho)(phi) = (T_100, T_010, T_001)(phi) and the monomials
+// c1^e1 c2^e2 c3^e3 used by the level's coefficient polynomials.
+template <typename R>
+__device__ __forceinline__ void node_monomials(const cx<R> P[3][7], const DevLevel& lv, cx<R>* mono) {
+  cx<R> c[3] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
+#pragma unroll
+  for (int t = 0; t < kCTerms; ++t) {
+    const CTerm& ct = c_cterm[t];
+    cx<R> p = phase(P, 2 * ct.l0, 2 * ct.l1, 2 * ct.l2);
+    c[ct.d] = c[ct.d] + R(ct.w) * p;
+  }
+  for (int q = 0; q < lv.nmono; ++q) {
+    cx<R> v{R(1), R(0)};
+    for (int d = 0; d < 3; ++d)
+      for (int e = 0; e < lv.mono[3 * q + d]; ++e) v = v * c[d];
+    mono[q] = v;
+  }
+}
+
+// Index of mu / def inside its block of A (class 1: {1,3,4,6}, class 2: {2,5,7}).
+__device__ __forceinline__ int blk_pos(int f) {
+  // f: 0 1 2 3 4 5 6 7
+  // ->  0 0 0 1 2 1 3 2
+  return (0x23121000 >> (4 * f)) & 0xF;
+}
+__device__ __forceinline__ int blk_class(int f) {
+  // f: 0 1 2 3 4 5 6 7 -> 0 1 2 1 1 2 1 2
+  return (0x21211210 >> (4 * f)) & 0xF;
+}
+
+// Blocks of A(phi): a4 (classes {1,3,4,6}) and a3 ({2,5,7}); A[0][0] = 1.
+template <typename R>
+__device__ __forceinline__ void build_A(const cx<R> P[3][7], cx<R> a4[4][4], cx<R> a3[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a4[i][j] = {R(0), R(0)};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) a3[i][j] = {R(0), R(0)};
+#pragma unroll
+  for (int t = 0; t < kDct2Terms; ++t) {
+    const OrbitTerm& ot = c_dct2[t];
+    if (ot.f == 0) continue;
+    int mu = ((ot.l0 & 1) << 2) | ((ot.l1 & 1) << 1) | (ot.l2 & 1);
+    cx<R> v = R(ot.w) * phase(P, ot.l0, ot.l1, ot.l2);
+    if (blk_class(ot.f) == 1)
+      a4[blk_pos(mu)][blk_pos(ot.f)] = a4[blk_pos(mu)][blk_pos(ot.f)] + v;
+    else
+      a3[blk_pos(mu)][blk_pos(ot.f)] = a3[blk_pos(mu)][blk_pos(ot.f)] + v;
+  }
+}
+
+// In-place 8-point Walsh-Hadamard transform: z[i] = sum_mu (-1)^(i.mu) t[mu].
+template <typename R>
+__device__ __forceinline__ void hadamard8(cx<R> t[8]) {
+#pragma unroll
+  for (int s = 1; s < 8; s <<= 1)
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (!(i & s)) {
+        cx<R> a = t[i], b = t[i | s];
+        t[i] = a + b;
+        t[i | s] = a - b;
+      }
+}
+
+// Solve M v = b in place (Gaussian elimination, partial pivoting), small K.
+template <typename R, int K>
+__device__ __forceinline__ void solve_small(cx<R> M[K][K], cx<R> b[K]) {
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    int piv = c;
+    R best = cabs2(M[c][c]);
+#pragma unroll
+    for (int r = c + 1; r < K; ++r) {
+      R v = cabs2(M[r][c]);
+      if (v > best) {
+        best = v;
+        piv = r;
+      }
+    }
+#pragma unroll
+    for (int r = c + 1; r < K; ++r)
+      if (r == piv) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          cx<R> tmp = M[c][j];
+          M[c][j] = M[r][j];
+          M[r][j] = tmp;
+        }
+        cx<R> tb = b[c];
+        b[c] = b[r];
+        b[r] = tb;
+      }
+#pragma unroll
+    for (int r = c + 1; r < K; ++r) {
+      cx<R> f = cdiv(M[r][c], M[c][c]);
+#pragma unroll
+      for (int j = c; j < K; ++j) M[r][j] = M[r][j] - f * M[c][j];
+      b[r] = b[r] - f * b[c];
+    }
+  }
+#pragma unroll
+  for (int c = K - 1; c >= 0; --c) {
+    cx<R> s = b[c];
+#pragma unroll
+    for (int j = c + 1; j < K; ++j) s = s - M[c][j] * b[j];
+    b[c] = cdiv(s, M[c][c]);
+  }
+}
+
+struct CubeIdx {
+  int J[3], a[3];
+};
+__device__ __forceinline__ CubeIdx cube_of(long long t, int n, int L) {
+  const long long h = n >> 1;
+  int qz = int(t % h), qy = int((t / h) % h), qx = int(t / (h * h));
+  int mask = (1 << L) - 1;
+  CubeIdx c;
+  c.J[0] = qx & mask;
+  c.J[1] = qy & mask;
+  c.J[2] = qz & mask;
+  c.a[0] = qx >> L;
+  c.a[1] = qy >> L;
+  c.a[2] = qz >> L;
+  return c;
+}
+__device__ __forceinline__ long long gpos(int n, int L, const int J[3], int kx, int ky, int kz) {
+  return ((long long)(J[0] + (kx << L)) * n + (J[1] + (ky << L))) * n + (J[2] + (kz << L));
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> poly_value(const DevLevel& lv, int pid, const cx<R>* mono) {
+  const double* pc = lv.poly + (long long)pid * lv.nmono;
+  cx<R> v{R(0), R(0)};
+  for (int q = 0; q < lv.nmono; ++q) v = v + R(pc[q]) * mono[q];
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+// Forward level L: basis change B_nl(phi) then DCT_2(phi) (x) I on every cube.
+template <typename R, typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_fwd_level(VolSet vs, int n, int L, DevLevel lv,
+                                                   const double2* __restrict__ hph) {
+  const long long h = n >> 1;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= h * h * h) return;
+  const TI* __restrict__ in = static_cast<const TI*>(vs.in[blockIdx.y]);
+  TO* __restrict__ out = static_cast<TO*>(vs.out[blockIdx.y]);
+  CubeIdx ci = cube_of(t, n, L);
+  const int m = (n >> L) >> 1;
+  cx<R> P[3][7];
+  node_powers(hph, L, ci.J, P);
+  cx<R> mono[kMaxMono];
+  node_monomials(P, lv, mono);
+
+  cx<R> y[8];
+  const int cube = (ci.a[0] * m + ci.a[1]) * m + ci.a[2];
+#pragma unroll
+  for (int f = 0; f < 8; ++f) {
+    const int r = cube * 8 + f;
+    cx<R> acc{R(0), R(0)};
+    for (int e = lv.b_rowptr[r]; e < lv.b_rowptr[r + 1]; ++e) {
+      uint32_t s = lv.b_src[e];
+      cx<R> v = IO<TI, R>::ld(in, gpos(n, L, ci.J, int(s >> 20), int((s >> 10) & 1023u), int(s & 1023u)));
+      acc = acc + poly_value(lv, lv.b_pid[e], mono) * v;
+    }
+    y[f] = acc;
+  }
+  // z = H_8 A(phi) y
+  cx<R> a4[4][4], a3[3][3];
+  build_A(P, a4, a3);
+  cx<R> tt[8];
+  tt[0] = y[0];
+  const int c4[4] = {1, 3, 4, 6}, c3[3] = {2, 5, 7};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    cx<R> s{R(0), R(0)};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s = s + a4[i][j] * y[c4[j]];
+    tt[c4[i]] = s;
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    cx<R> s{R(0), R(0)};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) s = s + a3[i][j] * y[c3[j]];
+    tt[c3[i]] = s;
+  }
+  hadamard8(tt);
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    IO<TO, R>::st(out, gpos(n, L, ci.J, ((i >> 2) & 1) + 2 * ci.a[0], ((i >> 1) & 1) + 2 * ci.a[1], (i & 1) + 2 * ci.a[2]),
+                  tt[i]);
+}
+
+// Inverse level L, first pass: y = DCT_2(phi)^{-1} z = A(phi)^{-1} H_8 z / 8 on every cube.
+template <typename R, typename TI>
+__global__ __launch_bounds__(256) void k_inv_dct2(VolSet vs, int n, int L, const double2* __restrict__ hph) {
+  const long long h = n >> 1;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= h * h * h) return;
+  // may run in place (in == out): each thread reads and writes only its own cube
+  const TI* in = static_cast<const TI*>(vs.in[blockIdx.y]);
+  cx<R>* out = static_cast<cx<R>*>(vs.out[blockIdx.y]);
+  CubeIdx ci = cube_of(t, n, L);
+  cx<R> z[8];
+  long long pos[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    pos[i] = gpos(n, L, ci.J, ((i >> 2) & 1) + 2 * ci.a[0], ((i >> 1) & 1) + 2 * ci.a[1], (i & 1) + 2 * ci.a[2]);
+    z[i] = IO<TI, R>::ld(in, pos[i]);
+  }
+  hadamard8(z);
+  cx<R> P[3][7];
+  node_powers(hph, L, ci.J, P);
+  cx<R> a4[4][4], a3[3][3];
+  build_A(P, a4, a3);
+  const int c4[4] = {1, 3, 4, 6}, c3[3] = {2, 5, 7};
+  cx<R> b4[4], b3[3];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) b4[i] = R(0.125) * z[c4[i]];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) b3[i] = R(0.125) * z[c3[i]];
+  solve_small<R, 4>(a4, b4);
+  solve_small<R, 3>(a3, b3);
+  cx<R> y[8];
+  y[0] = R(0.125) * z[0];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) y[c4[i]] = b4[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) y[c3[i]] = b3[i];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) out[pos[i]] = y[i];
+}
+
+// Inverse level L, second pass: x(kappa) = sum C_nl(phi)[kappa, (def,abc)] y(def + 2 abc).
+template <typename R, typename TO>
+__global__ __launch_bounds__(256) void k_inv_basis(VolSet vs, int n, int L, DevLevel lv,
+                                                   const double2* __restrict__ hph) {
+  const long long h = n >> 1;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= h * h * h) return;
+  const cx<R>* __restrict__ in = static_cast<const cx<R>*>(vs.in[blockIdx.y]);
+  TO* __restrict__ out = static_cast<TO*>(vs.out[blockIdx.y]);
+  CubeIdx ci = cube_of(t, n, L);
+  const int m = (n >> L) >> 1;
+  cx<R> P[3][7];
+  node_powers(hph, L, ci.J, P);
+  cx<R> mono[kMaxMono];
+  node_monomials(P, lv, mono);
+  const int cube = (ci.a[0] * m + ci.a[1]) * m + ci.a[2];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int r = cube * 8 + i;
+    cx<R> acc{R(0), R(0)};
+    for (int e = lv.c_rowptr[r]; e < lv.c_rowptr[r + 1]; ++e) {
+      uint32_t s = lv.c_src[e];
+      cx<R> v = in[gpos(n, L, ci.J, int(s >> 20), int((s >> 10) & 1023u), int(s & 1023u))];
+      acc = acc + poly_value(lv, lv.c_pid[e], mono) * v;
+    }
+    IO<TO, R>::st(out, gpos(n, L, ci.J, ((i >> 2) & 1) + 2 * ci.a[0], ((i >> 1) & 1) + 2 * ci.a[1], (i & 1) + 2 * ci.a[2]),
+                  acc);
+  }
+}
+
+// n = 1: the transform is the 1x1 matrix [T_0] = [1].
+template <typename TI, typename TO>
+__global__ void k_copy1(VolSet vs) {
+  if (threadIdx.x == 0) {
+    cx<double> v = IO<TI, double>::ld(static_cast<const TI*>(vs.in[blockIdx.y]), 0);
+    IO<TO, double>::st(static_cast<TO*>(vs.out[blockIdx.y]), 0, v);
+  }
+}
+
+// FP64 half phases of every level: level L, axis d, J_d -> exp(i pi (rst_d + J_d) / 2^L).
+__global__ void k_phase_table(double2* out, int D, double r0, double r1, double r2) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  // level L occupies [3 (2^L - 1), 3 (2^(L+1) - 1))
+  for (int L = 0; L < D; ++L) {
+    int base = 3 * ((1 << L) - 1), cnt = 3 << L;
+    if (idx < base || idx >= base + cnt) continue;
+    int d = (idx - base) >> L, J = (idx - base) & ((1 << L) - 1);
+    double rd = d == 0 ? r0 : (d == 1 ? r1 : r2);
+    double ang = (rd + J) / double(1 << L);  // in units of pi
+    double s, c;
+    sincospi(ang, &s, &c);
+    out[idx] = make_double2(c, s);
+  }
+}
+
+}  // namespace fcc
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+using namespace fcc;
+
+namespace {
+
+enum class DT { F32R, F64R, F32C, F64C };
+
+struct DevTablesCache {
+  std::mutex mu;
+  std::map<std::pair<int, int>, DevLevel> levels;  // (device, nl)
+  std::vector<void*> owned;
+  std::map<int, bool> consts_ready;
+};
+DevTablesCache& cache() {
+  static DevTablesCache c;
+  return c;
+}
+
+#define HIPCHK(expr)                      \
+  do {                                    \
+    hipError_t e_ = (expr);               \
+    if (e_ != hipSuccess) return FCC_ERR_HIP; \
+  } while (0)
+
+template <typename T>
+fcc_status upload(const std::vector<T>& v, const T** out) {
+  void* p = nullptr;
+  size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
+  if (hipMalloc(&p, bytes) != hipSuccess) return FCC_ERR_OOM;
+  if (!v.empty() && hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(p);
+    return FCC_ERR_HIP;
+  }
+  cache().owned.push_back(p);
+  *out = static_cast<const T*>(p);
+  return FCC_OK;
+}
+
+fcc_status ensure_constants(int dev) {
+  auto& C = cache();
+  if (C.consts_ready[dev]) return FCC_OK;
+  const auto& G = weyl_group();
+  std::vector<OrbitTerm> dt;
+  for (int f = 0; f < 8; ++f) {
+    int de[3] = {(f >> 2) & 1, (f >> 1) & 1, f & 1};
+    std::vector<std::array<int, 3>> seen;
+    std::vector<int> mult;
+    for (const auto& g : G) {
+      std::array<int, 3> l;
+      for (int i = 0; i < 3; ++i) l[i] = g[3 * i] * de[0] + g[3 * i + 1] * de[1] + g[3 * i + 2] * de[2];
+      auto it = std::find(seen.begin(), seen.end(), l);
+      if (it == seen.end()) {
+        seen.push_back(l);
+        mult.push_back(1);
+      } else {
+        ++mult[it - seen.begin()];
+      }
+    }
+    for (size_t q = 0; q < seen.size(); ++q) dt.push_back({f, seen[q][0], seen[q][1], seen[q][2], mult[q] / 24.0});
+  }
+  std::vector<CTerm> ct;
+  for (int d = 0; d < 3; ++d) {
+    std::vector<std::array<int, 3>> seen;
+    for (const auto& g : G) {
+      std::array<int, 3> l{g[d], g[3 + d], g[6 + d]};
+      if (std::find(seen.begin(), seen.end(), l) == seen.end()) seen.push_back(l);
+    }
+    for (const auto& l : seen) ct.push_back({d, l[0], l[1], l[2], 1.0 / double(seen.size())});
+  }
+  if ((int)dt.size() != kDct2Terms || (int)ct.size() != kCTerms) return FCC_ERR_UNSUPPORTED;
+  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_dct2), dt.data(), sizeof(OrbitTerm) * dt.size()));
+  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_cterm), ct.data(), sizeof(CTerm) * ct.size()));
+  C.consts_ready[dev] = true;
+  return FCC_OK;
+}
+
+fcc_status device_level(int dev, int nl, DevLevel* out) {
+  auto& C = cache();
+  auto key = std::make_pair(dev, nl);
+  auto it = C.levels.find(key);
+  if (it != C.levels.end()) {
+    *out = it->second;
+    return FCC_OK;
+  }
+  const LevelTables* T = level_tables(nl);
+  if (!T) return FCC_ERR_OOM;
+  if (T->nmono > kMaxMono) return FCC_ERR_UNSUPPORTED;
+  DevLevel lv{};
+  fcc_status s;
+  if ((s = upload(T->b_rowptr, &lv.b_rowptr)) != FCC_OK) return s;
+  if ((s = upload(T->b_src, &lv.b_src)) != FCC_OK) return s;
+  if ((s = upload(T->b_pid, &lv.b_pid)) != FCC_OK) return s;
+  if ((s = upload(T->c_rowptr, &lv.c_rowptr)) != FCC_OK) return s;
+  if ((s = upload(T->c_src, &lv.c_src)) != FCC_OK) return s;
+  if ((s = upload(T->c_pid, &lv.c_pid)) != FCC_OK) return s;
+  if ((s = upload(T->poly, &lv.poly)) != FCC_OK) return s;
+  lv.nmono = T->nmono;
+  for (int q = 0; q < 3 * T->nmono; ++q) lv.mono[q] = T->mono[q];
+  C.levels.emplace(key, lv);
+  *out = lv;
+  return FCC_OK;
+}
+
+bool is_pow2(int n) { return n >= 1 && n <= 1024 && (n & (n - 1)) == 0; }
+
+// Coinciding zeros: theta_j and theta_j' give the same (x,y,z) iff
+// theta_j' = g^T theta_j mod Z^3 for some g in W (T_k(g^T theta) = T_k(theta)).
+// With theta_j = (rst + j)/n this happens for some j != j' iff (g^T - I) rst is
+// integral for some g whose induced map j -> g^T j + (g^T - I) rst (mod n) is
+// not the identity.
+bool singular_skew(int n, const double rst[3]) {
+  if (n == 1) return false;
+  for (const auto& g : weyl_group()) {
+    int gt[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) gt[3 * i + j] = g[3 * j + i];
+    bool ident = true;
+    for (int i = 0; i < 9; ++i) ident &= gt[i] == ((i % 4) == 0 ? 1 : 0);
+    if (ident) continue;
+    double v[3];
+    bool integral = true;
+    for (int i = 0; i < 3; ++i) {
+      v[i] = gt[3 * i] * rst[0] + gt[3 * i + 1] * rst[1] + gt[3 * i + 2] * rst[2] - rst[i];
+      integral &= std::fabs(v[i] - std::nearbyint(v[i])) < 1e-12;
+    }
+    if (!integral) continue;
+    bool identity_mod_n = true;
+    for (int i = 0; i < 3; ++i) {
+      long long vi = (long long)std::nearbyint(v[i]);
+      if (((vi % n) + n) % n != 0) identity_mod_n = false;
+      for (int j = 0; j < 3; ++j) {
+        long long e = gt[3 * i + j] - (i == j ? 1 : 0);
+        if (((e % n) + n) % n != 0) identity_mod_n = false;
+      }
+    }
+    if (!identity_mod_n) return true;
+  }
+  return false;
+}
+
+}  // namespace
+
+struct fcc_plan_s {
+  int n = 0, D = 0, device = 0;
+  double rst[3] = {0.125, 0.0, 0.375};
+  fcc_precision prec = FCC_PREC_FP64;
+  unsigned flags = 0;
+  bool stages64 = true;
+  std::vector<DevLevel> lv;  // per level L: tables of nl = n >> L
+  double2* hph = nullptr;    // phase tables, all levels
+  void* ws[2] = {nullptr, nullptr};
+  size_t ws_bytes = 0;
+};
+
+namespace {
+
+DT in_type(const fcc_plan_s* p) {
+  bool dbl = p->prec == FCC_PREC_FP64;
+  if (p->flags & FCC_REAL_INPUT) return dbl ? DT::F64R : DT::F32R;
+  return dbl ? DT::F64C : DT::F32C;
+}
+DT cplx_type(const fcc_plan_s* p) { return p->prec == FCC_PREC_FP64 ? DT::F64C : DT::F32C; }
+DT stage_type(const fcc_plan_s* p) { return p->stages64 ? DT::F64C : DT::F32C; }
+
+constexpr int kBlock = 256;
+
+dim3 grid_for(int n, int nvol) {
+  long long h = n >> 1;
+  long long cubes = h * h * h;
+  return dim3((unsigned)((cubes + kBlock - 1) / kBlock), (unsigned)nvol, 1);
+}
+
+template <typename R, typename TI, typename TO>
+void launch_fwd(const fcc_plan_s* p, int L, const VolSet& vs, int nvol, hipStream_t st) {
+  hipLaunchKernelGGL((k_fwd_level<R, TI, TO>), grid_for(p->n, nvol), dim3(kBlock), 0, st, vs, p->n, L, p->lv[L],
+                     p->hph + 3 * ((1 << L) - 1));
+}
+
+template <typename R, typename TI>
+void fwd_dispatch_out(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int nvol, hipStream_t st) {
+  switch (to) {
+    case DT::F32C: launch_fwd<R, TI, float2>(p, L, vs, nvol, st); break;
+    case DT::F64C: launch_fwd<R, TI, double2>(p, L, vs, nvol, st); break;
+    default: break;
+  }
+}
+template <typename R>
+void fwd_dispatch(const fcc_plan_s* p, int L, DT ti, DT to, const VolSet& vs, int nvol, hipStream_t st) {
+  switch (ti) {
+    case DT::F32R: fwd_dispatch_out<R, float>(p, L, to, vs, nvol, st); break;
+    case DT::F64R: fwd_dispatch_out<R, double>(p, L, to, vs, nvol, st); break;
+    case DT::F32C: fwd_dispatch_out<R, float2>(p, L, to, vs, nvol, st); break;
+    case DT::F64C: fwd_dispatch_out<R, double2>(p, L, to, vs, nvol, st); break;
+  }
+}
+
+template <typename R>
+void inv_dct2_dispatch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, int nvol, hipStream_t st) {
+  const double2* h = p->hph + 3 * ((1 << L) - 1);
+  if (ti == DT::F32C)
+    hipLaunchKernelGGL((k_inv_dct2<R, float2>), grid_for(p->n, nvol), dim3(kBlock), 0, st, vs, p->n, L, h);
+  else
+    hipLaunchKernelGGL((k_inv_dct2<R, double2>), grid_for(p->n, nvol), dim3(kBlock), 0, st, vs, p->n, L, h);
+}
+template <typename R>
+void inv_basis_dispatch(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int nvol, hipStream_t st) {
+  const double2* h = p->hph + 3 * ((1 << L) - 1);
+  dim3 g = grid_for(p->n, nvol);
+  switch (to) {
+    case DT::F32R: hipLaunchKernelGGL((k_inv_basis<R, float>), g, dim3(kBlock), 0, st, vs, p->n, L, p->lv[L], h); break;
+    case DT::F64R: hipLaunchKernelGGL((k_inv_basis<R, double>), g, dim3(kBlock), 0, st, vs, p->n, L, p->lv[L], h); break;
+    case DT::F32C: hipLaunchKernelGGL((k_inv_basis<R, float2>), g, dim3(kBlock), 0, st, vs, p->n, L, p->lv[L], h); break;
+    case DT::F64C: hipLaunchKernelGGL((k_inv_basis<R, double2>), g, dim3(kBlock), 0, st, vs, p->n, L, p->lv[L], h); break;
+  }
+}
+
+template <typename TI, typename TO>
+void launch_copy1(const VolSet& vs, int nvol, hipStream_t st) {
+  hipLaunchKernelGGL((k_copy1<TI, TO>), dim3(1, nvol), dim3(64), 0, st, vs);
+}
+void copy1_dispatch(DT ti, DT to, const VolSet& vs, int nvol, hipStream_t st) {
+  auto go = [&](auto tag_in) {
+    using TI = decltype(tag_in);
+    switch (to) {
+      case DT::F32R: launch_copy1<TI, float>(vs, nvol, st); break;
+      case DT::F64R: launch_copy1<TI, double>(vs, nvol, st); break;
+      case DT::F32C: launch_copy1<TI, float2>(vs, nvol, st); break;
+      case DT::F64C: launch_copy1<TI, double2>(vs, nvol, st); break;
+    }
+  };
+  switch (ti) {
+    case DT::F32R: go(float{}); break;
+    case DT::F64R: go(double{}); break;
+    case DT::F32C: go(float2{}); break;
+    case DT::F64C: go(double2{}); break;
+  }
+}
+
+// Enqueue the forward transform of nvol volumes that share plan p.
+// ws0/ws1[v]: two scratch arrays of n^3 stage-precision complex per volume.
+fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, const void* const* in, void* const* out,
+                           void* const* ws0, void* const* ws1, hipStream_t st) {
+  VolSet vs;
+  if (p->n == 1) {
+    for (int v = 0; v < nvol; ++v) {
+      vs.in[v] = in[v];
+      vs.out[v] = out[v];
+    }
+    copy1_dispatch(in_type(p), cplx_type(p), vs, nvol, st);
+    return hipGetLastError() == hipSuccess ? FCC_OK : FCC_ERR_HIP;
+  }
+  const void* const* src = in;
+  for (int L = 0; L < p->D; ++L) {
+    bool last = L == p->D - 1;
+    void* const* dst = last ? out : ((L & 1) ? ws1 : ws0);
+    for (int v = 0; v < nvol; ++v) {
+      vs.in[v] = src[v];
+      vs.out[v] = dst[v];
+    }
+    DT ti = L == 0 ? in_type(p) : stage_type(p);
+    DT to = last ? cplx_type(p) : stage_type(p);
+    if (p->stages64)
+      fwd_dispatch<double>(p, L, ti, to, vs, nvol, st);
+    else
+      fwd_dispatch<float>(p, L, ti, to, vs, nvol, st);
+    src = reinterpret_cast<const void* const*>(dst);
+  }
+  return hipGetLastError() == hipSuccess ? FCC_OK : FCC_ERR_HIP;
+}
+
+fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, const void* const* in, void* const* out,
+                           void* const* ws0, void* const* ws1, hipStream_t st) {
+  VolSet vs;
+  DT real_or_cplx = (p->flags & FCC_REAL_INPUT) ? in_type(p) : cplx_type(p);
+  if (p->n == 1) {
+    for (int v = 0; v < nvol; ++v) {
+      vs.in[v] = in[v];
+      vs.out[v] = out[v];
+    }
+    copy1_dispatch(cplx_type(p), real_or_cplx, vs, nvol, st);
+    return hipGetLastError() == hipSuccess ? FCC_OK : FCC_ERR_HIP;
+  }
+  const void* const* cur = in;
+  bool cur_is_user = true;
+  int which = 0;  // scratch array holding the current level's data
+  for (int L = p->D - 1; L >= 0; --L) {
+    void* const* a = which ? ws1 : ws0;
+    void* const* b = which ? ws0 : ws1;
+    for (int v = 0; v < nvol; ++v) {
+      vs.in[v] = cur[v];
+      vs.out[v] = a[v];
+    }
+    DT ti = cur_is_user ? cplx_type(p) : stage_type(p);
+    if (p->stages64)
+      inv_dct2_dispatch<double>(p, L, ti, vs, nvol, st);
+    else
+      inv_dct2_dispatch<float>(p, L, ti, vs, nvol, st);
+    void* const* dst = L == 0 ? out : b;
+    for (int v = 0; v < nvol; ++v) {
+      vs.in[v] = a[v];
+      vs.out[v] = dst[v];
+    }
+    DT to = L == 0 ? real_or_cplx : stage_type(p);
+    if (p->stages64)
+      inv_basis_dispatch<double>(p, L, to, vs, nvol, st);
+    else
+      inv_basis_dispatch<float>(p, L, to, vs, nvol, st);
+    cur = reinterpret_cast<const void* const*>(b);
+    cur_is_user = false;
+    which ^= 1;
+  }
+  return hipGetLastError() == hipSuccess ? FCC_OK : FCC_ERR_HIP;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+const char* fcc_status_string(fcc_status s) {
+  switch (s) {
+    case FCC_OK: return "FCC_OK: success";
+    case FCC_ERR_INVALID_ARG: return "FCC_ERR_INVALID_ARG: null/misaligned pointer or bad argument";
+    case FCC_ERR_NOT_POW2: return "FCC_ERR_NOT_POW2: n must be a power of two in [1, 1024]";
+    case FCC_ERR_SINGULAR_SKEW: return "FCC_ERR_SINGULAR_SKEW: the skew (r,s,t) gives coinciding zeros";
+    case FCC_ERR_OOM: return "FCC_ERR_OOM: allocation failed";
+    case FCC_ERR_HIP: return "FCC_ERR_HIP: HIP runtime error";
+    case FCC_ERR_UNSUPPORTED: return "FCC_ERR_UNSUPPORTED: request not supported by this build";
+  }
+  return "unknown fcc_status";
+}
+
+fcc_status fcc_asp_tables(int nl, fcc_level_tables* out) {
+  if (!out) return FCC_ERR_INVALID_ARG;
+  if (nl < 2 || !is_pow2(nl)) return FCC_ERR_NOT_POW2;
+  const LevelTables* T = level_tables(nl);
+  if (!T) return FCC_ERR_OOM;
+  out->nl = T->nl;
+  out->m = T->m;
+  out->nmono = T->nmono;
+  out->npoly = T->npoly;
+  out->mono = T->mono.data();
+  out->poly = T->poly.data();
+  out->b_rowptr = T->b_rowptr.data();
+  out->b_src = T->b_src.data();
+  out->b_pid = T->b_pid.data();
+  out->c_rowptr = T->c_rowptr.data();
+  out->c_src = T->c_src.data();
+  out->c_pid = T->c_pid.data();
+  return FCC_OK;
+}
+
+fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precision prec, unsigned flags,
+                        void* hip_stream) {
+  if (!plan) return FCC_ERR_INVALID_ARG;
+  *plan = nullptr;
+  if (!is_pow2(n)) return FCC_ERR_NOT_POW2;
+  if (prec < FCC_PREC_FP64 || prec > FCC_PREC_SPLIT_FP16) return FCC_ERR_INVALID_ARG;
+  if ((flags & FCC_STAGES_FP32) && (flags & FCC_STAGES_FP64)) return FCC_ERR_INVALID_ARG;
+  if (flags & ~(unsigned)(FCC_REAL_INPUT | FCC_STAGES_FP32 | FCC_STAGES_FP64)) return FCC_ERR_INVALID_ARG;
+  if (prec == FCC_PREC_SPLIT_BF16 || prec == FCC_PREC_SPLIT_FP16) return FCC_ERR_UNSUPPORTED;
+  double r[3] = {0.125, 0.0, 0.375};
+  if (rst)
+    for (int d = 0; d < 3; ++d) {
+      if (!std::isfinite(rst[d])) return FCC_ERR_INVALID_ARG;
+      r[d] = rst[d];
+    }
+  if (singular_skew(n, r)) return FCC_ERR_SINGULAR_SKEW;
+  fcc_plan_s* p = new (std::nothrow) fcc_plan_s;
+  if (!p) return FCC_ERR_OOM;
+  p->n = n;
+  p->prec = prec;
+  p->flags = flags;
+  for (int d = 0; d < 3; ++d) p->rst[d] = r[d];
+  while ((1 << p->D) < n) ++p->D;
+  // Stage precision.  FP32 stages lose accuracy with depth (the skew children
+  // approach W-fixed points and their coefficient vectors become ill
+  // conditioned); measured FP32-stage errors pass 1e-5 only up to n = 8.
+  if (prec == FCC_PREC_FP64)
+    p->stages64 = true;
+  else if (flags & FCC_STAGES_FP32)
+    p->stages64 = false;
+  else if (flags & FCC_STAGES_FP64)
+    p->stages64 = true;
+  else
+    p->stages64 = n > 8;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  fcc_status s = FCC_OK;
+  {
+    std::lock_guard<std::mutex> lock(cache().mu);
+    if (hipGetDevice(&p->device) != hipSuccess) s = FCC_ERR_HIP;
+    if (s == FCC_OK) s = ensure_constants(p->device);
+    for (int L = 0; s == FCC_OK && L < p->D; ++L) {
+      DevLevel lv;
+      s = device_level(p->device, n >> L, &lv);
+      p->lv.push_back(lv);
+    }
+  }
+  if (s == FCC_OK && p->D > 0) {
+    size_t cnt = 3 * ((size_t(1) << p->D) - 1);
+    if (hipMalloc(&p->hph, cnt * sizeof(double2)) != hipSuccess) s = FCC_ERR_OOM;
+    if (s == FCC_OK) {
+      hipLaunchKernelGGL(k_phase_table, dim3(unsigned((cnt + 255) / 256)), dim3(256), 0, st, p->hph, p->D, r[0], r[1],
+                         r[2]);
+      if (hipGetLastError() != hipSuccess) s = FCC_ERR_HIP;
+    }
+  }
+  if (s == FCC_OK && p->D > 0) {
+    size_t N = size_t(n) * n * n;
+    p->ws_bytes = N * (p->stages64 ? sizeof(double2) : sizeof(float2));
+    for (int b = 0; b < 2 && s == FCC_OK; ++b)
+      if (hipMalloc(&p->ws[b], p->ws_bytes) != hipSuccess) s = FCC_ERR_OOM;
+  }
+  if (s == FCC_OK && hipStreamSynchronize(st) != hipSuccess) s = FCC_ERR_HIP;
+  if (s != FCC_OK) {
+    fcc_dct_destroy(p);
+    return s;
+  }
+  *plan = p;
+  return FCC_OK;
+}
+
+fcc_status fcc_dct_destroy(fcc_plan_t p) {
+  if (!p) return FCC_OK;
+  if (p->hph) (void)hipFree(p->hph);
+  for (void* w : p->ws)
+    if (w) (void)hipFree(w);
+  delete p;
+  return FCC_OK;
+}
+
+fcc_status fcc_dct_forward(fcc_plan_t p, const void* x, void* X, void* hip_stream) {
+  if (!p || !x || !X || !aligned16(x) || !aligned16(X)) return FCC_ERR_INVALID_ARG;
+  if (x == X) return FCC_ERR_UNSUPPORTED;
+  void* w0 = p->ws[0];
+  void* w1 = p->ws[1];
+  return enqueue_forward(p, 1, &x, &X, &w0, &w1, static_cast<hipStream_t>(hip_stream));
+}
+
+fcc_status fcc_dct_inverse(fcc_plan_t p, const void* X, void* x, void* hip_stream) {
+  if (!p || !x || !X || !aligned16(x) || !aligned16(X)) return FCC_ERR_INVALID_ARG;
+  if (x == X) return FCC_ERR_UNSUPPORTED;
+  void* w0 = p->ws[0];
+  void* w1 = p->ws[1];
+  return enqueue_inverse(p, 1, &X, &x, &w0, &w1, static_cast<hipStream_t>(hip_stream));
+}
+
+fcc_status fcc_dct_batched(const fcc_plan_t* plans, int count, const void* const* in, void* const* out,
+                           int direction, void* hip_stream) {
+  if (!plans || !in || !out || count < 1) return FCC_ERR_INVALID_ARG;
+  if (direction < -1 || direction > 1) return FCC_ERR_INVALID_ARG;
+  for (int i = 0; i < count; ++i)
+    if (!plans[i] || !in[i] || !out[i] || !aligned16(in[i]) || !aligned16(out[i]) || in[i] == out[i])
+      return FCC_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (int i = 0; i < count; ++i) {
+    fcc_status s = FCC_OK;
+    if (direction >= 0) s = fcc_dct_forward(plans[i], in[i], out[i], st);
+    if (s == FCC_OK && direction == 0) s = fcc_dct_inverse(plans[i], out[i], const_cast<void*>(in[i]), st);
+    if (s == FCC_OK && direction < 0) s = fcc_dct_inverse(plans[i], in[i], out[i], st);
+    if (s != FCC_OK) return s;
+  }
+  return FCC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// Device code of the radix-2x2x2 FCC cosine transform (Sec. IV-B, eq.
+// FastAlgorithm) for gfx950.
+//
+// Data layout.  One volume is an n^3 array in lexicographic order.  The
+// transform runs in place level by level on this index space: at level L a
+// node J in [0,2^L)^3 owns the strided sub-lattice J + 2^L * a, a in [0, nl)^3,
+// nl = n >> L, holding its coefficient vector in the basis b_nl.  The node's
+// children are its 2x2x2 cosets: child i owns J + 2^L i + 2^(L+1) k, and its
+// skew parameter is ((r,s,t) + J + 2^L i) / 2^(L+1) (eq. BaseCaseA3AlgebraLevel).
+// After the last level every node is a single point and position j holds the
+// value at the zero theta_j, so the permutation P_n of eq. PermutationStep...
+// costs nothing.
+//
+// One thread owns one 2x2x2 cube of one node: (J, abc), abc in [0, nl/2)^3.
+//   forward : y(def) = row (def,abc) of B_nl(c) applied to the node (gather),
+//             z = DCT_2(phi) y, stored at the cube's 8 positions;
+//   inverse : y = DCT_2(phi)^{-1} z on the cube, then a second pass gathers
+//             x(kappa) = row kappa of C_nl(c) applied to y.
+// DCT_2(phi)[i, def] = T_def((phi + i)/2) = (H_8 A(phi))[i, def], with
+// H_8[i, mu] = (-1)^(i.mu) and A(phi)[mu, def] = (1/24) sum_{g: g def = mu mod 2}
+// exp(i pi (g def).phi).  A is block diagonal over the classes of {0,1}^3 mod W:
+// {000}, {001,011,100,110}, {010,101,111}.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fcc {
+
+template <typename R>
+struct cx {
+  R x, y;
+};
+template <typename R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {s * a.x, s * a.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> conj(cx<R> a) { return {a.x, -a.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> cdiv(cx<R> a, cx<R> b) {
+  R d = b.x * b.x + b.y * b.y;
+  return {(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
+}
+template <typename R>
+__device__ __forceinline__ R cabs2(cx<R> a) { return a.x * a.x + a.y * a.y; }
+
+// ---- element access (real or interleaved complex, float or double) ----------
+template <typename T, typename R>
+struct IO;
+template <typename R>
+struct IO<float, R> {
+  static __device__ __forceinline__ cx<R> ld(const float* p, long long i) { return {R(p[i]), R(0)}; }
+  static __device__ __forceinline__ void st(float* p, long long i, cx<R> v) { p[i] = float(v.x); }
+};
+template <typename R>
+struct IO<double, R> {
+  static __device__ __forceinline__ cx<R> ld(const double* p, long long i) { return {R(p[i]), R(0)}; }
+  static __device__ __forceinline__ void st(double* p, long long i, cx<R> v) { p[i] = double(v.x); }
+};
+template <typename R>
+struct IO<float2, R> {
+  static __device__ __forceinline__ cx<R> ld(const float2* p, long long i) {
+    float2 v = p[i];
+    return {R(v.x), R(v.y)};
+  }
+  static __device__ __forceinline__ void st(float2* p, long long i, cx<R> v) { p[i] = make_float2(float(v.x), float(v.y)); }
+};
+template <typename R>
+struct IO<double2, R> {
+  static __device__ __forceinline__ cx<R> ld(const double2* p, long long i) {
+    double2 v = p[i];
+    return {R(v.x), R(v.y)};
+  }
+  static __device__ __forceinline__ void st(double2* p, long long i, cx<R> v) { p[i] = make_double2(double(v.x), double(v.y)); }
+};
+
+// ---- constant tables: W-orbits used by DCT_2 and by c = (sigma,tau,rho) -----
+struct OrbitTerm {
+  int f;         // def index (d0*4 + d1*2 + d2)
+  int l0, l1, l2;  // lambda = g def
+  double w;      // multiplicity / 24
+};
+struct CTerm {
+  int d;         // 0,1,2 for x,y,z
+  int l0, l1, l2;  // lambda in W e_d
+  double w;      // 1 / |W e_d|
+};
+constexpr int kDct2Terms = 75;
+constexpr int kCTerms = 14;
+constexpr int kMaxMono = 8;
+
+// Device view of the basis-change tables of one node size.
+struct DevLevel {
+  const int* b_rowptr;
+  const uint32_t* b_src;
+  const uint16_t* b_pid;
+  const int* c_rowptr;
+  const uint32_t* c_src;
+  const uint16_t* c_pid;
+  const double* poly;  // npoly * nmono
+  int nmono;
+  int mono[3 * kMaxMono];
+};
+
+constexpr int kMaxVol = 120;
+// Pointers of up to kMaxVol volumes that share one launch (passed by value).
+struct VolSet {
+  const void* in[kMaxVol];
+  void* out[kMaxVol];
+};
+
+}  // namespace fcc
