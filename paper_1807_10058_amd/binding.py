@@ -13,6 +13,10 @@ FCC_OK = 0
 FCC_PREC_FP64, FCC_PREC_FP32, FCC_PREC_SPLIT_BF16, FCC_PREC_SPLIT_FP16 = 0, 1, 2, 3
 FCC_REAL_INPUT, FCC_STAGES_FP32, FCC_STAGES_FP64 = 1, 2, 4
 
+# torch is loaded first so that libfccdct.so binds to the HIP runtime torch
+# already carries (same soname): one HIP/HSA runtime per process.
+import torch  # noqa: E402,F401
+
 if not os.path.exists(_LIB_PATH):
     raise ImportError("libfccdct.so is not built: run `python -m paper_1807_10058_amd.build` "
                       "(or __graft_entry__.build())")

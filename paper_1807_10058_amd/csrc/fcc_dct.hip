@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -370,20 +371,40 @@ DevTablesCache& cache() {
   return c;
 }
 
-#define HIPCHK(expr)                      \
-  do {                                    \
-    hipError_t e_ = (expr);               \
-    if (e_ != hipSuccess) return FCC_ERR_HIP; \
+// Set FCC_VERBOSE=1 to print the HIP call that failed to stderr.
+bool verbose() {
+  static const bool v = [] {
+    const char* e = std::getenv("FCC_VERBOSE");
+    return e && *e && *e != '0';
+  }();
+  return v;
+}
+fcc_status hip_fail(hipError_t e, const char* what, int line) {
+  if (verbose()) std::fprintf(stderr, "fcc_dct: %s failed at line %d: %s\n", what, line, hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? FCC_ERR_OOM : FCC_ERR_HIP;
+}
+#define HIPCHK(expr)                                              \
+  do {                                                            \
+    hipError_t e_ = (expr);                                       \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr, __LINE__);   \
   } while (0)
+// Status of the launches just enqueued (stale errors are cleared on entry).
+fcc_status launch_status(const char* what) {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? FCC_OK : hip_fail(e, what, 0);
+}
 
 template <typename T>
 fcc_status upload(const std::vector<T>& v, const T** out) {
   void* p = nullptr;
   size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
-  if (hipMalloc(&p, bytes) != hipSuccess) return FCC_ERR_OOM;
-  if (!v.empty() && hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipFree(p);
-    return FCC_ERR_HIP;
+  HIPCHK(hipMalloc(&p, bytes));
+  if (!v.empty()) {
+    hipError_t e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(p);
+      return hip_fail(e, "hipMemcpy(tables)", __LINE__);
+    }
   }
   cache().owned.push_back(p);
   *out = static_cast<const T*>(p);
@@ -601,7 +622,7 @@ fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, const void* const* in,
       vs.out[v] = out[v];
     }
     copy1_dispatch(in_type(p), cplx_type(p), vs, nvol, st);
-    return hipGetLastError() == hipSuccess ? FCC_OK : FCC_ERR_HIP;
+    return launch_status("forward n=1 launch");
   }
   const void* const* src = in;
   for (int L = 0; L < p->D; ++L) {
@@ -619,7 +640,7 @@ fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, const void* const* in,
       fwd_dispatch<float>(p, L, ti, to, vs, nvol, st);
     src = reinterpret_cast<const void* const*>(dst);
   }
-  return hipGetLastError() == hipSuccess ? FCC_OK : FCC_ERR_HIP;
+  return launch_status("forward level launch");
 }
 
 fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, const void* const* in, void* const* out,
@@ -632,7 +653,7 @@ fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, const void* const* in,
       vs.out[v] = out[v];
     }
     copy1_dispatch(cplx_type(p), real_or_cplx, vs, nvol, st);
-    return hipGetLastError() == hipSuccess ? FCC_OK : FCC_ERR_HIP;
+    return launch_status("inverse n=1 launch");
   }
   const void* const* cur = in;
   bool cur_is_user = true;
@@ -663,7 +684,7 @@ fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, const void* const* in,
     cur_is_user = false;
     which ^= 1;
   }
-  return hipGetLastError() == hipSuccess ? FCC_OK : FCC_ERR_HIP;
+  return launch_status("inverse level launch");
 }
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
@@ -741,9 +762,11 @@ fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precis
     p->stages64 = n > 8;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   fcc_status s = FCC_OK;
+  (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
   {
     std::lock_guard<std::mutex> lock(cache().mu);
-    if (hipGetDevice(&p->device) != hipSuccess) s = FCC_ERR_HIP;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) s = hip_fail(e, "hipGetDevice", __LINE__);
     if (s == FCC_OK) s = ensure_constants(p->device);
     for (int L = 0; s == FCC_OK && L < p->D; ++L) {
       DevLevel lv;
@@ -753,20 +776,26 @@ fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precis
   }
   if (s == FCC_OK && p->D > 0) {
     size_t cnt = 3 * ((size_t(1) << p->D) - 1);
-    if (hipMalloc(&p->hph, cnt * sizeof(double2)) != hipSuccess) s = FCC_ERR_OOM;
+    hipError_t e = hipMalloc(&p->hph, cnt * sizeof(double2));
+    if (e != hipSuccess) s = hip_fail(e, "hipMalloc(phase table)", __LINE__);
     if (s == FCC_OK) {
       hipLaunchKernelGGL(k_phase_table, dim3(unsigned((cnt + 255) / 256)), dim3(256), 0, st, p->hph, p->D, r[0], r[1],
                          r[2]);
-      if (hipGetLastError() != hipSuccess) s = FCC_ERR_HIP;
+      s = launch_status("phase table launch");
     }
   }
   if (s == FCC_OK && p->D > 0) {
     size_t N = size_t(n) * n * n;
     p->ws_bytes = N * (p->stages64 ? sizeof(double2) : sizeof(float2));
-    for (int b = 0; b < 2 && s == FCC_OK; ++b)
-      if (hipMalloc(&p->ws[b], p->ws_bytes) != hipSuccess) s = FCC_ERR_OOM;
+    for (int b = 0; b < 2 && s == FCC_OK; ++b) {
+      hipError_t e = hipMalloc(&p->ws[b], p->ws_bytes);
+      if (e != hipSuccess) s = hip_fail(e, "hipMalloc(scratch)", __LINE__);
+    }
   }
-  if (s == FCC_OK && hipStreamSynchronize(st) != hipSuccess) s = FCC_ERR_HIP;
+  if (s == FCC_OK) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) s = hip_fail(e, "hipStreamSynchronize", __LINE__);
+  }
   if (s != FCC_OK) {
     fcc_dct_destroy(p);
     return s;
@@ -787,6 +816,7 @@ fcc_status fcc_dct_destroy(fcc_plan_t p) {
 fcc_status fcc_dct_forward(fcc_plan_t p, const void* x, void* X, void* hip_stream) {
   if (!p || !x || !X || !aligned16(x) || !aligned16(X)) return FCC_ERR_INVALID_ARG;
   if (x == X) return FCC_ERR_UNSUPPORTED;
+  (void)hipGetLastError();
   void* w0 = p->ws[0];
   void* w1 = p->ws[1];
   return enqueue_forward(p, 1, &x, &X, &w0, &w1, static_cast<hipStream_t>(hip_stream));
@@ -795,6 +825,7 @@ fcc_status fcc_dct_forward(fcc_plan_t p, const void* x, void* X, void* hip_strea
 fcc_status fcc_dct_inverse(fcc_plan_t p, const void* X, void* x, void* hip_stream) {
   if (!p || !x || !X || !aligned16(x) || !aligned16(X)) return FCC_ERR_INVALID_ARG;
   if (x == X) return FCC_ERR_UNSUPPORTED;
+  (void)hipGetLastError();
   void* w0 = p->ws[0];
   void* w1 = p->ws[1];
   return enqueue_inverse(p, 1, &X, &x, &w0, &w1, static_cast<hipStream_t>(hip_stream));
