@@ -114,6 +114,20 @@ fcc_status fcc_dct_destroy(fcc_plan_t plan);
 /* Static description of a status code. */
 const char* fcc_status_string(fcc_status s);
 
+/* ---- measurement ------------------------------------------------------- */
+
+/* Per-launch timing of one direction of the fast path: enqueues `reps`
+ * transforms of `in` into `out` (direction +1 forward, -1 inverse) on
+ * `hip_stream` with HIP events recorded around every kernel launch, waits for
+ * them, and writes the average duration in ms of each launch slot to ms[k].
+ * Slots in launch order: forward = level 0..D-1; inverse = (DCT_2^{-1} pass,
+ * C pass) for level D-1 down to 0; n = 1 has one slot.  *count receives the
+ * number of slots; with ms == NULL only *count is set.
+ * Errors: FCC_ERR_INVALID_ARG (cap too small, bad pointers or direction),
+ * FCC_ERR_HIP. */
+fcc_status fcc_dct_time_launches(fcc_plan_t plan, const void* in, void* out, int direction, int reps,
+                                 float* ms, int cap, int* count, void* hip_stream);
+
 /* ---- introspection (host logic; no GPU needed) ------------------------- */
 
 /* Host view of the basis-change tables for one node size nl = 2m (2 <= nl <= 1024).

@@ -40,11 +40,13 @@ _lib.fcc_dct_inverse.argtypes = [_vp, _vp, _vp, _vp]
 _lib.fcc_dct_batched.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                  ctypes.c_int, _vp]
 _lib.fcc_dct_destroy.argtypes = [_vp]
+_lib.fcc_dct_time_launches.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float),
+                                       ctypes.c_int, ctypes.POINTER(ctypes.c_int), _vp]
 _lib.fcc_status_string.argtypes = [ctypes.c_int]
 _lib.fcc_status_string.restype = ctypes.c_char_p
 _lib.fcc_asp_tables.argtypes = [ctypes.c_int, ctypes.POINTER(_LevelTables)]
 for _f in ("fcc_dct_plan", "fcc_dct_forward", "fcc_dct_inverse", "fcc_dct_batched", "fcc_dct_destroy",
-           "fcc_asp_tables"):
+           "fcc_asp_tables", "fcc_dct_time_launches"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -129,6 +131,17 @@ def fcc_dct_batched(plans, ins, outs, direction, stream=None):
     I = (_vp * cnt)(*[_ptr(t) for t in ins])
     O = (_vp * cnt)(*[_ptr(t) for t in outs])
     _check(_lib.fcc_dct_batched(P, cnt, I, O, int(direction), _stream(stream)), "fcc_dct_batched")
+
+
+def fcc_dct_time_launches(plan, x, out, direction, reps=10, stream=None):
+    """Average duration (ms) of each kernel launch of one transform, in launch order."""
+    cnt = ctypes.c_int(0)
+    _check(_lib.fcc_dct_time_launches(plan.handle, _ptr(x), _ptr(out), int(direction), 1, None, 0,
+                                      ctypes.byref(cnt), _stream(stream)), "fcc_dct_time_launches")
+    ms = (ctypes.c_float * cnt.value)()
+    _check(_lib.fcc_dct_time_launches(plan.handle, _ptr(x), _ptr(out), int(direction), int(reps), ms, cnt.value,
+                                      ctypes.byref(cnt), _stream(stream)), "fcc_dct_time_launches")
+    return [float(v) for v in ms]
 
 
 def fcc_dct_destroy(plan):

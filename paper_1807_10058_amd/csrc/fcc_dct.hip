@@ -17,11 +17,10 @@
 #include "asp_tables.hpp"
 #include "fcc_dct.h"
 #include "kernels.hpp"
+#include "orbits.inc"
 
 namespace fcc {
 
-__constant__ OrbitTerm c_dct2[kDct2Terms];
-__constant__ CTerm c_cterm[kCTerms];
 
 // ---------------------------------------------------------------------------
 // Per-node constants
@@ -53,32 +52,29 @@ __device__ __forceinline__ cx<R> phase(const cx<R> P[3][7], int l0, int l1, int 
   return P[0][l0 + 3] * P[1][l1 + 3] * P[2][l2 + 3];
 }
 
-// c = (sigma, tau, rho)(phi) = (T_100, T_010, T_001)(phi) and the monomials
-// c1^e1 c2^e2 c3^e3 used by the level's coefficient polynomials.
+// c = (sigma, tau, rho)(phi) = (T_100, T_010, T_001)(phi) and the five
+// monomials of the coefficient polynomials, in the fixed order
+// {1, c3, c1, c2, c1 c3} (the only ones the derivation produces).
 template <typename R>
-__device__ __forceinline__ void node_monomials(const cx<R> P[3][7], const DevLevel& lv, cx<R>* mono) {
+__device__ __forceinline__ void node_monomials(const cx<R> P[3][7], cx<R> mono[kNumMono]) {
   cx<R> c[3] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
-#pragma unroll
-  for (int t = 0; t < kCTerms; ++t) {
-    const CTerm& ct = c_cterm[t];
-    cx<R> p = phase(P, 2 * ct.l0, 2 * ct.l1, 2 * ct.l2);
-    c[ct.d] = c[ct.d] + R(ct.w) * p;
-  }
-  for (int q = 0; q < lv.nmono; ++q) {
-    cx<R> v{R(1), R(0)};
-    for (int d = 0; d < 3; ++d)
-      for (int e = 0; e < lv.mono[3 * q + d]; ++e) v = v * c[d];
-    mono[q] = v;
-  }
+#define FCC_ADD_C(d, l0, l1, l2, w) c[d] = c[d] + R(w) * phase(P, 2 * (l0), 2 * (l1), 2 * (l2));
+  FCC_C_TERMS(FCC_ADD_C)
+#undef FCC_ADD_C
+  mono[0] = {R(1), R(0)};
+  mono[1] = c[2];
+  mono[2] = c[0];
+  mono[3] = c[1];
+  mono[4] = c[0] * c[2];
 }
 
 // Index of mu / def inside its block of A (class 1: {1,3,4,6}, class 2: {2,5,7}).
-__device__ __forceinline__ int blk_pos(int f) {
+__host__ __device__ constexpr int blk_pos(int f) {
   // f: 0 1 2 3 4 5 6 7
   // ->  0 0 0 1 2 1 3 2
   return (0x23121000 >> (4 * f)) & 0xF;
 }
-__device__ __forceinline__ int blk_class(int f) {
+__host__ __device__ constexpr int blk_class(int f) {
   // f: 0 1 2 3 4 5 6 7 -> 0 1 2 1 1 2 1 2
   return (0x21211210 >> (4 * f)) & 0xF;
 }
@@ -94,17 +90,17 @@ __device__ __forceinline__ void build_A(const cx<R> P[3][7], cx<R> a4[4][4], cx<
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) a3[i][j] = {R(0), R(0)};
-#pragma unroll
-  for (int t = 0; t < kDct2Terms; ++t) {
-    const OrbitTerm& ot = c_dct2[t];
-    if (ot.f == 0) continue;
-    int mu = ((ot.l0 & 1) << 2) | ((ot.l1 & 1) << 1) | (ot.l2 & 1);
-    cx<R> v = R(ot.w) * phase(P, ot.l0, ot.l1, ot.l2);
-    if (blk_class(ot.f) == 1)
-      a4[blk_pos(mu)][blk_pos(ot.f)] = a4[blk_pos(mu)][blk_pos(ot.f)] + v;
-    else
-      a3[blk_pos(mu)][blk_pos(ot.f)] = a3[blk_pos(mu)][blk_pos(ot.f)] + v;
+#define FCC_ADD_A(f, l0, l1, l2, w)                                                   \
+  if ((f) != 0) {                                                                     \
+    constexpr int mu_ = (((l0) & 1) << 2) | (((l1) & 1) << 1) | ((l2) & 1);           \
+    const cx<R> v_ = R(w) * phase(P, (l0), (l1), (l2));                               \
+    if (blk_class(f) == 1)                                                            \
+      a4[blk_pos(mu_)][blk_pos(f)] = a4[blk_pos(mu_)][blk_pos(f)] + v_;               \
+    else                                                                              \
+      a3[blk_pos(mu_)][blk_pos(f)] = a3[blk_pos(mu_)][blk_pos(f)] + v_;               \
   }
+  FCC_DCT2_TERMS(FCC_ADD_A)
+#undef FCC_ADD_A
 }
 
 // In-place 8-point Walsh-Hadamard transform: z[i] = sum_mu (-1)^(i.mu) t[mu].
@@ -186,11 +182,15 @@ __device__ __forceinline__ long long gpos(int n, int L, const int J[3], int kx, 
   return ((long long)(J[0] + (kx << L)) * n + (J[1] + (ky << L))) * n + (J[2] + (kz << L));
 }
 
+// Coefficient of one table entry: polynomials are sorted so that ids below
+// lv.nconst are constants (86% of all entries), read with one load.
 template <typename R>
-__device__ __forceinline__ cx<R> poly_value(const DevLevel& lv, int pid, const cx<R>* mono) {
-  const double* pc = lv.poly + (long long)pid * lv.nmono;
-  cx<R> v{R(0), R(0)};
-  for (int q = 0; q < lv.nmono; ++q) v = v + R(pc[q]) * mono[q];
+__device__ __forceinline__ cx<R> poly_value(const DevLevel& lv, int pid, const cx<R> mono[kNumMono]) {
+  const double* pc = lv.poly + pid * kNumMono;
+  if (pid < lv.nconst) return {R(pc[0]), R(0)};
+  cx<R> v = R(pc[0]) * mono[0];
+#pragma unroll
+  for (int q = 1; q < kNumMono; ++q) v = v + R(pc[q]) * mono[q];
   return v;
 }
 
@@ -211,8 +211,8 @@ __global__ __launch_bounds__(256) void k_fwd_level(VolSet vs, int n, int L, DevL
   const int m = (n >> L) >> 1;
   cx<R> P[3][7];
   node_powers(hph, L, ci.J, P);
-  cx<R> mono[kMaxMono];
-  node_monomials(P, lv, mono);
+  cx<R> mono[kNumMono];
+  node_monomials(P, mono);
 
   cx<R> y[8];
   const int cube = (ci.a[0] * m + ci.a[1]) * m + ci.a[2];
@@ -307,8 +307,8 @@ __global__ __launch_bounds__(256) void k_inv_basis(VolSet vs, int n, int L, DevL
   const int m = (n >> L) >> 1;
   cx<R> P[3][7];
   node_powers(hph, L, ci.J, P);
-  cx<R> mono[kMaxMono];
-  node_monomials(P, lv, mono);
+  cx<R> mono[kNumMono];
+  node_monomials(P, mono);
   const int cube = (ci.a[0] * m + ci.a[1]) * m + ci.a[2];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
@@ -364,7 +364,6 @@ struct DevTablesCache {
   std::mutex mu;
   std::map<std::pair<int, int>, DevLevel> levels;  // (device, nl)
   std::vector<void*> owned;
-  std::map<int, bool> consts_ready;
 };
 DevTablesCache& cache() {
   static DevTablesCache c;
@@ -411,44 +410,6 @@ fcc_status upload(const std::vector<T>& v, const T** out) {
   return FCC_OK;
 }
 
-fcc_status ensure_constants(int dev) {
-  auto& C = cache();
-  if (C.consts_ready[dev]) return FCC_OK;
-  const auto& G = weyl_group();
-  std::vector<OrbitTerm> dt;
-  for (int f = 0; f < 8; ++f) {
-    int de[3] = {(f >> 2) & 1, (f >> 1) & 1, f & 1};
-    std::vector<std::array<int, 3>> seen;
-    std::vector<int> mult;
-    for (const auto& g : G) {
-      std::array<int, 3> l;
-      for (int i = 0; i < 3; ++i) l[i] = g[3 * i] * de[0] + g[3 * i + 1] * de[1] + g[3 * i + 2] * de[2];
-      auto it = std::find(seen.begin(), seen.end(), l);
-      if (it == seen.end()) {
-        seen.push_back(l);
-        mult.push_back(1);
-      } else {
-        ++mult[it - seen.begin()];
-      }
-    }
-    for (size_t q = 0; q < seen.size(); ++q) dt.push_back({f, seen[q][0], seen[q][1], seen[q][2], mult[q] / 24.0});
-  }
-  std::vector<CTerm> ct;
-  for (int d = 0; d < 3; ++d) {
-    std::vector<std::array<int, 3>> seen;
-    for (const auto& g : G) {
-      std::array<int, 3> l{g[d], g[3 + d], g[6 + d]};
-      if (std::find(seen.begin(), seen.end(), l) == seen.end()) seen.push_back(l);
-    }
-    for (const auto& l : seen) ct.push_back({d, l[0], l[1], l[2], 1.0 / double(seen.size())});
-  }
-  if ((int)dt.size() != kDct2Terms || (int)ct.size() != kCTerms) return FCC_ERR_UNSUPPORTED;
-  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_dct2), dt.data(), sizeof(OrbitTerm) * dt.size()));
-  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_cterm), ct.data(), sizeof(CTerm) * ct.size()));
-  C.consts_ready[dev] = true;
-  return FCC_OK;
-}
-
 fcc_status device_level(int dev, int nl, DevLevel* out) {
   auto& C = cache();
   auto key = std::make_pair(dev, nl);
@@ -459,18 +420,50 @@ fcc_status device_level(int dev, int nl, DevLevel* out) {
   }
   const LevelTables* T = level_tables(nl);
   if (!T) return FCC_ERR_OOM;
-  if (T->nmono > kMaxMono) return FCC_ERR_UNSUPPORTED;
+  // Remap the coefficient polynomials to the fixed monomial order
+  // {1, c3, c1, c2, c1 c3} and sort them so that constants come first.
+  auto slot_of = [](int e1, int e2, int e3) {
+    if (e1 == 0 && e2 == 0 && e3 == 0) return 0;
+    if (e1 == 0 && e2 == 0 && e3 == 1) return 1;
+    if (e1 == 1 && e2 == 0 && e3 == 0) return 2;
+    if (e1 == 0 && e2 == 1 && e3 == 0) return 3;
+    if (e1 == 1 && e2 == 0 && e3 == 1) return 4;
+    return -1;
+  };
+  std::vector<double> fixed(size_t(T->npoly) * kNumMono, 0.0);
+  for (int q = 0; q < T->nmono; ++q) {
+    int sl = slot_of(T->mono[3 * q], T->mono[3 * q + 1], T->mono[3 * q + 2]);
+    if (sl < 0) return FCC_ERR_UNSUPPORTED;
+    for (int p = 0; p < T->npoly; ++p) fixed[size_t(p) * kNumMono + sl] = T->poly[size_t(p) * T->nmono + q];
+  }
+  std::vector<int> order(T->npoly), newid(T->npoly);
+  for (int p = 0; p < T->npoly; ++p) order[p] = p;
+  auto is_const = [&](int p) {
+    for (int q = 1; q < kNumMono; ++q)
+      if (fixed[size_t(p) * kNumMono + q] != 0.0) return false;
+    return true;
+  };
+  std::stable_partition(order.begin(), order.end(), is_const);
+  int nconst = 0;
+  for (int p = 0; p < T->npoly; ++p) nconst += is_const(p) ? 1 : 0;
+  std::vector<double> poly(fixed.size());
+  for (int i = 0; i < T->npoly; ++i) {
+    newid[order[i]] = i;
+    for (int q = 0; q < kNumMono; ++q) poly[size_t(i) * kNumMono + q] = fixed[size_t(order[i]) * kNumMono + q];
+  }
+  std::vector<uint16_t> bp(T->b_pid.size()), cp(T->c_pid.size());
+  for (size_t e = 0; e < bp.size(); ++e) bp[e] = (uint16_t)newid[T->b_pid[e]];
+  for (size_t e = 0; e < cp.size(); ++e) cp[e] = (uint16_t)newid[T->c_pid[e]];
   DevLevel lv{};
   fcc_status s;
   if ((s = upload(T->b_rowptr, &lv.b_rowptr)) != FCC_OK) return s;
   if ((s = upload(T->b_src, &lv.b_src)) != FCC_OK) return s;
-  if ((s = upload(T->b_pid, &lv.b_pid)) != FCC_OK) return s;
+  if ((s = upload(bp, &lv.b_pid)) != FCC_OK) return s;
   if ((s = upload(T->c_rowptr, &lv.c_rowptr)) != FCC_OK) return s;
   if ((s = upload(T->c_src, &lv.c_src)) != FCC_OK) return s;
-  if ((s = upload(T->c_pid, &lv.c_pid)) != FCC_OK) return s;
-  if ((s = upload(T->poly, &lv.poly)) != FCC_OK) return s;
-  lv.nmono = T->nmono;
-  for (int q = 0; q < 3 * T->nmono; ++q) lv.mono[q] = T->mono[q];
+  if ((s = upload(cp, &lv.c_pid)) != FCC_OK) return s;
+  if ((s = upload(poly, &lv.poly)) != FCC_OK) return s;
+  lv.nconst = nconst;
   C.levels.emplace(key, lv);
   *out = lv;
   return FCC_OK;
@@ -611,11 +604,22 @@ void copy1_dispatch(DT ti, DT to, const VolSet& vs, int nvol, hipStream_t st) {
   }
 }
 
+// Optional per-launch timing: an event is recorded before the first launch and
+// after every launch, so slot k's duration is ev[k+1] - ev[k].
+struct LaunchTimer {
+  std::vector<hipEvent_t>* ev = nullptr;
+  size_t next = 0;
+  void mark(hipStream_t st) {
+    if (ev && next < ev->size()) (void)hipEventRecord((*ev)[next++], st);
+  }
+};
+
 // Enqueue the forward transform of nvol volumes that share plan p.
 // ws0/ws1[v]: two scratch arrays of n^3 stage-precision complex per volume.
 fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, const void* const* in, void* const* out,
-                           void* const* ws0, void* const* ws1, hipStream_t st) {
+                           void* const* ws0, void* const* ws1, hipStream_t st, LaunchTimer* tm = nullptr) {
   VolSet vs;
+  if (tm) tm->mark(st);
   if (p->n == 1) {
     for (int v = 0; v < nvol; ++v) {
       vs.in[v] = in[v];
@@ -638,14 +642,16 @@ fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, const void* const* in,
       fwd_dispatch<double>(p, L, ti, to, vs, nvol, st);
     else
       fwd_dispatch<float>(p, L, ti, to, vs, nvol, st);
+    if (tm) tm->mark(st);
     src = reinterpret_cast<const void* const*>(dst);
   }
   return launch_status("forward level launch");
 }
 
 fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, const void* const* in, void* const* out,
-                           void* const* ws0, void* const* ws1, hipStream_t st) {
+                           void* const* ws0, void* const* ws1, hipStream_t st, LaunchTimer* tm = nullptr) {
   VolSet vs;
+  if (tm) tm->mark(st);
   DT real_or_cplx = (p->flags & FCC_REAL_INPUT) ? in_type(p) : cplx_type(p);
   if (p->n == 1) {
     for (int v = 0; v < nvol; ++v) {
@@ -670,6 +676,7 @@ fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, const void* const* in,
       inv_dct2_dispatch<double>(p, L, ti, vs, nvol, st);
     else
       inv_dct2_dispatch<float>(p, L, ti, vs, nvol, st);
+    if (tm) tm->mark(st);
     void* const* dst = L == 0 ? out : b;
     for (int v = 0; v < nvol; ++v) {
       vs.in[v] = a[v];
@@ -680,6 +687,7 @@ fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, const void* const* in,
       inv_basis_dispatch<double>(p, L, to, vs, nvol, st);
     else
       inv_basis_dispatch<float>(p, L, to, vs, nvol, st);
+    if (tm) tm->mark(st);
     cur = reinterpret_cast<const void* const*>(b);
     cur_is_user = false;
     which ^= 1;
@@ -767,7 +775,6 @@ fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precis
     std::lock_guard<std::mutex> lock(cache().mu);
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) s = hip_fail(e, "hipGetDevice", __LINE__);
-    if (s == FCC_OK) s = ensure_constants(p->device);
     for (int L = 0; s == FCC_OK && L < p->D; ++L) {
       DevLevel lv;
       s = device_level(p->device, n >> L, &lv);
@@ -829,6 +836,53 @@ fcc_status fcc_dct_inverse(fcc_plan_t p, const void* X, void* x, void* hip_strea
   void* w0 = p->ws[0];
   void* w1 = p->ws[1];
   return enqueue_inverse(p, 1, &X, &x, &w0, &w1, static_cast<hipStream_t>(hip_stream));
+}
+
+fcc_status fcc_dct_time_launches(fcc_plan_t p, const void* in, void* out, int direction, int reps, float* ms,
+                                 int cap, int* count, void* hip_stream) {
+  if (!p || !in || !out || !count || reps < 1 || (direction != 1 && direction != -1)) return FCC_ERR_INVALID_ARG;
+  if (!aligned16(in) || !aligned16(out) || in == out) return FCC_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int slots = p->n == 1 ? 1 : (direction > 0 ? p->D : 2 * p->D);
+  *count = slots;
+  if (!ms || cap < slots) return ms ? FCC_ERR_INVALID_ARG : FCC_OK;
+  (void)hipGetLastError();
+  std::vector<hipEvent_t> ev(size_t(slots + 1) * reps, nullptr);
+  fcc_status s = FCC_OK;
+  for (auto& e : ev) {
+    hipError_t he = hipEventCreate(&e);
+    if (he != hipSuccess) {
+      s = hip_fail(he, "hipEventCreate", __LINE__);
+      break;
+    }
+  }
+  void* w0 = p->ws[0];
+  void* w1 = p->ws[1];
+  for (int r = 0; r < reps && s == FCC_OK; ++r) {
+    std::vector<hipEvent_t> sub(ev.begin() + size_t(r) * (slots + 1), ev.begin() + size_t(r + 1) * (slots + 1));
+    LaunchTimer tm;
+    tm.ev = &sub;
+    s = direction > 0 ? enqueue_forward(p, 1, &in, &out, &w0, &w1, st, &tm)
+                      : enqueue_inverse(p, 1, &in, &out, &w0, &w1, st, &tm);
+    if (p->n == 1 && s == FCC_OK) (void)hipEventRecord(sub[1], st);
+  }
+  if (s == FCC_OK) {
+    hipError_t he = hipStreamSynchronize(st);
+    if (he != hipSuccess) s = hip_fail(he, "hipStreamSynchronize", __LINE__);
+  }
+  if (s == FCC_OK)
+    for (int k = 0; k < slots; ++k) {
+      double acc = 0.0;
+      for (int r = 0; r < reps; ++r) {
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, ev[size_t(r) * (slots + 1) + k], ev[size_t(r) * (slots + 1) + k + 1]);
+        acc += t;
+      }
+      ms[k] = float(acc / reps);
+    }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return s;
 }
 
 fcc_status fcc_dct_batched(const fcc_plan_t* plans, int count, const void* const* in, void* const* out,

@@ -81,20 +81,9 @@ struct IO<double2, R> {
   static __device__ __forceinline__ void st(double2* p, long long i, cx<R> v) { p[i] = make_double2(double(v.x), double(v.y)); }
 };
 
-// ---- constant tables: W-orbits used by DCT_2 and by c = (sigma,tau,rho) -----
-struct OrbitTerm {
-  int f;         // def index (d0*4 + d1*2 + d2)
-  int l0, l1, l2;  // lambda = g def
-  double w;      // multiplicity / 24
-};
-struct CTerm {
-  int d;         // 0,1,2 for x,y,z
-  int l0, l1, l2;  // lambda in W e_d
-  double w;      // 1 / |W e_d|
-};
-constexpr int kDct2Terms = 75;
-constexpr int kCTerms = 14;
-constexpr int kMaxMono = 8;
+// Coefficient polynomials use the monomials {1, c3, c1, c2, c1 c3} of
+// c = (sigma, tau, rho) of the node, in that order.
+constexpr int kNumMono = 5;
 
 // Device view of the basis-change tables of one node size.
 struct DevLevel {
@@ -104,9 +93,8 @@ struct DevLevel {
   const int* c_rowptr;
   const uint32_t* c_src;
   const uint16_t* c_pid;
-  const double* poly;  // npoly * nmono
-  int nmono;
-  int mono[3 * kMaxMono];
+  const double* poly;  // npoly * kNumMono, constant polynomials first
+  int nconst;          // ids below nconst are constants
 };
 
 constexpr int kMaxVol = 120;
