@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
@@ -18,6 +19,7 @@
 #include "fcc_dct.h"
 #include "kernels.hpp"
 #include "orbits.inc"
+#include "plan.hpp"
 
 namespace fcc {
 
@@ -91,10 +93,10 @@ __device__ __forceinline__ void build_A(const cx<R> P[3][7], cx<R> a4[4][4], cx<
 #pragma unroll
     for (int j = 0; j < 3; ++j) a3[i][j] = {R(0), R(0)};
 #define FCC_ADD_A(f, l0, l1, l2, w)                                                   \
-  if ((f) != 0) {                                                                     \
+  if constexpr ((f) != 0) {                                                           \
     constexpr int mu_ = (((l0) & 1) << 2) | (((l1) & 1) << 1) | ((l2) & 1);           \
     const cx<R> v_ = R(w) * phase(P, (l0), (l1), (l2));                               \
-    if (blk_class(f) == 1)                                                            \
+    if constexpr (blk_class(f) == 1)                                                  \
       a4[blk_pos(mu_)][blk_pos(f)] = a4[blk_pos(mu_)][blk_pos(f)] + v_;               \
     else                                                                              \
       a3[blk_pos(mu_)][blk_pos(f)] = a3[blk_pos(mu_)][blk_pos(f)] + v_;               \
@@ -508,18 +510,6 @@ bool singular_skew(int n, const double rst[3]) {
 
 }  // namespace
 
-struct fcc_plan_s {
-  int n = 0, D = 0, device = 0;
-  double rst[3] = {0.125, 0.0, 0.375};
-  fcc_precision prec = FCC_PREC_FP64;
-  unsigned flags = 0;
-  bool stages64 = true;
-  std::vector<DevLevel> lv;  // per level L: tables of nl = n >> L
-  double2* hph = nullptr;    // phase tables, all levels
-  void* ws[2] = {nullptr, nullptr};
-  size_t ws_bytes = 0;
-};
-
 namespace {
 
 DT in_type(const fcc_plan_s* p) {
@@ -699,6 +689,175 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 }  // namespace
 
+namespace fcc {
+fcc_status enqueue_forward_ext(const fcc_plan_s* p, int nvol, const void* const* in, void* const* out,
+                               void* const* ws0, void* const* ws1, hipStream_t st) {
+  return enqueue_forward(p, nvol, in, out, ws0, ws1, st);
+}
+fcc_status enqueue_inverse_ext(const fcc_plan_s* p, int nvol, const void* const* in, void* const* out,
+                               void* const* ws0, void* const* ws1, hipStream_t st) {
+  return enqueue_inverse(p, nvol, in, out, ws0, ws1, st);
+}
+}  // namespace fcc
+
+namespace {
+
+// ---- batched execution: volumes grouped by plan configuration, recorded
+// into a HIP graph on first use and replayed afterwards ----------------------
+struct BatchGroup {
+  const fcc_plan_s* p = nullptr;   // representative plan
+  std::vector<int> vols;           // indices into the call's arrays
+};
+
+struct BatchExec {
+  std::vector<uintptr_t> key;      // count, direction, plans, in, out
+  std::vector<void*> allocations;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+};
+
+std::mutex& batch_mu() {
+  static std::mutex m;
+  return m;
+}
+std::vector<BatchExec*>& batch_cache() {
+  static std::vector<BatchExec*> c;
+  return c;
+}
+
+void free_batch(BatchExec* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (void* a : b->allocations) (void)hipFree(a);
+  delete b;
+}
+
+bool same_config(const fcc_plan_s* a, const fcc_plan_s* b) {
+  return a->n == b->n && a->prec == b->prec && a->flags == b->flags && a->stages64 == b->stages64 &&
+         a->dense == b->dense && a->rst[0] == b->rst[0] && a->rst[1] == b->rst[1] && a->rst[2] == b->rst[2];
+}
+
+// Resources of one group, allocated before capture (no allocation or
+// synchronous copy may happen while a stream is being captured).
+struct GroupRes {
+  void** rows = nullptr;   // dense: device row pointers (in, out) and scales
+  float* scale = nullptr;
+  void* ws = nullptr;      // fast path: per-volume scratch pairs
+  size_t wb = 0;
+};
+
+fcc_status prepare_group(BatchExec* bx, const BatchGroup& g, const void* const* in, void* const* out, GroupRes* r) {
+  const fcc_plan_s* p = g.p;
+  const int cnt = int(g.vols.size());
+  if (p->dense) {
+    std::vector<const void*> ri(cnt), ro(cnt);
+    for (int v = 0; v < cnt; ++v) {
+      ri[v] = in[g.vols[v]];
+      ro[v] = out[g.vols[v]];
+    }
+    void* d = nullptr;
+    if (hipMalloc(&d, sizeof(void*) * 2 * cnt + sizeof(float) * cnt) != hipSuccess) return FCC_ERR_OOM;
+    bx->allocations.push_back(d);
+    r->rows = static_cast<void**>(d);
+    if (hipMemcpy(r->rows, ri.data(), sizeof(void*) * cnt, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(r->rows + cnt, ro.data(), sizeof(void*) * cnt, hipMemcpyHostToDevice) != hipSuccess)
+      return FCC_ERR_HIP;
+    r->scale = reinterpret_cast<float*>(r->rows + 2 * cnt);
+    return FCC_OK;
+  }
+  if (p->n == 1 || p->D == 0) return FCC_OK;
+  const size_t N = size_t(p->n) * p->n * p->n;
+  r->wb = N * (p->stages64 ? sizeof(double2) : sizeof(float2));
+  if (hipMalloc(&r->ws, r->wb * 2 * cnt) != hipSuccess) return FCC_ERR_OOM;
+  bx->allocations.push_back(r->ws);
+  return FCC_OK;
+}
+
+fcc_status record_group(const BatchGroup& g, const GroupRes& r, const void* const* in, void* const* out, int dir,
+                        hipStream_t st) {
+  const fcc_plan_s* p = g.p;
+  const int cnt = int(g.vols.size());
+  if (p->dense) {
+    void** dp = r.rows;
+    fcc_status s = FCC_OK;
+    if (dir >= 0) s = dense_run(p, p->dfwd, cnt, dp, dp + cnt, nullptr, nullptr, r.scale, st);
+    if (s == FCC_OK && dir == 0) s = dense_run(p, p->dinv, cnt, dp + cnt, dp, nullptr, nullptr, r.scale, st);
+    if (s == FCC_OK && dir < 0) s = dense_run(p, p->dinv, cnt, dp, dp + cnt, nullptr, nullptr, r.scale, st);
+    return s;
+  }
+  for (int c0 = 0; c0 < cnt; c0 += kMaxVol) {
+    const int c = std::min(kMaxVol, cnt - c0);
+    std::vector<const void*> ii(c);
+    std::vector<void*> oo(c), iw(c), w0(c, nullptr), w1(c, nullptr);
+    for (int v = 0; v < c; ++v) {
+      ii[v] = in[g.vols[c0 + v]];
+      iw[v] = const_cast<void*>(in[g.vols[c0 + v]]);  // round trip writes back into in[]
+      oo[v] = out[g.vols[c0 + v]];
+      if (r.ws) {
+        w0[v] = static_cast<char*>(r.ws) + r.wb * (2 * size_t(c0 + v));
+        w1[v] = static_cast<char*>(r.ws) + r.wb * (2 * size_t(c0 + v) + 1);
+      }
+    }
+    fcc_status s = FCC_OK;
+    if (dir >= 0) s = enqueue_forward(p, c, ii.data(), oo.data(), w0.data(), w1.data(), st);
+    if (s == FCC_OK && dir == 0)
+      s = enqueue_inverse(p, c, reinterpret_cast<const void* const*>(oo.data()), iw.data(), w0.data(), w1.data(), st);
+    if (s == FCC_OK && dir < 0) s = enqueue_inverse(p, c, ii.data(), oo.data(), w0.data(), w1.data(), st);
+    if (s != FCC_OK) return s;
+  }
+  return FCC_OK;
+}
+
+fcc_status build_batch(BatchExec* bx, const fcc_plan_t* plans, int count, const void* const* in, void* const* out,
+                       int dir) {
+  std::vector<BatchGroup> groups;
+  for (int i = 0; i < count; ++i) {
+    bool placed = false;
+    for (auto& g : groups)
+      if (same_config(g.p, plans[i])) {
+        g.vols.push_back(i);
+        placed = true;
+        break;
+      }
+    if (!placed) {
+      BatchGroup g;
+      g.p = plans[i];
+      g.vols.push_back(i);
+      groups.push_back(g);
+    }
+  }
+  // record on a private stream (the caller's may be the legacy default stream,
+  // which cannot be captured); kernels only, no memset nodes
+  hipStream_t cap = nullptr;
+  if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return FCC_ERR_HIP;
+  fcc_status s = FCC_OK;
+  std::vector<GroupRes> res(groups.size());
+  for (size_t gi = 0; gi < groups.size() && s == FCC_OK; ++gi) s = prepare_group(bx, groups[gi], in, out, &res[gi]);
+  if (s != FCC_OK) {
+    (void)hipStreamDestroy(cap);
+    return s;
+  }
+  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipStreamDestroy(cap);
+    return FCC_ERR_HIP;
+  }
+  for (size_t gi = 0; gi < groups.size() && s == FCC_OK; ++gi) s = record_group(groups[gi], res[gi], in, out, dir, cap);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(cap, &graph);
+  (void)hipStreamDestroy(cap);
+  if (s != FCC_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture", __LINE__);
+  bx->graph = graph;
+  e = hipGraphInstantiate(&bx->exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate", __LINE__);
+  return FCC_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* fcc_status_string(fcc_status s) {
@@ -742,7 +901,7 @@ fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precis
   if (prec < FCC_PREC_FP64 || prec > FCC_PREC_SPLIT_FP16) return FCC_ERR_INVALID_ARG;
   if ((flags & FCC_STAGES_FP32) && (flags & FCC_STAGES_FP64)) return FCC_ERR_INVALID_ARG;
   if (flags & ~(unsigned)(FCC_REAL_INPUT | FCC_STAGES_FP32 | FCC_STAGES_FP64)) return FCC_ERR_INVALID_ARG;
-  if (prec == FCC_PREC_SPLIT_BF16 || prec == FCC_PREC_SPLIT_FP16) return FCC_ERR_UNSUPPORTED;
+  if ((prec == FCC_PREC_SPLIT_BF16 || prec == FCC_PREC_SPLIT_FP16) && n > 8) return FCC_ERR_UNSUPPORTED;
   double r[3] = {0.125, 0.0, 0.375};
   if (rst)
     for (int d = 0; d < 3; ++d) {
@@ -760,7 +919,8 @@ fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precis
   // Stage precision.  FP32 stages lose accuracy with depth (the skew children
   // approach W-fixed points and their coefficient vectors become ill
   // conditioned); measured FP32-stage errors pass 1e-5 only up to n = 8.
-  if (prec == FCC_PREC_FP64)
+  p->dense = prec == FCC_PREC_SPLIT_BF16 || prec == FCC_PREC_SPLIT_FP16;
+  if (prec == FCC_PREC_FP64 || p->dense)
     p->stages64 = true;
   else if (flags & FCC_STAGES_FP32)
     p->stages64 = false;
@@ -803,6 +963,11 @@ fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precis
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) s = hip_fail(e, "hipStreamSynchronize", __LINE__);
   }
+  if (s == FCC_OK && p->dense) {
+    s = dense_prepare(p, st);
+    if (s == FCC_OK && hipMalloc(&p->rowscale, sizeof(float)) != hipSuccess) s = FCC_ERR_OOM;
+    p->rows_cap = 1;
+  }
   if (s != FCC_OK) {
     fcc_dct_destroy(p);
     return s;
@@ -813,6 +978,21 @@ fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precis
 
 fcc_status fcc_dct_destroy(fcc_plan_t p) {
   if (!p) return FCC_OK;
+  {
+    std::lock_guard<std::mutex> lock(batch_mu());
+    auto& c = batch_cache();
+    for (size_t i = 0; i < c.size();) {
+      bool uses = false;
+      for (size_t k = 2; k < c[i]->key.size(); k += 3) uses |= c[i]->key[k] == reinterpret_cast<uintptr_t>(p);
+      if (uses) {
+        free_batch(c[i]);
+        c.erase(c.begin() + i);
+      } else {
+        ++i;
+      }
+    }
+  }
+  dense_free(p);
   if (p->hph) (void)hipFree(p->hph);
   for (void* w : p->ws)
     if (w) (void)hipFree(w);
@@ -824,6 +1004,8 @@ fcc_status fcc_dct_forward(fcc_plan_t p, const void* x, void* X, void* hip_strea
   if (!p || !x || !X || !aligned16(x) || !aligned16(X)) return FCC_ERR_INVALID_ARG;
   if (x == X) return FCC_ERR_UNSUPPORTED;
   (void)hipGetLastError();
+  if (p->dense)
+    return dense_run(p, p->dfwd, 1, nullptr, nullptr, x, X, p->rowscale, static_cast<hipStream_t>(hip_stream));
   void* w0 = p->ws[0];
   void* w1 = p->ws[1];
   return enqueue_forward(p, 1, &x, &X, &w0, &w1, static_cast<hipStream_t>(hip_stream));
@@ -833,6 +1015,8 @@ fcc_status fcc_dct_inverse(fcc_plan_t p, const void* X, void* x, void* hip_strea
   if (!p || !x || !X || !aligned16(x) || !aligned16(X)) return FCC_ERR_INVALID_ARG;
   if (x == X) return FCC_ERR_UNSUPPORTED;
   (void)hipGetLastError();
+  if (p->dense)
+    return dense_run(p, p->dinv, 1, nullptr, nullptr, X, x, p->rowscale, static_cast<hipStream_t>(hip_stream));
   void* w0 = p->ws[0];
   void* w1 = p->ws[1];
   return enqueue_inverse(p, 1, &X, &x, &w0, &w1, static_cast<hipStream_t>(hip_stream));
@@ -843,7 +1027,7 @@ fcc_status fcc_dct_time_launches(fcc_plan_t p, const void* in, void* out, int di
   if (!p || !in || !out || !count || reps < 1 || (direction != 1 && direction != -1)) return FCC_ERR_INVALID_ARG;
   if (!aligned16(in) || !aligned16(out) || in == out) return FCC_ERR_INVALID_ARG;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  const int slots = p->n == 1 ? 1 : (direction > 0 ? p->D : 2 * p->D);
+  const int slots = (p->n == 1 || p->dense) ? 1 : (direction > 0 ? p->D : 2 * p->D);
   *count = slots;
   if (!ms || cap < slots) return ms ? FCC_ERR_INVALID_ARG : FCC_OK;
   (void)hipGetLastError();
@@ -862,6 +1046,12 @@ fcc_status fcc_dct_time_launches(fcc_plan_t p, const void* in, void* out, int di
     std::vector<hipEvent_t> sub(ev.begin() + size_t(r) * (slots + 1), ev.begin() + size_t(r + 1) * (slots + 1));
     LaunchTimer tm;
     tm.ev = &sub;
+    if (p->dense) {
+      tm.mark(st);
+      s = dense_run(p, direction > 0 ? p->dfwd : p->dinv, 1, nullptr, nullptr, in, out, p->rowscale, st);
+      tm.mark(st);
+      continue;
+    }
     s = direction > 0 ? enqueue_forward(p, 1, &in, &out, &w0, &w1, st, &tm)
                       : enqueue_inverse(p, 1, &in, &out, &w0, &w1, st, &tm);
     if (p->n == 1 && s == FCC_OK) (void)hipEventRecord(sub[1], st);
@@ -893,13 +1083,33 @@ fcc_status fcc_dct_batched(const fcc_plan_t* plans, int count, const void* const
     if (!plans[i] || !in[i] || !out[i] || !aligned16(in[i]) || !aligned16(out[i]) || in[i] == out[i])
       return FCC_ERR_INVALID_ARG;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  (void)hipGetLastError();
+  std::vector<uintptr_t> key;
+  key.reserve(3 * size_t(count) + 2);
+  key.push_back(uintptr_t(count));
+  key.push_back(uintptr_t(direction + 1));
   for (int i = 0; i < count; ++i) {
-    fcc_status s = FCC_OK;
-    if (direction >= 0) s = fcc_dct_forward(plans[i], in[i], out[i], st);
-    if (s == FCC_OK && direction == 0) s = fcc_dct_inverse(plans[i], out[i], const_cast<void*>(in[i]), st);
-    if (s == FCC_OK && direction < 0) s = fcc_dct_inverse(plans[i], in[i], out[i], st);
-    if (s != FCC_OK) return s;
+    key.push_back(reinterpret_cast<uintptr_t>(plans[i]));
+    key.push_back(reinterpret_cast<uintptr_t>(in[i]));
+    key.push_back(reinterpret_cast<uintptr_t>(out[i]));
   }
+  std::lock_guard<std::mutex> lock(batch_mu());
+  BatchExec* bx = nullptr;
+  for (BatchExec* b : batch_cache())
+    if (b->key == key) bx = b;
+  if (!bx) {
+    bx = new (std::nothrow) BatchExec;
+    if (!bx) return FCC_ERR_OOM;
+    bx->key = key;
+    fcc_status s = build_batch(bx, plans, count, in, out, direction);
+    if (s != FCC_OK) {
+      free_batch(bx);
+      return s;
+    }
+    batch_cache().push_back(bx);
+  }
+  hipError_t e = hipGraphLaunch(bx->exec, st);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch", __LINE__);
   return FCC_OK;
 }
 

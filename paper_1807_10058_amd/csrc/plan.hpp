@@ -1,0 +1,48 @@
+// Private plan state shared by the translation units of libfccdct.so.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "fcc_dct.h"
+#include "kernels.hpp"
+
+// Dense path (FCC_PREC_SPLIT_*): the whole transform as one matrix W applied by
+// a split-precision MFMA GEMM  out[b, :] = W in[b, :]  (see dense.hip).
+struct DenseOp {
+  int K = 0, Nc = 0;       // logical GEMM sizes: in row length, out row length (floats)
+  int Kp = 0, Ncp = 0;     // padded sizes of the stored operand
+  void* w_hi = nullptr;    // Ncp x Kp, 16-bit (bf16 or fp16), row-major
+  void* w_lo = nullptr;
+  float w_unscale = 1.0f;  // the stored W is the true one times 1/w_unscale
+};
+
+struct fcc_plan_s {
+  int n = 0, D = 0, device = 0;
+  double rst[3] = {0.125, 0.0, 0.375};
+  fcc_precision prec = FCC_PREC_FP64;
+  unsigned flags = 0;
+  bool stages64 = true;
+  std::vector<fcc::DevLevel> lv;  // per level L: tables of nl = n >> L
+  double2* hph = nullptr;         // phase tables, all levels
+  void* ws[2] = {nullptr, nullptr};
+  size_t ws_bytes = 0;
+  bool dense = false;             // FCC_PREC_SPLIT_*: dense matrix on MFMA
+  DenseOp dfwd, dinv;
+  float* rowscale = nullptr;      // per-row input scales (FP16 split), rows_cap entries
+  int rows_cap = 0;
+};
+
+namespace fcc {
+// dense.hip
+fcc_status dense_prepare(fcc_plan_s* p, hipStream_t st);
+fcc_status dense_run(const fcc_plan_s* p, const DenseOp& op, int M, const void* const* in_rows_dev,
+                     void* const* out_rows_dev, const void* in_base, void* out_base, float* rowscale,
+                     hipStream_t st);
+void dense_free(fcc_plan_s* p);
+// fcc_dct.hip: the level-by-level fast path for nvol volumes of plan p
+fcc_status enqueue_forward_ext(const fcc_plan_s* p, int nvol, const void* const* in, void* const* out,
+                               void* const* ws0, void* const* ws1, hipStream_t st);
+fcc_status enqueue_inverse_ext(const fcc_plan_s* p, int nvol, const void* const* in, void* const* out,
+                               void* const* ws0, void* const* ws1, hipStream_t st);
+}  // namespace fcc
