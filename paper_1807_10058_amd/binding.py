@@ -11,7 +11,7 @@ _LIB_PATH = os.path.join(_HERE, "libfccdct.so")
 
 FCC_OK = 0
 FCC_PREC_FP64, FCC_PREC_FP32, FCC_PREC_SPLIT_BF16, FCC_PREC_SPLIT_FP16 = 0, 1, 2, 3
-FCC_REAL_INPUT, FCC_STAGES_FP32, FCC_STAGES_FP64 = 1, 2, 4
+FCC_REAL_INPUT, FCC_STAGES_FP32, FCC_STAGES_FP64, FCC_LEVEL0_FP32 = 1, 2, 4, 8
 
 # torch is loaded first so that libfccdct.so binds to the HIP runtime torch
 # already carries (same soname): one HIP/HSA runtime per process.

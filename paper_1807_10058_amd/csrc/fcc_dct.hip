@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -54,6 +55,46 @@ __device__ __forceinline__ cx<R> phase(const cx<R> P[3][7], int l0, int l1, int 
   return P[0][l0 + 3] * P[1][l1 + 3] * P[2][l2 + 3];
 }
 
+// Positive powers only: Q[d][k] = h_d^(k+1), k = 0..2; negative powers are
+// conjugates (|h_d| = 1).  Indices are compile-time constants at every use.
+template <typename R>
+__device__ __forceinline__ void node_pos_powers(const double2* __restrict__ hph, int L, const int J[3], cx<R> Q[3][3]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double2 hv = hph[(d << L) + J[d]];
+    Q[d][0] = {R(hv.x), R(hv.y)};
+    Q[d][1] = Q[d][0] * Q[d][0];
+    Q[d][2] = Q[d][1] * Q[d][0];
+  }
+}
+template <typename R>
+__device__ __forceinline__ cx<R> qpow(const cx<R> Q[3][3], int d, int l) {
+  if (l == 0) return {R(1), R(0)};
+  return l > 0 ? Q[d][l - 1] : conj(Q[d][-l - 1]);
+}
+template <typename R>
+__device__ __forceinline__ cx<R> qphase(const cx<R> Q[3][3], int l0, int l1, int l2) {
+  cx<R> v = qpow(Q, 0, l0);
+  if (l1 != 0) v = v * qpow(Q, 1, l1);
+  if (l2 != 0) v = v * qpow(Q, 2, l2);
+  return v;
+}
+
+// t = A(phi) y accumulated term by term (A is never materialised):
+// t[mu] = sum over orbit terms (f, lambda) with lambda = mu mod 2 of w e^{i pi lambda.phi} y[f].
+template <typename R>
+__device__ __forceinline__ void apply_A(const cx<R> Q[3][3], const cx<R> y[8], cx<R> t[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) t[i] = {R(0), R(0)};
+#define FCC_APPLY_A(f, l0, l1, l2, w)                                               \
+  {                                                                                 \
+    constexpr int mu_ = (((l0) & 1) << 2) | (((l1) & 1) << 1) | ((l2) & 1);        \
+    t[mu_] = t[mu_] + (R(w) * qphase(Q, (l0), (l1), (l2))) * y[f];                 \
+  }
+  FCC_DCT2_TERMS(FCC_APPLY_A)
+#undef FCC_APPLY_A
+}
+
 // c = (sigma, tau, rho)(phi) = (T_100, T_010, T_001)(phi) and the five
 // monomials of the coefficient polynomials, in the fixed order
 // {1, c3, c1, c2, c1 c3} (the only ones the derivation produces).
@@ -83,7 +124,7 @@ __host__ __device__ constexpr int blk_class(int f) {
 
 // Blocks of A(phi): a4 (classes {1,3,4,6}) and a3 ({2,5,7}); A[0][0] = 1.
 template <typename R>
-__device__ __forceinline__ void build_A(const cx<R> P[3][7], cx<R> a4[4][4], cx<R> a3[3][3]) {
+__device__ __forceinline__ void build_A(const cx<R> Q[3][3], cx<R> a4[4][4], cx<R> a3[3][3]) {
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -95,7 +136,7 @@ __device__ __forceinline__ void build_A(const cx<R> P[3][7], cx<R> a4[4][4], cx<
 #define FCC_ADD_A(f, l0, l1, l2, w)                                                   \
   if constexpr ((f) != 0) {                                                           \
     constexpr int mu_ = (((l0) & 1) << 2) | (((l1) & 1) << 1) | ((l2) & 1);           \
-    const cx<R> v_ = R(w) * phase(P, (l0), (l1), (l2));                               \
+    const cx<R> v_ = R(w) * qphase(Q, (l0), (l1), (l2));                              \
     if constexpr (blk_class(f) == 1)                                                  \
       a4[blk_pos(mu_)][blk_pos(f)] = a4[blk_pos(mu_)][blk_pos(f)] + v_;               \
     else                                                                              \
@@ -167,18 +208,24 @@ __device__ __forceinline__ void solve_small(cx<R> M[K][K], cx<R> b[K]) {
 struct CubeIdx {
   int J[3], a[3];
 };
-__device__ __forceinline__ CubeIdx cube_of(long long t, int n, int L) {
-  const long long h = n >> 1;
-  int qz = int(t % h), qy = int((t / h) % h), qx = int(t / (h * h));
-  int mask = (1 << L) - 1;
-  CubeIdx c;
-  c.J[0] = qx & mask;
-  c.J[1] = qy & mask;
-  c.J[2] = qz & mask;
-  c.a[0] = qx >> L;
-  c.a[1] = qy >> L;
-  c.a[2] = qz >> L;
-  return c;
+// Thread t -> (node J, cube abc): the 8^L nodes of level L vary fastest, so
+// from level 2 on a whole wavefront works on one cube position of 64 nodes
+// (one table row, loads of adjacent nodes' elements); at levels 0 and 1 a
+// wavefront covers one table slice.
+__device__ __forceinline__ CubeIdx cube_of(long long t, int n, int L, int* cube) {
+  const int mask = (1 << L) - 1;
+  const int jf = int(t & ((1LL << (3 * L)) - 1));
+  const long long c = t >> (3 * L);
+  const int m = (n >> L) >> 1;
+  CubeIdx ci;
+  ci.J[0] = jf >> (2 * L);
+  ci.J[1] = (jf >> L) & mask;
+  ci.J[2] = jf & mask;
+  ci.a[0] = int(c / ((long long)m * m));
+  ci.a[1] = int((c / m) % m);
+  ci.a[2] = int(c % m);
+  *cube = int(c);
+  return ci;
 }
 __device__ __forceinline__ long long gpos(int n, int L, const int J[3], int kx, int ky, int kz) {
   return ((long long)(J[0] + (kx << L)) * n + (J[1] + (ky << L))) * n + (J[2] + (kz << L));
@@ -187,13 +234,52 @@ __device__ __forceinline__ long long gpos(int n, int L, const int J[3], int kx, 
 // Coefficient of one table entry: polynomials are sorted so that ids below
 // lv.nconst are constants (86% of all entries), read with one load.
 template <typename R>
-__device__ __forceinline__ cx<R> poly_value(const DevLevel& lv, int pid, const cx<R> mono[kNumMono]) {
-  const double* pc = lv.poly + pid * kNumMono;
-  if (pid < lv.nconst) return {R(pc[0]), R(0)};
+__device__ __forceinline__ cx<R> poly_value(const double* poly, int nconst, int pid, const cx<R> mono[kNumMono]) {
+  const double* pc = poly + pid * kNumMono;
+  if (pid < nconst) return {R(pc[0]), R(0)};
   cx<R> v = R(pc[0]) * mono[0];
 #pragma unroll
   for (int q = 1; q < kNumMono; ++q) v = v + R(pc[q]) * mono[q];
   return v;
+}
+
+// The level's coefficient polynomials, copied to LDS by the whole block.
+constexpr int kMaxPoly = 256;
+__device__ __forceinline__ void load_polys(const DevLevel& lv, double* sp) {
+  for (int i = threadIdx.x; i < lv.npoly * kNumMono; i += blockDim.x) sp[i] = lv.poly[i];
+  __syncthreads();
+}
+
+// Gather sum_e coef(pid_e) in[J + 2^L src_e] over one sliced row, four entries
+// in flight at a time.
+template <typename R, typename TI>
+__device__ __forceinline__ cx<R> gather_row(const TI* __restrict__ in, int n, int L, const int J[3], const DevSide& sd,
+                                            int S, int r, int j, const double* sp, int nconst,
+                                            const cx<R> mono[kNumMono]) {
+  const int e0 = sd.start[r] + j, len = sd.len[r];
+  cx<R> acc{R(0), R(0)};
+  int e = 0;
+  for (; e + 4 <= len; e += 4) {
+    uint32_t s4[4];
+    uint16_t p4[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      s4[u] = sd.src[e0 + (e + u) * S];
+      p4[u] = sd.pid[e0 + (e + u) * S];
+    }
+    cx<R> v4[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      v4[u] = IO<TI, R>::ld(in, gpos(n, L, J, int(s4[u] >> 20), int((s4[u] >> 10) & 1023u), int(s4[u] & 1023u)));
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = acc + poly_value(sp, nconst, p4[u], mono) * v4[u];
+  }
+  for (; e < len; ++e) {
+    const uint32_t s = sd.src[e0 + e * S];
+    const cx<R> v = IO<TI, R>::ld(in, gpos(n, L, J, int(s >> 20), int((s >> 10) & 1023u), int(s & 1023u)));
+    acc = acc + poly_value(sp, nconst, sd.pid[e0 + e * S], mono) * v;
+  }
+  return acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -201,54 +287,40 @@ __device__ __forceinline__ cx<R> poly_value(const DevLevel& lv, int pid, const c
 // ---------------------------------------------------------------------------
 
 // Forward level L: basis change B_nl(phi) then DCT_2(phi) (x) I on every cube.
+#ifndef FCC_FWD_ATTR
+#define FCC_FWD_ATTR
+#endif
+#ifndef FCC_ROW_UNROLL
+#define FCC_ROW_UNROLL 8
+#endif
 template <typename R, typename TI, typename TO>
-__global__ __launch_bounds__(256) void k_fwd_level(VolSet vs, int n, int L, DevLevel lv,
+__global__ __launch_bounds__(256) FCC_FWD_ATTR void k_fwd_level(VolSet vs, int n, int L, DevLevel lv,
                                                    const double2* __restrict__ hph) {
+  __shared__ double sp[kMaxPoly * kNumMono];
+  load_polys(lv, sp);
   const long long h = n >> 1;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= h * h * h) return;
   const TI* __restrict__ in = static_cast<const TI*>(vs.in[blockIdx.y]);
   TO* __restrict__ out = static_cast<TO*>(vs.out[blockIdx.y]);
-  CubeIdx ci = cube_of(t, n, L);
-  const int m = (n >> L) >> 1;
-  cx<R> P[3][7];
-  node_powers(hph, L, ci.J, P);
+  int cube;
+  CubeIdx ci = cube_of(t, n, L, &cube);
   cx<R> mono[kNumMono];
-  node_monomials(P, mono);
-
+  {
+    cx<R> P[3][7];
+    node_powers(hph, L, ci.J, P);
+    node_monomials(P, mono);
+  }
   cx<R> y[8];
-  const int cube = (ci.a[0] * m + ci.a[1]) * m + ci.a[2];
-#pragma unroll
-  for (int f = 0; f < 8; ++f) {
-    const int r = cube * 8 + f;
-    cx<R> acc{R(0), R(0)};
-    for (int e = lv.b_rowptr[r]; e < lv.b_rowptr[r + 1]; ++e) {
-      uint32_t s = lv.b_src[e];
-      cx<R> v = IO<TI, R>::ld(in, gpos(n, L, ci.J, int(s >> 20), int((s >> 10) & 1023u), int(s & 1023u)));
-      acc = acc + poly_value(lv, lv.b_pid[e], mono) * v;
-    }
-    y[f] = acc;
-  }
-  // z = H_8 A(phi) y
-  cx<R> a4[4][4], a3[3][3];
-  build_A(P, a4, a3);
+  const int slice = cube / lv.S, j = cube - slice * lv.S;
+#pragma unroll FCC_ROW_UNROLL
+  for (int f = 0; f < 8; ++f) y[f] = gather_row<R, TI>(in, n, L, ci.J, lv.b, lv.S, slice * 8 + f, j, sp, lv.nconst, mono);
+  // z = H_8 A(phi) y; the phases are reloaded rather than kept live over the gathers
+  __asm__ volatile("" ::: "memory");
+  cx<R> Q[3][3];
+  node_pos_powers(hph, L, ci.J, Q);
   cx<R> tt[8];
-  tt[0] = y[0];
-  const int c4[4] = {1, 3, 4, 6}, c3[3] = {2, 5, 7};
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    cx<R> s{R(0), R(0)};
-#pragma unroll
-    for (int j = 0; j < 4; ++j) s = s + a4[i][j] * y[c4[j]];
-    tt[c4[i]] = s;
-  }
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    cx<R> s{R(0), R(0)};
-#pragma unroll
-    for (int j = 0; j < 3; ++j) s = s + a3[i][j] * y[c3[j]];
-    tt[c3[i]] = s;
-  }
+  apply_A(Q, y, tt);
   hadamard8(tt);
 #pragma unroll
   for (int i = 0; i < 8; ++i)
@@ -257,15 +329,19 @@ __global__ __launch_bounds__(256) void k_fwd_level(VolSet vs, int n, int L, DevL
 }
 
 // Inverse level L, first pass: y = DCT_2(phi)^{-1} z = A(phi)^{-1} H_8 z / 8 on every cube.
+#ifndef FCC_INV_ATTR
+#define FCC_INV_ATTR
+#endif
 template <typename R, typename TI>
-__global__ __launch_bounds__(256) void k_inv_dct2(VolSet vs, int n, int L, const double2* __restrict__ hph) {
+__global__ __launch_bounds__(256) FCC_INV_ATTR void k_inv_dct2(VolSet vs, int n, int L, const double2* __restrict__ hph) {
   const long long h = n >> 1;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= h * h * h) return;
   // may run in place (in == out): each thread reads and writes only its own cube
   const TI* in = static_cast<const TI*>(vs.in[blockIdx.y]);
   cx<R>* out = static_cast<cx<R>*>(vs.out[blockIdx.y]);
-  CubeIdx ci = cube_of(t, n, L);
+  int cube;
+  CubeIdx ci = cube_of(t, n, L, &cube);
   cx<R> z[8];
   long long pos[8];
 #pragma unroll
@@ -274,10 +350,10 @@ __global__ __launch_bounds__(256) void k_inv_dct2(VolSet vs, int n, int L, const
     z[i] = IO<TI, R>::ld(in, pos[i]);
   }
   hadamard8(z);
-  cx<R> P[3][7];
-  node_powers(hph, L, ci.J, P);
+  cx<R> Q[3][3];
+  node_pos_powers(hph, L, ci.J, Q);
   cx<R> a4[4][4], a3[3][3];
-  build_A(P, a4, a3);
+  build_A(Q, a4, a3);
   const int c4[4] = {1, 3, 4, 6}, c3[3] = {2, 5, 7};
   cx<R> b4[4], b3[3];
 #pragma unroll
@@ -300,27 +376,25 @@ __global__ __launch_bounds__(256) void k_inv_dct2(VolSet vs, int n, int L, const
 template <typename R, typename TO>
 __global__ __launch_bounds__(256) void k_inv_basis(VolSet vs, int n, int L, DevLevel lv,
                                                    const double2* __restrict__ hph) {
+  __shared__ double sp[kMaxPoly * kNumMono];
+  load_polys(lv, sp);
   const long long h = n >> 1;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= h * h * h) return;
   const cx<R>* __restrict__ in = static_cast<const cx<R>*>(vs.in[blockIdx.y]);
   TO* __restrict__ out = static_cast<TO*>(vs.out[blockIdx.y]);
-  CubeIdx ci = cube_of(t, n, L);
-  const int m = (n >> L) >> 1;
-  cx<R> P[3][7];
-  node_powers(hph, L, ci.J, P);
+  int cube;
+  CubeIdx ci = cube_of(t, n, L, &cube);
   cx<R> mono[kNumMono];
-  node_monomials(P, mono);
-  const int cube = (ci.a[0] * m + ci.a[1]) * m + ci.a[2];
+  {
+    cx<R> P[3][7];
+    node_powers(hph, L, ci.J, P);
+    node_monomials(P, mono);
+  }
+  const int slice = cube / lv.S, j = cube - slice * lv.S;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const int r = cube * 8 + i;
-    cx<R> acc{R(0), R(0)};
-    for (int e = lv.c_rowptr[r]; e < lv.c_rowptr[r + 1]; ++e) {
-      uint32_t s = lv.c_src[e];
-      cx<R> v = in[gpos(n, L, ci.J, int(s >> 20), int((s >> 10) & 1023u), int(s & 1023u))];
-      acc = acc + poly_value(lv, lv.c_pid[e], mono) * v;
-    }
+    const cx<R> acc = gather_row<R, cx<R>>(in, n, L, ci.J, lv.c, lv.S, slice * 8 + i, j, sp, lv.nconst, mono);
     IO<TO, R>::st(out, gpos(n, L, ci.J, ((i >> 2) & 1) + 2 * ci.a[0], ((i >> 1) & 1) + 2 * ci.a[1], (i & 1) + 2 * ci.a[2]),
                   acc);
   }
@@ -364,7 +438,7 @@ enum class DT { F32R, F64R, F32C, F64C };
 
 struct DevTablesCache {
   std::mutex mu;
-  std::map<std::pair<int, int>, DevLevel> levels;  // (device, nl)
+  std::map<std::array<int, 3>, DevLevel> levels;  // (device, nl, cubes per slice)
   std::vector<void*> owned;
 };
 DevTablesCache& cache() {
@@ -412,9 +486,47 @@ fcc_status upload(const std::vector<T>& v, const T** out) {
   return FCC_OK;
 }
 
-fcc_status device_level(int dev, int nl, DevLevel* out) {
+// Sliced copy of one side's gather rows (see DevSide).  rowptr is the CSR of
+// rows cube * 8 + f; zero_pid names a polynomial equal to zero.
+fcc_status upload_side(const std::vector<int>& rowptr, const std::vector<uint32_t>& src,
+                       const std::vector<uint16_t>& pid, int S, uint16_t zero_pid, DevSide* out) {
+  const int rows = int(rowptr.size()) - 1, cubes = rows / 8, slices = (cubes + S - 1) / S;
+  std::vector<int> start(size_t(slices) * 8), len(size_t(slices) * 8);
+  size_t total = 0;
+  for (int sl = 0; sl < slices; ++sl)
+    for (int f = 0; f < 8; ++f) {
+      int mx = 0;
+      for (int j = 0; j < S && sl * S + j < cubes; ++j) {
+        const int r = (sl * S + j) * 8 + f;
+        mx = std::max(mx, rowptr[r + 1] - rowptr[r]);
+      }
+      start[size_t(sl) * 8 + f] = int(total);
+      len[size_t(sl) * 8 + f] = mx;
+      total += size_t(mx) * S;
+    }
+  if (total > 0x7fffffffu) return FCC_ERR_UNSUPPORTED;
+  std::vector<uint32_t> ssrc(total, 0u);
+  std::vector<uint16_t> spid(total, zero_pid);
+  for (int sl = 0; sl < slices; ++sl)
+    for (int f = 0; f < 8; ++f)
+      for (int j = 0; j < S && sl * S + j < cubes; ++j) {
+        const int r = (sl * S + j) * 8 + f;
+        for (int e = 0; e < rowptr[r + 1] - rowptr[r]; ++e) {
+          const size_t q = size_t(start[size_t(sl) * 8 + f]) + size_t(e) * S + j;
+          ssrc[q] = src[rowptr[r] + e];
+          spid[q] = pid[rowptr[r] + e];
+        }
+      }
+  fcc_status s;
+  if ((s = upload(start, &out->start)) != FCC_OK) return s;
+  if ((s = upload(len, &out->len)) != FCC_OK) return s;
+  if ((s = upload(ssrc, &out->src)) != FCC_OK) return s;
+  return upload(spid, &out->pid);
+}
+
+fcc_status device_level(int dev, int nl, int S, DevLevel* out) {
   auto& C = cache();
-  auto key = std::make_pair(dev, nl);
+  std::array<int, 3> key{dev, nl, S};
   auto it = C.levels.find(key);
   if (it != C.levels.end()) {
     *out = it->second;
@@ -448,8 +560,14 @@ fcc_status device_level(int dev, int nl, DevLevel* out) {
   std::stable_partition(order.begin(), order.end(), is_const);
   int nconst = 0;
   for (int p = 0; p < T->npoly; ++p) nconst += is_const(p) ? 1 : 0;
-  std::vector<double> poly(fixed.size());
-  for (int i = 0; i < T->npoly; ++i) {
+  // one extra constant polynomial equal to zero pads the sliced tables
+  order.insert(order.begin() + nconst, -1);
+  ++nconst;
+  const uint16_t zero_pid = uint16_t(nconst - 1);
+  newid.resize(T->npoly + 1);
+  std::vector<double> poly(fixed.size() + kNumMono, 0.0);
+  for (int i = 0; i <= T->npoly; ++i) {
+    if (order[i] < 0) continue;
     newid[order[i]] = i;
     for (int q = 0; q < kNumMono; ++q) poly[size_t(i) * kNumMono + q] = fixed[size_t(order[i]) * kNumMono + q];
   }
@@ -458,14 +576,13 @@ fcc_status device_level(int dev, int nl, DevLevel* out) {
   for (size_t e = 0; e < cp.size(); ++e) cp[e] = (uint16_t)newid[T->c_pid[e]];
   DevLevel lv{};
   fcc_status s;
-  if ((s = upload(T->b_rowptr, &lv.b_rowptr)) != FCC_OK) return s;
-  if ((s = upload(T->b_src, &lv.b_src)) != FCC_OK) return s;
-  if ((s = upload(bp, &lv.b_pid)) != FCC_OK) return s;
-  if ((s = upload(T->c_rowptr, &lv.c_rowptr)) != FCC_OK) return s;
-  if ((s = upload(T->c_src, &lv.c_src)) != FCC_OK) return s;
-  if ((s = upload(cp, &lv.c_pid)) != FCC_OK) return s;
+  if ((s = upload_side(T->b_rowptr, T->b_src, bp, S, zero_pid, &lv.b)) != FCC_OK) return s;
+  if ((s = upload_side(T->c_rowptr, T->c_src, cp, S, zero_pid, &lv.c)) != FCC_OK) return s;
   if ((s = upload(poly, &lv.poly)) != FCC_OK) return s;
   lv.nconst = nconst;
+  lv.npoly = T->npoly + 1;
+  if (lv.npoly > kMaxPoly) return FCC_ERR_UNSUPPORTED;
+  lv.S = S;
   C.levels.emplace(key, lv);
   *out = lv;
   return FCC_OK;
@@ -519,6 +636,13 @@ DT in_type(const fcc_plan_s* p) {
 }
 DT cplx_type(const fcc_plan_s* p) { return p->prec == FCC_PREC_FP64 ? DT::F64C : DT::F32C; }
 DT stage_type(const fcc_plan_s* p) { return p->stages64 ? DT::F64C : DT::F32C; }
+// Type of the buffer that holds the coefficient vectors of level L's nodes
+// (the input of forward level L, the output of inverse level L).  With
+// level0_fp32 the top level's result (level 1's input) is complex64; the
+// in-place DCT_2^{-1} pass of level L then reads and writes elements of one
+// size (buf_type(L+1) has the size of level L's arithmetic type) at every L.
+DT buf_type(const fcc_plan_s* p, int L) { return (p->level0_fp32 && L == 1) ? DT::F32C : stage_type(p); }
+bool arith64(const fcc_plan_s* p, int L) { return p->stages64 && !(p->level0_fp32 && L == 0); }
 
 constexpr int kBlock = 256;
 
@@ -626,9 +750,9 @@ fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, const void* const* in,
       vs.in[v] = src[v];
       vs.out[v] = dst[v];
     }
-    DT ti = L == 0 ? in_type(p) : stage_type(p);
-    DT to = last ? cplx_type(p) : stage_type(p);
-    if (p->stages64)
+    DT ti = L == 0 ? in_type(p) : buf_type(p, L);
+    DT to = last ? cplx_type(p) : buf_type(p, L + 1);
+    if (arith64(p, L))
       fwd_dispatch<double>(p, L, ti, to, vs, nvol, st);
     else
       fwd_dispatch<float>(p, L, ti, to, vs, nvol, st);
@@ -661,8 +785,10 @@ fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, const void* const* in,
       vs.in[v] = cur[v];
       vs.out[v] = a[v];
     }
-    DT ti = cur_is_user ? cplx_type(p) : stage_type(p);
-    if (p->stages64)
+    // the DCT_2^{-1} pass reads level L+1's result (or the user's X) and
+    // writes level L's cube values in level L's arithmetic type
+    DT ti = cur_is_user ? cplx_type(p) : buf_type(p, L + 1);
+    if (arith64(p, L))
       inv_dct2_dispatch<double>(p, L, ti, vs, nvol, st);
     else
       inv_dct2_dispatch<float>(p, L, ti, vs, nvol, st);
@@ -672,8 +798,8 @@ fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, const void* const* in,
       vs.in[v] = a[v];
       vs.out[v] = dst[v];
     }
-    DT to = L == 0 ? real_or_cplx : stage_type(p);
-    if (p->stages64)
+    DT to = L == 0 ? real_or_cplx : buf_type(p, L);
+    if (arith64(p, L))
       inv_basis_dispatch<double>(p, L, to, vs, nvol, st);
     else
       inv_basis_dispatch<float>(p, L, to, vs, nvol, st);
@@ -900,7 +1026,8 @@ fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precis
   if (!is_pow2(n)) return FCC_ERR_NOT_POW2;
   if (prec < FCC_PREC_FP64 || prec > FCC_PREC_SPLIT_FP16) return FCC_ERR_INVALID_ARG;
   if ((flags & FCC_STAGES_FP32) && (flags & FCC_STAGES_FP64)) return FCC_ERR_INVALID_ARG;
-  if (flags & ~(unsigned)(FCC_REAL_INPUT | FCC_STAGES_FP32 | FCC_STAGES_FP64)) return FCC_ERR_INVALID_ARG;
+  if (flags & ~(unsigned)(FCC_REAL_INPUT | FCC_STAGES_FP32 | FCC_STAGES_FP64 | FCC_LEVEL0_FP32))
+    return FCC_ERR_INVALID_ARG;
   if ((prec == FCC_PREC_SPLIT_BF16 || prec == FCC_PREC_SPLIT_FP16) && n > 8) return FCC_ERR_UNSUPPORTED;
   double r[3] = {0.125, 0.0, 0.375};
   if (rst)
@@ -927,7 +1054,11 @@ fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precis
   else if (flags & FCC_STAGES_FP64)
     p->stages64 = true;
   else
-    p->stages64 = n > 8;
+    p->stages64 = n > 4;
+  // Opt-in: level 0 in FP32.  Rounding at the top level is not amplified by
+  // the well-conditioned children, but it raises the round-trip error from
+  // ~5e-8 to ~4e-6 at n = 32..128 (measured), so it is not the default.
+  p->level0_fp32 = (flags & FCC_LEVEL0_FP32) && prec == FCC_PREC_FP32 && p->stages64 && p->D >= 2;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   fcc_status s = FCC_OK;
   (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
@@ -937,7 +1068,7 @@ fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precis
     if (e != hipSuccess) s = hip_fail(e, "hipGetDevice", __LINE__);
     for (int L = 0; s == FCC_OK && L < p->D; ++L) {
       DevLevel lv;
-      s = device_level(p->device, n >> L, &lv);
+      s = device_level(p->device, n >> L, L == 0 ? 64 : (L == 1 ? 8 : 1), &lv);
       p->lv.push_back(lv);
     }
   }

@@ -81,20 +81,37 @@ struct IO<double2, R> {
   static __device__ __forceinline__ void st(double2* p, long long i, cx<R> v) { p[i] = make_double2(double(v.x), double(v.y)); }
 };
 
+template <typename R2, typename R>
+struct IO<cx<R2>, R> {
+  static __device__ __forceinline__ cx<R> ld(const cx<R2>* p, long long i) {
+    cx<R2> v = p[i];
+    return {R(v.x), R(v.y)};
+  }
+  static __device__ __forceinline__ void st(cx<R2>* p, long long i, cx<R> v) { p[i] = {R2(v.x), R2(v.y)}; }
+};
+
 // Coefficient polynomials use the monomials {1, c3, c1, c2, c1 c3} of
 // c = (sigma, tau, rho) of the node, in that order.
 constexpr int kNumMono = 5;
 
-// Device view of the basis-change tables of one node size.
+// Device view of the basis-change tables of one node size, sliced for the
+// wavefronts that read them: the rows of S consecutive cubes form a slice; for
+// each def (or i) the slice stores max-length entries interleaved cube by cube
+// (entry e of the slice's cube j at start + e * S + j), padded with entries of
+// coefficient zero.  S = 64 / 8^L at levels 0 and 1 (one slice per
+// wavefront), S = 1 below (every lane of a wavefront reads the same row).
+struct DevSide {
+  const int* start;     // per (slice * 8 + f)
+  const int* len;       // per (slice * 8 + f)
+  const uint32_t* src;  // packed node-local position
+  const uint16_t* pid;  // coefficient polynomial
+};
 struct DevLevel {
-  const int* b_rowptr;
-  const uint32_t* b_src;
-  const uint16_t* b_pid;
-  const int* c_rowptr;
-  const uint32_t* c_src;
-  const uint16_t* c_pid;
+  DevSide b, c;        // forward B_nl, inverse C_nl
   const double* poly;  // npoly * kNumMono, constant polynomials first
+  int npoly;
   int nconst;          // ids below nconst are constants
+  int S;               // cubes per slice
 };
 
 constexpr int kMaxVol = 120;

@@ -23,6 +23,7 @@ struct fcc_plan_s {
   fcc_precision prec = FCC_PREC_FP64;
   unsigned flags = 0;
   bool stages64 = true;
+  bool level0_fp32 = false;        // level 0 (top node) in FP32 arithmetic and storage
   std::vector<fcc::DevLevel> lv;  // per level L: tables of nl = n >> L
   double2* hph = nullptr;         // phase tables, all levels
   void* ws[2] = {nullptr, nullptr};
