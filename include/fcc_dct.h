@@ -132,6 +132,14 @@ const char* fcc_status_string(fcc_status s);
 fcc_status fcc_dct_time_launches(fcc_plan_t plan, const void* in, void* out, int direction, int reps,
                                  float* ms, int cap, int* count, void* hip_stream);
 
+/* FP64 round-trip residual on the GPU: *result = max_k |x_k - y_k| / max_k |x_k|
+ * over the plan's n^3 elements, x and y laid out like the forward input
+ * (real with FCC_REAL_INPUT, else complex; float or double per precision).
+ * Typically y = inverse(forward(x)).  Waits for `hip_stream` (the result is a
+ * host value).  Errors: FCC_ERR_INVALID_ARG, FCC_ERR_HIP. */
+fcc_status fcc_dct_roundtrip_residual(fcc_plan_t plan, const void* x, const void* y, double* result,
+                                      void* hip_stream);
+
 /* ---- introspection (host logic; no GPU needed) ------------------------- */
 
 /* Host view of the basis-change tables for one node size nl = 2m (2 <= nl <= 1024).

@@ -40,13 +40,14 @@ _lib.fcc_dct_inverse.argtypes = [_vp, _vp, _vp, _vp]
 _lib.fcc_dct_batched.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                  ctypes.c_int, _vp]
 _lib.fcc_dct_destroy.argtypes = [_vp]
+_lib.fcc_dct_roundtrip_residual.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp]
 _lib.fcc_dct_time_launches.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float),
                                        ctypes.c_int, ctypes.POINTER(ctypes.c_int), _vp]
 _lib.fcc_status_string.argtypes = [ctypes.c_int]
 _lib.fcc_status_string.restype = ctypes.c_char_p
 _lib.fcc_asp_tables.argtypes = [ctypes.c_int, ctypes.POINTER(_LevelTables)]
 for _f in ("fcc_dct_plan", "fcc_dct_forward", "fcc_dct_inverse", "fcc_dct_batched", "fcc_dct_destroy",
-           "fcc_asp_tables", "fcc_dct_time_launches"):
+           "fcc_asp_tables", "fcc_dct_time_launches", "fcc_dct_roundtrip_residual"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -142,6 +143,14 @@ def fcc_dct_time_launches(plan, x, out, direction, reps=10, stream=None):
     _check(_lib.fcc_dct_time_launches(plan.handle, _ptr(x), _ptr(out), int(direction), int(reps), ms, cnt.value,
                                       ctypes.byref(cnt), _stream(stream)), "fcc_dct_time_launches")
     return [float(v) for v in ms]
+
+
+def fcc_dct_roundtrip_residual(plan, x, y, stream=None):
+    """max|x - y| / max|x| computed in FP64 on the GPU (x, y shaped like the forward input)."""
+    r = ctypes.c_double(0.0)
+    _check(_lib.fcc_dct_roundtrip_residual(plan.handle, _ptr(x), _ptr(y), ctypes.byref(r), _stream(stream)),
+           "fcc_dct_roundtrip_residual")
+    return r.value
 
 
 def fcc_dct_destroy(plan):

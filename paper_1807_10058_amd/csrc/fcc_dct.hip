@@ -409,6 +409,41 @@ __global__ void k_copy1(VolSet vs) {
   }
 }
 
+// FP64 round-trip residual: out[0] = max |x - y|, out[1] = max |x| over
+// `count` elements (|.| of complex values for complex data).  out must be
+// zeroed first; maxima of non-negative doubles are combined through their bit
+// patterns (monotonic for non-negative IEEE values) with 64-bit atomic max.
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual(const T* __restrict__ x, const T* __restrict__ y, long long count,
+                                                  unsigned long long* out) {
+  double dmax = 0.0, xmax = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x) {
+    const cx<double> a = IO<T, double>::ld(x, i), b = IO<T, double>::ld(y, i);
+    const double dx = a.x - b.x, dy = a.y - b.y;
+    dmax = fmax(dmax, sqrt(dx * dx + dy * dy));
+    xmax = fmax(xmax, sqrt(a.x * a.x + a.y * a.y));
+  }
+  __shared__ double sd[256], sx[256];
+  sd[threadIdx.x] = dmax;
+  sx[threadIdx.x] = xmax;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + s]);
+      sx[threadIdx.x] = fmax(sx[threadIdx.x], sx[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicMax(&out[0], (unsigned long long)__double_as_longlong(sd[0]));
+    atomicMax(&out[1], (unsigned long long)__double_as_longlong(sx[0]));
+  }
+}
+
+__global__ void k_zero2(unsigned long long* p) {
+  if (threadIdx.x < 2) p[threadIdx.x] = 0ull;
+}
+
 // FP64 half phases of every level: level L, axis d, J_d -> exp(i pi (rst_d + J_d) / 2^L).
 __global__ void k_phase_table(double2* out, int D, double r0, double r1, double r2) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1124,6 +1159,7 @@ fcc_status fcc_dct_destroy(fcc_plan_t p) {
     }
   }
   dense_free(p);
+  if (p->resid) (void)hipFree(p->resid);
   if (p->hph) (void)hipFree(p->hph);
   for (void* w : p->ws)
     if (w) (void)hipFree(w);
@@ -1204,6 +1240,41 @@ fcc_status fcc_dct_time_launches(fcc_plan_t p, const void* in, void* out, int di
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
   return s;
+}
+
+fcc_status fcc_dct_roundtrip_residual(fcc_plan_t p, const void* x, const void* y, double* result,
+                                      void* hip_stream) {
+  if (!p || !x || !y || !result || !aligned16(x) || !aligned16(y)) return FCC_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  (void)hipGetLastError();
+  const long long N = (long long)p->n * p->n * p->n;
+  if (!p->resid) {
+    hipError_t ea = hipMalloc(reinterpret_cast<void**>(&p->resid), 2 * sizeof(unsigned long long));
+    if (ea != hipSuccess) return hip_fail(ea, "hipMalloc(residual)", __LINE__);
+  }
+  unsigned long long* d = p->resid;
+  hipError_t e = hipSuccess;
+  hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, st, d);
+  const unsigned blocks = unsigned(std::min<long long>((N + 255) / 256, 2048));
+  switch (in_type(p)) {
+    case DT::F32R: hipLaunchKernelGGL(k_residual<float>, dim3(blocks), dim3(256), 0, st, static_cast<const float*>(x), static_cast<const float*>(y), N, d); break;
+    case DT::F64R: hipLaunchKernelGGL(k_residual<double>, dim3(blocks), dim3(256), 0, st, static_cast<const double*>(x), static_cast<const double*>(y), N, d); break;
+    case DT::F32C: hipLaunchKernelGGL(k_residual<float2>, dim3(blocks), dim3(256), 0, st, static_cast<const float2*>(x), static_cast<const float2*>(y), N, d); break;
+    case DT::F64C: hipLaunchKernelGGL(k_residual<double2>, dim3(blocks), dim3(256), 0, st, static_cast<const double2*>(x), static_cast<const double2*>(y), N, d); break;
+  }
+  fcc_status s = launch_status("residual launch");
+  unsigned long long h[2] = {0ull, 0ull};
+  if (s == FCC_OK) {
+    e = hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) s = hip_fail(e, "residual copy", __LINE__);
+  }
+  if (s != FCC_OK) return s;
+  double dmax, xmax;
+  std::memcpy(&dmax, &h[0], 8);
+  std::memcpy(&xmax, &h[1], 8);
+  *result = xmax > 0.0 ? dmax / xmax : dmax;
+  return FCC_OK;
 }
 
 fcc_status fcc_dct_batched(const fcc_plan_t* plans, int count, const void* const* in, void* const* out,

@@ -32,6 +32,7 @@ struct fcc_plan_s {
   DenseOp dfwd, dinv;
   float* rowscale = nullptr;      // per-row input scales (FP16 split), rows_cap entries
   int rows_cap = 0;
+  unsigned long long* resid = nullptr;  // 2 words for fcc_dct_roundtrip_residual
 };
 
 namespace fcc {
