@@ -201,9 +201,7 @@ def batched(args, name):
     def run(variant):
         split = variant == "split"
         plans = [plan_for(n, fcc.FCC_PREC_SPLIT_BF16 if (split and n <= 8) else fcc.FCC_PREC_FP32) for n in ns]
-
-        def step():
-            fcc.fcc_dct_batched(plans, xs, outs, direction)
+        step = fcc.BatchedCall(plans, xs, outs, direction)
         t0 = time.perf_counter()
         step()  # records the graph
         torch.cuda.synchronize()

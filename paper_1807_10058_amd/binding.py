@@ -126,12 +126,25 @@ def fcc_dct_inverse(plan, X, x, stream=None):
     _check(_lib.fcc_dct_inverse(plan.handle, _ptr(X), _ptr(x), _stream(stream)), "fcc_dct_inverse")
 
 
+class BatchedCall:
+    """The arguments of one fcc_dct_batched call marshalled once, for repeated
+    calls (the library replays its recorded graph on every call)."""
+
+    def __init__(self, plans, ins, outs, direction):
+        self.cnt = len(plans)
+        self.plans = list(plans)  # keep the plans alive
+        self.P = (_vp * self.cnt)(*[p.handle for p in plans])
+        self.I = (_vp * self.cnt)(*[_ptr(t) for t in ins])
+        self.O = (_vp * self.cnt)(*[_ptr(t) for t in outs])
+        self.direction = int(direction)
+
+    def __call__(self, stream=None):
+        _check(_lib.fcc_dct_batched(self.P, self.cnt, self.I, self.O, self.direction, _stream(stream)),
+               "fcc_dct_batched")
+
+
 def fcc_dct_batched(plans, ins, outs, direction, stream=None):
-    cnt = len(plans)
-    P = (_vp * cnt)(*[p.handle for p in plans])
-    I = (_vp * cnt)(*[_ptr(t) for t in ins])
-    O = (_vp * cnt)(*[_ptr(t) for t in outs])
-    _check(_lib.fcc_dct_batched(P, cnt, I, O, int(direction), _stream(stream)), "fcc_dct_batched")
+    BatchedCall(plans, ins, outs, direction)(stream)
 
 
 def fcc_dct_time_launches(plan, x, out, direction, reps=10, stream=None):

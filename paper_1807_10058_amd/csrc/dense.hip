@@ -309,8 +309,10 @@ fcc_status dense_prepare(fcc_plan_s* p, hipStream_t st) {
   double2* E = nullptr;
   double2* Finv = nullptr;
   double2* scratch = nullptr;
+  void** parr = nullptr;
   fcc_status s = FCC_OK;
   auto fail = [&](fcc_status e) {
+    if (parr) (void)hipFree(parr);
     if (F) (void)hipFree(F);
     if (E) (void)hipFree(E);
     if (Finv) (void)hipFree(Finv);
@@ -337,23 +339,22 @@ fcc_status dense_prepare(fcc_plan_s* p, hipStream_t st) {
     sub.stages64 = true;
     sub.lv = p->lv;
     sub.hph = p->hph;
-    const int chunk = std::min<long long>(kMaxVol, N);
-    if (hipMalloc(&E, sizeof(double2) * N * chunk) != hipSuccess) return fail(FCC_ERR_OOM);
-    if (hipMalloc(&scratch, sizeof(double2) * N * chunk * 2) != hipSuccess) return fail(FCC_ERR_OOM);
-    std::vector<const void*> in(chunk);
-    std::vector<void*> out(chunk), w0(chunk), w1(chunk);
-    for (long long j0 = 0; j0 < N; j0 += chunk) {
-      const int cnt = int(std::min<long long>(chunk, N - j0));
-      hipLaunchKernelGGL(k_unit_vectors, dim3(unsigned((N * cnt + 255) / 256)), dim3(256), 0, st, E, N, j0, cnt);
-      for (int v = 0; v < cnt; ++v) {
-        in[v] = E + N * v;
-        out[v] = Finv + N * (j0 + v);  // column j0+v of F^{-1}, stored contiguously
-        w0[v] = scratch + N * (2 * v);
-        w1[v] = scratch + N * (2 * v + 1);
-      }
-      s = enqueue_inverse_ext(&sub, cnt, in.data(), out.data(), w0.data(), w1.data(), st);
-      if (s != FCC_OK) return fail(s);
+    // all N unit vectors in one launch sequence; pointer arrays on the device
+    if (hipMalloc(&E, sizeof(double2) * N * N) != hipSuccess) return fail(FCC_ERR_OOM);
+    if (hipMalloc(&scratch, sizeof(double2) * N * N * 2) != hipSuccess) return fail(FCC_ERR_OOM);
+    hipLaunchKernelGGL(k_unit_vectors, dim3(unsigned((N * N + 255) / 256)), dim3(256), 0, st, E, N, 0LL, int(N));
+    std::vector<void*> ptr(size_t(4) * N);
+    for (long long v = 0; v < N; ++v) {
+      ptr[v] = E + N * v;
+      ptr[N + v] = Finv + N * v;  // column v of F^{-1}, stored contiguously
+      ptr[2 * N + v] = scratch + N * (2 * v);
+      ptr[3 * N + v] = scratch + N * (2 * v + 1);
     }
+    if (hipMalloc(&parr, sizeof(void*) * ptr.size()) != hipSuccess) return fail(FCC_ERR_OOM);
+    if (hipMemcpy(parr, ptr.data(), sizeof(void*) * ptr.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(FCC_ERR_HIP);
+    s = enqueue_inverse_arrays(&sub, int(N), parr, parr + N, parr + 2 * N, parr + 3 * N, st);
+    if (s != FCC_OK) return fail(s);
   }
   if (hipStreamSynchronize(st) != hipSuccess) return fail(FCC_ERR_HIP);
   std::vector<double2> hF(N * N), hFi(N * N);

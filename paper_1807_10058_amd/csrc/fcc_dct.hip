@@ -294,15 +294,16 @@ __device__ __forceinline__ cx<R> gather_row(const TI* __restrict__ in, int n, in
 #define FCC_ROW_UNROLL 8
 #endif
 template <typename R, typename TI, typename TO>
-__global__ __launch_bounds__(256) FCC_FWD_ATTR void k_fwd_level(VolSet vs, int n, int L, DevLevel lv,
+__global__ __launch_bounds__(256) FCC_FWD_ATTR void k_fwd_level(VolSet vs, int nvol, int n, int L, DevLevel lv,
                                                    const double2* __restrict__ hph) {
   __shared__ double sp[kMaxPoly * kNumMono];
   load_polys(lv, sp);
-  const long long h = n >> 1;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= h * h * h) return;
-  const TI* __restrict__ in = static_cast<const TI*>(vs.in[blockIdx.y]);
-  TO* __restrict__ out = static_cast<TO*>(vs.out[blockIdx.y]);
+  const long long h = n >> 1, cubes = h * h * h;
+  const long long tg = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tg >= cubes * nvol) return;
+  const long long vol = tg / cubes, t = tg - vol * cubes;
+  const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, vol));
+  TO* __restrict__ out = static_cast<TO*>(vol_ptr(vs.out, vol));
   int cube;
   CubeIdx ci = cube_of(t, n, L, &cube);
   cx<R> mono[kNumMono];
@@ -333,13 +334,14 @@ __global__ __launch_bounds__(256) FCC_FWD_ATTR void k_fwd_level(VolSet vs, int n
 #define FCC_INV_ATTR
 #endif
 template <typename R, typename TI>
-__global__ __launch_bounds__(256) FCC_INV_ATTR void k_inv_dct2(VolSet vs, int n, int L, const double2* __restrict__ hph) {
-  const long long h = n >> 1;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= h * h * h) return;
+__global__ __launch_bounds__(256) FCC_INV_ATTR void k_inv_dct2(VolSet vs, int nvol, int n, int L, const double2* __restrict__ hph) {
+  const long long h = n >> 1, cubes = h * h * h;
+  const long long tg = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tg >= cubes * nvol) return;
+  const long long vol = tg / cubes, t = tg - vol * cubes;
   // may run in place (in == out): each thread reads and writes only its own cube
-  const TI* in = static_cast<const TI*>(vs.in[blockIdx.y]);
-  cx<R>* out = static_cast<cx<R>*>(vs.out[blockIdx.y]);
+  const TI* in = static_cast<const TI*>(vol_ptr(vs.in, vol));
+  cx<R>* out = static_cast<cx<R>*>(vol_ptr(vs.out, vol));
   int cube;
   CubeIdx ci = cube_of(t, n, L, &cube);
   cx<R> z[8];
@@ -374,15 +376,16 @@ __global__ __launch_bounds__(256) FCC_INV_ATTR void k_inv_dct2(VolSet vs, int n,
 
 // Inverse level L, second pass: x(kappa) = sum C_nl(phi)[kappa, (def,abc)] y(def + 2 abc).
 template <typename R, typename TO>
-__global__ __launch_bounds__(256) void k_inv_basis(VolSet vs, int n, int L, DevLevel lv,
+__global__ __launch_bounds__(256) void k_inv_basis(VolSet vs, int nvol, int n, int L, DevLevel lv,
                                                    const double2* __restrict__ hph) {
   __shared__ double sp[kMaxPoly * kNumMono];
   load_polys(lv, sp);
-  const long long h = n >> 1;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= h * h * h) return;
-  const cx<R>* __restrict__ in = static_cast<const cx<R>*>(vs.in[blockIdx.y]);
-  TO* __restrict__ out = static_cast<TO*>(vs.out[blockIdx.y]);
+  const long long h = n >> 1, cubes = h * h * h;
+  const long long tg = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tg >= cubes * nvol) return;
+  const long long vol = tg / cubes, t = tg - vol * cubes;
+  const cx<R>* __restrict__ in = static_cast<const cx<R>*>(vol_ptr(vs.in, vol));
+  TO* __restrict__ out = static_cast<TO*>(vol_ptr(vs.out, vol));
   int cube;
   CubeIdx ci = cube_of(t, n, L, &cube);
   cx<R> mono[kNumMono];
@@ -402,10 +405,11 @@ __global__ __launch_bounds__(256) void k_inv_basis(VolSet vs, int n, int L, DevL
 
 // n = 1: the transform is the 1x1 matrix [T_0] = [1].
 template <typename TI, typename TO>
-__global__ void k_copy1(VolSet vs) {
-  if (threadIdx.x == 0) {
-    cx<double> v = IO<TI, double>::ld(static_cast<const TI*>(vs.in[blockIdx.y]), 0);
-    IO<TO, double>::st(static_cast<TO*>(vs.out[blockIdx.y]), 0, v);
+__global__ void k_copy1(VolSet vs, int nvol) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < nvol) {
+    cx<double> x = IO<TI, double>::ld(static_cast<const TI*>(vol_ptr(vs.in, v)), 0);
+    IO<TO, double>::st(static_cast<TO*>(vol_ptr(vs.out, v)), 0, x);
   }
 }
 
@@ -683,13 +687,13 @@ constexpr int kBlock = 256;
 
 dim3 grid_for(int n, int nvol) {
   long long h = n >> 1;
-  long long cubes = h * h * h;
-  return dim3((unsigned)((cubes + kBlock - 1) / kBlock), (unsigned)nvol, 1);
+  long long threads = h * h * h * nvol;
+  return dim3((unsigned)((threads + kBlock - 1) / kBlock), 1, 1);
 }
 
 template <typename R, typename TI, typename TO>
 void launch_fwd(const fcc_plan_s* p, int L, const VolSet& vs, int nvol, hipStream_t st) {
-  hipLaunchKernelGGL((k_fwd_level<R, TI, TO>), grid_for(p->n, nvol), dim3(kBlock), 0, st, vs, p->n, L, p->lv[L],
+  hipLaunchKernelGGL((k_fwd_level<R, TI, TO>), grid_for(p->n, nvol), dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L],
                      p->hph + 3 * ((1 << L) - 1));
 }
 
@@ -715,25 +719,25 @@ template <typename R>
 void inv_dct2_dispatch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, int nvol, hipStream_t st) {
   const double2* h = p->hph + 3 * ((1 << L) - 1);
   if (ti == DT::F32C)
-    hipLaunchKernelGGL((k_inv_dct2<R, float2>), grid_for(p->n, nvol), dim3(kBlock), 0, st, vs, p->n, L, h);
+    hipLaunchKernelGGL((k_inv_dct2<R, float2>), grid_for(p->n, nvol), dim3(kBlock), 0, st, vs, nvol, p->n, L, h);
   else
-    hipLaunchKernelGGL((k_inv_dct2<R, double2>), grid_for(p->n, nvol), dim3(kBlock), 0, st, vs, p->n, L, h);
+    hipLaunchKernelGGL((k_inv_dct2<R, double2>), grid_for(p->n, nvol), dim3(kBlock), 0, st, vs, nvol, p->n, L, h);
 }
 template <typename R>
 void inv_basis_dispatch(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int nvol, hipStream_t st) {
   const double2* h = p->hph + 3 * ((1 << L) - 1);
   dim3 g = grid_for(p->n, nvol);
   switch (to) {
-    case DT::F32R: hipLaunchKernelGGL((k_inv_basis<R, float>), g, dim3(kBlock), 0, st, vs, p->n, L, p->lv[L], h); break;
-    case DT::F64R: hipLaunchKernelGGL((k_inv_basis<R, double>), g, dim3(kBlock), 0, st, vs, p->n, L, p->lv[L], h); break;
-    case DT::F32C: hipLaunchKernelGGL((k_inv_basis<R, float2>), g, dim3(kBlock), 0, st, vs, p->n, L, p->lv[L], h); break;
-    case DT::F64C: hipLaunchKernelGGL((k_inv_basis<R, double2>), g, dim3(kBlock), 0, st, vs, p->n, L, p->lv[L], h); break;
+    case DT::F32R: hipLaunchKernelGGL((k_inv_basis<R, float>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h); break;
+    case DT::F64R: hipLaunchKernelGGL((k_inv_basis<R, double>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h); break;
+    case DT::F32C: hipLaunchKernelGGL((k_inv_basis<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h); break;
+    case DT::F64C: hipLaunchKernelGGL((k_inv_basis<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h); break;
   }
 }
 
 template <typename TI, typename TO>
 void launch_copy1(const VolSet& vs, int nvol, hipStream_t st) {
-  hipLaunchKernelGGL((k_copy1<TI, TO>), dim3(1, nvol), dim3(64), 0, st, vs);
+  hipLaunchKernelGGL((k_copy1<TI, TO>), dim3(unsigned((nvol + 63) / 64)), dim3(64), 0, st, vs, nvol);
 }
 void copy1_dispatch(DT ti, DT to, const VolSet& vs, int nvol, hipStream_t st) {
   auto go = [&](auto tag_in) {
@@ -764,100 +768,77 @@ struct LaunchTimer {
 };
 
 // Enqueue the forward transform of nvol volumes that share plan p.
-// ws0/ws1[v]: two scratch arrays of n^3 stage-precision complex per volume.
-fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, const void* const* in, void* const* out,
-                           void* const* ws0, void* const* ws1, hipStream_t st, LaunchTimer* tm = nullptr) {
-  VolSet vs;
+// ws0/ws1: two scratch arrays of n^3 stage-precision complex per volume.
+fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0, VolPtrs ws1,
+                           hipStream_t st, LaunchTimer* tm = nullptr) {
   if (tm) tm->mark(st);
   if (p->n == 1) {
-    for (int v = 0; v < nvol; ++v) {
-      vs.in[v] = in[v];
-      vs.out[v] = out[v];
-    }
-    copy1_dispatch(in_type(p), cplx_type(p), vs, nvol, st);
+    copy1_dispatch(in_type(p), cplx_type(p), VolSet{in, out}, nvol, st);
     return launch_status("forward n=1 launch");
   }
-  const void* const* src = in;
+  VolPtrs src = in;
   for (int L = 0; L < p->D; ++L) {
     bool last = L == p->D - 1;
-    void* const* dst = last ? out : ((L & 1) ? ws1 : ws0);
-    for (int v = 0; v < nvol; ++v) {
-      vs.in[v] = src[v];
-      vs.out[v] = dst[v];
-    }
+    VolPtrs dst = last ? out : ((L & 1) ? ws1 : ws0);
     DT ti = L == 0 ? in_type(p) : buf_type(p, L);
     DT to = last ? cplx_type(p) : buf_type(p, L + 1);
     if (arith64(p, L))
-      fwd_dispatch<double>(p, L, ti, to, vs, nvol, st);
+      fwd_dispatch<double>(p, L, ti, to, VolSet{src, dst}, nvol, st);
     else
-      fwd_dispatch<float>(p, L, ti, to, vs, nvol, st);
+      fwd_dispatch<float>(p, L, ti, to, VolSet{src, dst}, nvol, st);
     if (tm) tm->mark(st);
-    src = reinterpret_cast<const void* const*>(dst);
+    src = dst;
   }
   return launch_status("forward level launch");
 }
 
-fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, const void* const* in, void* const* out,
-                           void* const* ws0, void* const* ws1, hipStream_t st, LaunchTimer* tm = nullptr) {
-  VolSet vs;
+fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0, VolPtrs ws1,
+                           hipStream_t st, LaunchTimer* tm = nullptr) {
   if (tm) tm->mark(st);
   DT real_or_cplx = (p->flags & FCC_REAL_INPUT) ? in_type(p) : cplx_type(p);
   if (p->n == 1) {
-    for (int v = 0; v < nvol; ++v) {
-      vs.in[v] = in[v];
-      vs.out[v] = out[v];
-    }
-    copy1_dispatch(cplx_type(p), real_or_cplx, vs, nvol, st);
+    copy1_dispatch(cplx_type(p), real_or_cplx, VolSet{in, out}, nvol, st);
     return launch_status("inverse n=1 launch");
   }
-  const void* const* cur = in;
+  VolPtrs cur = in;
   bool cur_is_user = true;
   int which = 0;  // scratch array holding the current level's data
   for (int L = p->D - 1; L >= 0; --L) {
-    void* const* a = which ? ws1 : ws0;
-    void* const* b = which ? ws0 : ws1;
-    for (int v = 0; v < nvol; ++v) {
-      vs.in[v] = cur[v];
-      vs.out[v] = a[v];
-    }
+    VolPtrs a = which ? ws1 : ws0;
+    VolPtrs b = which ? ws0 : ws1;
     // the DCT_2^{-1} pass reads level L+1's result (or the user's X) and
     // writes level L's cube values in level L's arithmetic type
     DT ti = cur_is_user ? cplx_type(p) : buf_type(p, L + 1);
     if (arith64(p, L))
-      inv_dct2_dispatch<double>(p, L, ti, vs, nvol, st);
+      inv_dct2_dispatch<double>(p, L, ti, VolSet{cur, a}, nvol, st);
     else
-      inv_dct2_dispatch<float>(p, L, ti, vs, nvol, st);
+      inv_dct2_dispatch<float>(p, L, ti, VolSet{cur, a}, nvol, st);
     if (tm) tm->mark(st);
-    void* const* dst = L == 0 ? out : b;
-    for (int v = 0; v < nvol; ++v) {
-      vs.in[v] = a[v];
-      vs.out[v] = dst[v];
-    }
+    VolPtrs dst = L == 0 ? out : b;
     DT to = L == 0 ? real_or_cplx : buf_type(p, L);
     if (arith64(p, L))
-      inv_basis_dispatch<double>(p, L, to, vs, nvol, st);
+      inv_basis_dispatch<double>(p, L, to, VolSet{a, dst}, nvol, st);
     else
-      inv_basis_dispatch<float>(p, L, to, vs, nvol, st);
+      inv_basis_dispatch<float>(p, L, to, VolSet{a, dst}, nvol, st);
     if (tm) tm->mark(st);
-    cur = reinterpret_cast<const void* const*>(b);
+    cur = b;
     cur_is_user = false;
     which ^= 1;
   }
   return launch_status("inverse level launch");
 }
 
+VolPtrs one_vol(const void* p) { return VolPtrs{nullptr, const_cast<void*>(p)}; }
+VolPtrs many_vol(void* const* dev_arr) { return VolPtrs{dev_arr, nullptr}; }
+
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 }  // namespace
 
 namespace fcc {
-fcc_status enqueue_forward_ext(const fcc_plan_s* p, int nvol, const void* const* in, void* const* out,
-                               void* const* ws0, void* const* ws1, hipStream_t st) {
-  return enqueue_forward(p, nvol, in, out, ws0, ws1, st);
-}
-fcc_status enqueue_inverse_ext(const fcc_plan_s* p, int nvol, const void* const* in, void* const* out,
-                               void* const* ws0, void* const* ws1, hipStream_t st) {
-  return enqueue_inverse(p, nvol, in, out, ws0, ws1, st);
+fcc_status enqueue_inverse_arrays(const fcc_plan_s* p, int nvol, void* const* in_dev, void* const* out_dev,
+                                  void* const* ws0_dev, void* const* ws1_dev, hipStream_t st) {
+  return enqueue_inverse(p, nvol, many_vol(in_dev), many_vol(out_dev), many_vol(ws0_dev), many_vol(ws1_dev), st);
 }
 }  // namespace fcc
 
@@ -901,8 +882,8 @@ bool same_config(const fcc_plan_s* a, const fcc_plan_s* b) {
 // Resources of one group, allocated before capture (no allocation or
 // synchronous copy may happen while a stream is being captured).
 struct GroupRes {
-  void** rows = nullptr;   // dense: device row pointers (in, out) and scales
-  float* scale = nullptr;
+  void** rows = nullptr;   // device pointer arrays: in, out, scratch 0, scratch 1 (cnt each)
+  float* scale = nullptr;  // dense FP16: per-row scales
   void* ws = nullptr;      // fast path: per-volume scratch pairs
   size_t wb = 0;
 };
@@ -910,63 +891,51 @@ struct GroupRes {
 fcc_status prepare_group(BatchExec* bx, const BatchGroup& g, const void* const* in, void* const* out, GroupRes* r) {
   const fcc_plan_s* p = g.p;
   const int cnt = int(g.vols.size());
-  if (p->dense) {
-    std::vector<const void*> ri(cnt), ro(cnt);
-    for (int v = 0; v < cnt; ++v) {
-      ri[v] = in[g.vols[v]];
-      ro[v] = out[g.vols[v]];
-    }
-    void* d = nullptr;
-    if (hipMalloc(&d, sizeof(void*) * 2 * cnt + sizeof(float) * cnt) != hipSuccess) return FCC_ERR_OOM;
-    bx->allocations.push_back(d);
-    r->rows = static_cast<void**>(d);
-    if (hipMemcpy(r->rows, ri.data(), sizeof(void*) * cnt, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(r->rows + cnt, ro.data(), sizeof(void*) * cnt, hipMemcpyHostToDevice) != hipSuccess)
-      return FCC_ERR_HIP;
-    r->scale = reinterpret_cast<float*>(r->rows + 2 * cnt);
-    return FCC_OK;
+  const bool scratch = !p->dense && p->n > 1;
+  if (scratch) {
+    const size_t N = size_t(p->n) * p->n * p->n;
+    r->wb = N * (p->stages64 ? sizeof(double2) : sizeof(float2));
+    if (hipMalloc(&r->ws, r->wb * 2 * cnt) != hipSuccess) return FCC_ERR_OOM;
+    bx->allocations.push_back(r->ws);
   }
-  if (p->n == 1 || p->D == 0) return FCC_OK;
-  const size_t N = size_t(p->n) * p->n * p->n;
-  r->wb = N * (p->stages64 ? sizeof(double2) : sizeof(float2));
-  if (hipMalloc(&r->ws, r->wb * 2 * cnt) != hipSuccess) return FCC_ERR_OOM;
-  bx->allocations.push_back(r->ws);
+  std::vector<void*> ptr(size_t(4) * cnt, nullptr);
+  for (int v = 0; v < cnt; ++v) {
+    ptr[v] = const_cast<void*>(in[g.vols[v]]);
+    ptr[cnt + v] = out[g.vols[v]];
+    if (scratch) {
+      ptr[2 * cnt + v] = static_cast<char*>(r->ws) + r->wb * (2 * size_t(v));
+      ptr[3 * cnt + v] = static_cast<char*>(r->ws) + r->wb * (2 * size_t(v) + 1);
+    }
+  }
+  void* d = nullptr;
+  if (hipMalloc(&d, sizeof(void*) * ptr.size() + sizeof(float) * cnt) != hipSuccess) return FCC_ERR_OOM;
+  bx->allocations.push_back(d);
+  r->rows = static_cast<void**>(d);
+  r->scale = reinterpret_cast<float*>(r->rows + ptr.size());
+  if (hipMemcpy(r->rows, ptr.data(), sizeof(void*) * ptr.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return FCC_ERR_HIP;
   return FCC_OK;
 }
 
-fcc_status record_group(const BatchGroup& g, const GroupRes& r, const void* const* in, void* const* out, int dir,
-                        hipStream_t st) {
+fcc_status record_group(const BatchGroup& g, const GroupRes& r, int dir, hipStream_t st) {
   const fcc_plan_s* p = g.p;
   const int cnt = int(g.vols.size());
+  void** in = r.rows;
+  void** out = r.rows + cnt;
+  void** w0 = r.rows + 2 * cnt;
+  void** w1 = r.rows + 3 * cnt;
   if (p->dense) {
-    void** dp = r.rows;
     fcc_status s = FCC_OK;
-    if (dir >= 0) s = dense_run(p, p->dfwd, cnt, dp, dp + cnt, nullptr, nullptr, r.scale, st);
-    if (s == FCC_OK && dir == 0) s = dense_run(p, p->dinv, cnt, dp + cnt, dp, nullptr, nullptr, r.scale, st);
-    if (s == FCC_OK && dir < 0) s = dense_run(p, p->dinv, cnt, dp, dp + cnt, nullptr, nullptr, r.scale, st);
+    if (dir >= 0) s = dense_run(p, p->dfwd, cnt, in, out, nullptr, nullptr, r.scale, st);
+    if (s == FCC_OK && dir == 0) s = dense_run(p, p->dinv, cnt, out, in, nullptr, nullptr, r.scale, st);
+    if (s == FCC_OK && dir < 0) s = dense_run(p, p->dinv, cnt, in, out, nullptr, nullptr, r.scale, st);
     return s;
   }
-  for (int c0 = 0; c0 < cnt; c0 += kMaxVol) {
-    const int c = std::min(kMaxVol, cnt - c0);
-    std::vector<const void*> ii(c);
-    std::vector<void*> oo(c), iw(c), w0(c, nullptr), w1(c, nullptr);
-    for (int v = 0; v < c; ++v) {
-      ii[v] = in[g.vols[c0 + v]];
-      iw[v] = const_cast<void*>(in[g.vols[c0 + v]]);  // round trip writes back into in[]
-      oo[v] = out[g.vols[c0 + v]];
-      if (r.ws) {
-        w0[v] = static_cast<char*>(r.ws) + r.wb * (2 * size_t(c0 + v));
-        w1[v] = static_cast<char*>(r.ws) + r.wb * (2 * size_t(c0 + v) + 1);
-      }
-    }
-    fcc_status s = FCC_OK;
-    if (dir >= 0) s = enqueue_forward(p, c, ii.data(), oo.data(), w0.data(), w1.data(), st);
-    if (s == FCC_OK && dir == 0)
-      s = enqueue_inverse(p, c, reinterpret_cast<const void* const*>(oo.data()), iw.data(), w0.data(), w1.data(), st);
-    if (s == FCC_OK && dir < 0) s = enqueue_inverse(p, c, ii.data(), oo.data(), w0.data(), w1.data(), st);
-    if (s != FCC_OK) return s;
-  }
-  return FCC_OK;
+  fcc_status s = FCC_OK;
+  if (dir >= 0) s = enqueue_forward(p, cnt, many_vol(in), many_vol(out), many_vol(w0), many_vol(w1), st);
+  if (s == FCC_OK && dir == 0) s = enqueue_inverse(p, cnt, many_vol(out), many_vol(in), many_vol(w0), many_vol(w1), st);
+  if (s == FCC_OK && dir < 0) s = enqueue_inverse(p, cnt, many_vol(in), many_vol(out), many_vol(w0), many_vol(w1), st);
+  return s;
 }
 
 fcc_status build_batch(BatchExec* bx, const fcc_plan_t* plans, int count, const void* const* in, void* const* out,
@@ -1002,7 +971,7 @@ fcc_status build_batch(BatchExec* bx, const fcc_plan_t* plans, int count, const 
     (void)hipStreamDestroy(cap);
     return FCC_ERR_HIP;
   }
-  for (size_t gi = 0; gi < groups.size() && s == FCC_OK; ++gi) s = record_group(groups[gi], res[gi], in, out, dir, cap);
+  for (size_t gi = 0; gi < groups.size() && s == FCC_OK; ++gi) s = record_group(groups[gi], res[gi], dir, cap);
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(cap, &graph);
   (void)hipStreamDestroy(cap);
@@ -1173,9 +1142,8 @@ fcc_status fcc_dct_forward(fcc_plan_t p, const void* x, void* X, void* hip_strea
   (void)hipGetLastError();
   if (p->dense)
     return dense_run(p, p->dfwd, 1, nullptr, nullptr, x, X, p->rowscale, static_cast<hipStream_t>(hip_stream));
-  void* w0 = p->ws[0];
-  void* w1 = p->ws[1];
-  return enqueue_forward(p, 1, &x, &X, &w0, &w1, static_cast<hipStream_t>(hip_stream));
+  return enqueue_forward(p, 1, one_vol(x), one_vol(X), one_vol(p->ws[0]), one_vol(p->ws[1]),
+                         static_cast<hipStream_t>(hip_stream));
 }
 
 fcc_status fcc_dct_inverse(fcc_plan_t p, const void* X, void* x, void* hip_stream) {
@@ -1184,9 +1152,8 @@ fcc_status fcc_dct_inverse(fcc_plan_t p, const void* X, void* x, void* hip_strea
   (void)hipGetLastError();
   if (p->dense)
     return dense_run(p, p->dinv, 1, nullptr, nullptr, X, x, p->rowscale, static_cast<hipStream_t>(hip_stream));
-  void* w0 = p->ws[0];
-  void* w1 = p->ws[1];
-  return enqueue_inverse(p, 1, &X, &x, &w0, &w1, static_cast<hipStream_t>(hip_stream));
+  return enqueue_inverse(p, 1, one_vol(X), one_vol(x), one_vol(p->ws[0]), one_vol(p->ws[1]),
+                         static_cast<hipStream_t>(hip_stream));
 }
 
 fcc_status fcc_dct_time_launches(fcc_plan_t p, const void* in, void* out, int direction, int reps, float* ms,
@@ -1207,8 +1174,6 @@ fcc_status fcc_dct_time_launches(fcc_plan_t p, const void* in, void* out, int di
       break;
     }
   }
-  void* w0 = p->ws[0];
-  void* w1 = p->ws[1];
   for (int r = 0; r < reps && s == FCC_OK; ++r) {
     std::vector<hipEvent_t> sub(ev.begin() + size_t(r) * (slots + 1), ev.begin() + size_t(r + 1) * (slots + 1));
     LaunchTimer tm;
@@ -1219,8 +1184,8 @@ fcc_status fcc_dct_time_launches(fcc_plan_t p, const void* in, void* out, int di
       tm.mark(st);
       continue;
     }
-    s = direction > 0 ? enqueue_forward(p, 1, &in, &out, &w0, &w1, st, &tm)
-                      : enqueue_inverse(p, 1, &in, &out, &w0, &w1, st, &tm);
+    s = direction > 0 ? enqueue_forward(p, 1, one_vol(in), one_vol(out), one_vol(p->ws[0]), one_vol(p->ws[1]), st, &tm)
+                      : enqueue_inverse(p, 1, one_vol(in), one_vol(out), one_vol(p->ws[0]), one_vol(p->ws[1]), st, &tm);
     if (p->n == 1 && s == FCC_OK) (void)hipEventRecord(sub[1], st);
   }
   if (s == FCC_OK) {

@@ -114,11 +114,15 @@ struct DevLevel {
   int S;               // cubes per slice
 };
 
-constexpr int kMaxVol = 120;
-// Pointers of up to kMaxVol volumes that share one launch (passed by value).
+// Where the volumes of one launch live: one volume at `one` (arr == nullptr)
+// or one pointer per volume in the device array `arr`.
+struct VolPtrs {
+  void* const* arr;
+  void* one;
+};
+__device__ __forceinline__ void* vol_ptr(const VolPtrs& p, long long v) { return p.arr ? p.arr[v] : p.one; }
 struct VolSet {
-  const void* in[kMaxVol];
-  void* out[kMaxVol];
+  VolPtrs in, out;
 };
 
 }  // namespace fcc

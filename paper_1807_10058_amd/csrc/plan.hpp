@@ -42,9 +42,8 @@ fcc_status dense_run(const fcc_plan_s* p, const DenseOp& op, int M, const void* 
                      void* const* out_rows_dev, const void* in_base, void* out_base, float* rowscale,
                      hipStream_t st);
 void dense_free(fcc_plan_s* p);
-// fcc_dct.hip: the level-by-level fast path for nvol volumes of plan p
-fcc_status enqueue_forward_ext(const fcc_plan_s* p, int nvol, const void* const* in, void* const* out,
-                               void* const* ws0, void* const* ws1, hipStream_t st);
-fcc_status enqueue_inverse_ext(const fcc_plan_s* p, int nvol, const void* const* in, void* const* out,
-                               void* const* ws0, void* const* ws1, hipStream_t st);
+// fcc_dct.hip: the level-by-level fast inverse for nvol volumes of plan p,
+// with device arrays of per-volume pointers
+fcc_status enqueue_inverse_arrays(const fcc_plan_s* p, int nvol, void* const* in_dev, void* const* out_dev,
+                                  void* const* ws0_dev, void* const* ws1_dev, hipStream_t st);
 }  // namespace fcc
