@@ -55,7 +55,8 @@ def launch_bytes(n, prec, stages64, real_in, direction):
         for L in range(D):
             bi = (io_r if real_in else io_c) if L == 0 else st
             bo = io_c if L == D - 1 else st
-            out.append(("k_fwd_level L%d" % L, N * (bi + bo)))
+            out.append(("k_fwd_gather L%d" % L, N * (bi + st)))
+            out.append(("k_fwd_dct2 L%d" % L, N * (st + bo)))
     else:
         for k, L in enumerate(range(D - 1, -1, -1)):
             bi = io_c if k == 0 else st

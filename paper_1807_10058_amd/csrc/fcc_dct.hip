@@ -286,55 +286,155 @@ __device__ __forceinline__ cx<R> gather_row(const TI* __restrict__ in, int n, in
 // Kernels
 // ---------------------------------------------------------------------------
 
-// Forward level L: basis change B_nl(phi) then DCT_2(phi) (x) I on every cube.
-#ifndef FCC_FWD_ATTR
-#define FCC_FWD_ATTR
-#endif
-#ifndef FCC_ROW_UNROLL
-#define FCC_ROW_UNROLL 8
-#endif
-template <typename R, typename TI, typename TO>
-__global__ __launch_bounds__(256) FCC_FWD_ATTR void k_fwd_level(VolSet vs, int nvol, int n, int L, DevLevel lv,
-                                                   const double2* __restrict__ hph) {
+// Per-node constants of one level, precomputed in FP64 at plan time for the
+// levels with few nodes (every cube of such a node reuses them).
+// (A's blocks are stored, not their inverses: the inverse pass solves with
+// partial pivoting per cube, which stays accurate where A is ill conditioned;
+// applying a precomputed inverse raised the n = 256 round-trip error 1e4-fold.)
+struct NodeConst {
+  double2 a4[16], a3[9];   // blocks of A(phi)
+  double2 mono[kNumMono];  // {1, c3, c1, c2, c1 c3} of c = (sigma, tau, rho)(phi)
+};
+constexpr long long kNodeTableMax = 1 << 15;  // levels with at most this many nodes get a table
+
+__global__ void k_node_table(NodeConst* out, int L, const double2* __restrict__ hph) {
+  const long long node = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= (1LL << (3 * L))) return;
+  const int mask = (1 << L) - 1;
+  const int J[3] = {int(node >> (2 * L)), int((node >> L) & mask), int(node & mask)};
+  cx<double> Q[3][3];
+  node_pos_powers(hph, L, J, Q);
+  cx<double> a4[4][4], a3[3][3];
+  build_A(Q, a4, a3);
+  NodeConst& nc = out[node];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) nc.a4[4 * i + j] = make_double2(a4[i][j].x, a4[i][j].y);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) nc.a3[3 * i + j] = make_double2(a3[i][j].x, a3[i][j].y);
+  cx<double> P[3][7], mono[kNumMono];
+  node_powers(hph, L, J, P);
+  node_monomials(P, mono);
+  for (int q = 0; q < kNumMono; ++q) nc.mono[q] = make_double2(mono[q].x, mono[q].y);
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> ldc(const double2& v) {
+  return {R(v.x), R(v.y)};
+}
+
+// Thread t (within one volume) -> one row of the level's gather: node J (the
+// 8^L nodes vary fastest), then cube, then f.  At level 0 (1) a wavefront
+// covers 64 (8) consecutive cubes of one f = one table slice; from level 2 on
+// it covers 64 nodes of one row.
+struct RowIdx {
+  int J[3], a[3], cube, f;
+};
+__device__ __forceinline__ RowIdx row_of(long long t, int n, int L) {
+  const int mask = (1 << L) - 1;
+  const int jf = int(t & ((1LL << (3 * L)) - 1));
+  const long long rest = t >> (3 * L);
+  const int m = (n >> L) >> 1;
+  const long long cubes = (long long)m * m * m;
+  RowIdx r;
+  r.f = int(rest / cubes);
+  r.cube = int(rest - (long long)r.f * cubes);
+  r.J[0] = jf >> (2 * L);
+  r.J[1] = (jf >> L) & mask;
+  r.J[2] = jf & mask;
+  r.a[0] = r.cube / (m * m);
+  r.a[1] = (r.cube / m) % m;
+  r.a[2] = r.cube % m;
+  return r;
+}
+
+template <typename R>
+__device__ __forceinline__ void load_mono(const NodeConst* nodes, const double2* __restrict__ hph, int L,
+                                          const int J[3], cx<R> mono[kNumMono]) {
+  if (nodes) {
+    const NodeConst& nc = nodes[((long long)J[0] << (2 * L)) | ((long long)J[1] << L) | J[2]];
+#pragma unroll
+    for (int q = 0; q < kNumMono; ++q) mono[q] = ldc<R>(nc.mono[q]);
+  } else {
+    cx<R> P[3][7];
+    node_powers(hph, L, J, P);
+    node_monomials(P, mono);
+  }
+}
+
+// Forward level L, first pass: y(def, abc) = row (def,abc) of B_nl(c) applied to
+// the node, one thread per row, stored at node-local position def + 2 abc.
+template <typename R, typename TI>
+__global__ __launch_bounds__(256) void k_fwd_gather(VolSet vs, int nvol, int n, int L, DevLevel lv,
+                                                    const double2* __restrict__ hph, const NodeConst* nodes) {
   __shared__ double sp[kMaxPoly * kNumMono];
   load_polys(lv, sp);
+  const long long N = (long long)n * n * n;
+  const long long tg = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tg >= N * nvol) return;
+  const long long vol = tg / N, t = tg - vol * N;
+  const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, vol));
+  cx<R>* __restrict__ out = static_cast<cx<R>*>(vol_ptr(vs.out, vol));
+  const RowIdx ri = row_of(t, n, L);
+  cx<R> mono[kNumMono];
+  load_mono(nodes, hph, L, ri.J, mono);
+  const int slice = ri.cube / lv.S, j = ri.cube - slice * lv.S;
+  const cx<R> y = gather_row<R, TI>(in, n, L, ri.J, lv.b, lv.S, slice * 8 + ri.f, j, sp, lv.nconst, mono);
+  out[gpos(n, L, ri.J, ((ri.f >> 2) & 1) + 2 * ri.a[0], ((ri.f >> 1) & 1) + 2 * ri.a[1], (ri.f & 1) + 2 * ri.a[2])] = y;
+}
+
+// Forward level L, second pass: z = DCT_2(phi) y = H_8 A(phi) y on every cube
+// (may run in place when TO is the stage type).
+template <typename R, typename TO>
+__global__ __launch_bounds__(256) void k_fwd_dct2(VolSet vs, int nvol, int n, int L, const double2* __restrict__ hph,
+                                                  const NodeConst* nodes) {
   const long long h = n >> 1, cubes = h * h * h;
   const long long tg = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (tg >= cubes * nvol) return;
   const long long vol = tg / cubes, t = tg - vol * cubes;
-  const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, vol));
-  TO* __restrict__ out = static_cast<TO*>(vol_ptr(vs.out, vol));
+  const cx<R>* in = static_cast<const cx<R>*>(vol_ptr(vs.in, vol));
+  TO* out = static_cast<TO*>(vol_ptr(vs.out, vol));
   int cube;
   CubeIdx ci = cube_of(t, n, L, &cube);
-  cx<R> mono[kNumMono];
-  {
-    cx<R> P[3][7];
-    node_powers(hph, L, ci.J, P);
-    node_monomials(P, mono);
-  }
   cx<R> y[8];
-  const int slice = cube / lv.S, j = cube - slice * lv.S;
-#pragma unroll FCC_ROW_UNROLL
-  for (int f = 0; f < 8; ++f) y[f] = gather_row<R, TI>(in, n, L, ci.J, lv.b, lv.S, slice * 8 + f, j, sp, lv.nconst, mono);
-  // z = H_8 A(phi) y; the phases are reloaded rather than kept live over the gathers
-  __asm__ volatile("" ::: "memory");
-  cx<R> Q[3][3];
-  node_pos_powers(hph, L, ci.J, Q);
+  long long pos[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    pos[i] = gpos(n, L, ci.J, ((i >> 2) & 1) + 2 * ci.a[0], ((i >> 1) & 1) + 2 * ci.a[1], (i & 1) + 2 * ci.a[2]);
+    y[i] = in[pos[i]];
+  }
   cx<R> tt[8];
-  apply_A(Q, y, tt);
+  const int c4[4] = {1, 3, 4, 6}, c3[3] = {2, 5, 7};
+  if (nodes) {
+    const NodeConst& nc = nodes[((long long)ci.J[0] << (2 * L)) | ((long long)ci.J[1] << L) | ci.J[2]];
+    tt[0] = y[0];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      cx<R> s{R(0), R(0)};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) s = s + ldc<R>(nc.a4[4 * i + j]) * y[c4[j]];
+      tt[c4[i]] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      cx<R> s{R(0), R(0)};
+#pragma unroll
+      for (int j = 0; j < 3; ++j) s = s + ldc<R>(nc.a3[3 * i + j]) * y[c3[j]];
+      tt[c3[i]] = s;
+    }
+  } else {
+    cx<R> Q[3][3];
+    node_pos_powers(hph, L, ci.J, Q);
+    apply_A(Q, y, tt);
+  }
   hadamard8(tt);
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
-    IO<TO, R>::st(out, gpos(n, L, ci.J, ((i >> 2) & 1) + 2 * ci.a[0], ((i >> 1) & 1) + 2 * ci.a[1], (i & 1) + 2 * ci.a[2]),
-                  tt[i]);
+  for (int i = 0; i < 8; ++i) IO<TO, R>::st(out, pos[i], tt[i]);
 }
 
 // Inverse level L, first pass: y = DCT_2(phi)^{-1} z = A(phi)^{-1} H_8 z / 8 on every cube.
-#ifndef FCC_INV_ATTR
-#define FCC_INV_ATTR
-#endif
 template <typename R, typename TI>
-__global__ __launch_bounds__(256) FCC_INV_ATTR void k_inv_dct2(VolSet vs, int nvol, int n, int L, const double2* __restrict__ hph) {
+__global__ __launch_bounds__(256) void k_inv_dct2(VolSet vs, int nvol, int n, int L, const double2* __restrict__ hph,
+                                                  const NodeConst* nodes) {
   const long long h = n >> 1, cubes = h * h * h;
   const long long tg = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (tg >= cubes * nvol) return;
@@ -352,11 +452,21 @@ __global__ __launch_bounds__(256) FCC_INV_ATTR void k_inv_dct2(VolSet vs, int nv
     z[i] = IO<TI, R>::ld(in, pos[i]);
   }
   hadamard8(z);
-  cx<R> Q[3][3];
-  node_pos_powers(hph, L, ci.J, Q);
-  cx<R> a4[4][4], a3[3][3];
-  build_A(Q, a4, a3);
   const int c4[4] = {1, 3, 4, 6}, c3[3] = {2, 5, 7};
+  cx<R> y[8];
+  y[0] = R(0.125) * z[0];
+  cx<R> a4[4][4], a3[3][3];
+  if (nodes) {
+    const NodeConst& nc = nodes[((long long)ci.J[0] << (2 * L)) | ((long long)ci.J[1] << L) | ci.J[2]];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a4[i / 4][i % 4] = ldc<R>(nc.a4[i]);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) a3[i / 3][i % 3] = ldc<R>(nc.a3[i]);
+  } else {
+    cx<R> Q[3][3];
+    node_pos_powers(hph, L, ci.J, Q);
+    build_A(Q, a4, a3);
+  }
   cx<R> b4[4], b3[3];
 #pragma unroll
   for (int i = 0; i < 4; ++i) b4[i] = R(0.125) * z[c4[i]];
@@ -364,8 +474,6 @@ __global__ __launch_bounds__(256) FCC_INV_ATTR void k_inv_dct2(VolSet vs, int nv
   for (int i = 0; i < 3; ++i) b3[i] = R(0.125) * z[c3[i]];
   solve_small<R, 4>(a4, b4);
   solve_small<R, 3>(a3, b3);
-  cx<R> y[8];
-  y[0] = R(0.125) * z[0];
 #pragma unroll
   for (int i = 0; i < 4; ++i) y[c4[i]] = b4[i];
 #pragma unroll
@@ -374,33 +482,25 @@ __global__ __launch_bounds__(256) FCC_INV_ATTR void k_inv_dct2(VolSet vs, int nv
   for (int i = 0; i < 8; ++i) out[pos[i]] = y[i];
 }
 
-// Inverse level L, second pass: x(kappa) = sum C_nl(phi)[kappa, (def,abc)] y(def + 2 abc).
+// Inverse level L, second pass: x(kappa) = sum C_nl(phi)[kappa, (def,abc)] y(def + 2 abc),
+// one thread per output kappa = i + 2 abc.
 template <typename R, typename TO>
 __global__ __launch_bounds__(256) void k_inv_basis(VolSet vs, int nvol, int n, int L, DevLevel lv,
-                                                   const double2* __restrict__ hph) {
+                                                   const double2* __restrict__ hph, const NodeConst* nodes) {
   __shared__ double sp[kMaxPoly * kNumMono];
   load_polys(lv, sp);
-  const long long h = n >> 1, cubes = h * h * h;
+  const long long N = (long long)n * n * n;
   const long long tg = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tg >= cubes * nvol) return;
-  const long long vol = tg / cubes, t = tg - vol * cubes;
+  if (tg >= N * nvol) return;
+  const long long vol = tg / N, t = tg - vol * N;
   const cx<R>* __restrict__ in = static_cast<const cx<R>*>(vol_ptr(vs.in, vol));
   TO* __restrict__ out = static_cast<TO*>(vol_ptr(vs.out, vol));
-  int cube;
-  CubeIdx ci = cube_of(t, n, L, &cube);
+  const RowIdx ri = row_of(t, n, L);
   cx<R> mono[kNumMono];
-  {
-    cx<R> P[3][7];
-    node_powers(hph, L, ci.J, P);
-    node_monomials(P, mono);
-  }
-  const int slice = cube / lv.S, j = cube - slice * lv.S;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const cx<R> acc = gather_row<R, cx<R>>(in, n, L, ci.J, lv.c, lv.S, slice * 8 + i, j, sp, lv.nconst, mono);
-    IO<TO, R>::st(out, gpos(n, L, ci.J, ((i >> 2) & 1) + 2 * ci.a[0], ((i >> 1) & 1) + 2 * ci.a[1], (i & 1) + 2 * ci.a[2]),
-                  acc);
-  }
+  load_mono(nodes, hph, L, ri.J, mono);
+  const int slice = ri.cube / lv.S, j = ri.cube - slice * lv.S;
+  const cx<R> x = gather_row<R, cx<R>>(in, n, L, ri.J, lv.c, lv.S, slice * 8 + ri.f, j, sp, lv.nconst, mono);
+  IO<TO, R>::st(out, gpos(n, L, ri.J, ((ri.f >> 2) & 1) + 2 * ri.a[0], ((ri.f >> 1) & 1) + 2 * ri.a[1], (ri.f & 1) + 2 * ri.a[2]), x);
 }
 
 // n = 1: the transform is the 1x1 matrix [T_0] = [1].
@@ -685,53 +785,63 @@ bool arith64(const fcc_plan_s* p, int L) { return p->stages64 && !(p->level0_fp3
 
 constexpr int kBlock = 256;
 
-dim3 grid_for(int n, int nvol) {
+dim3 grid_cubes(int n, int nvol) {  // one thread per 2x2x2 cube
   long long h = n >> 1;
   long long threads = h * h * h * nvol;
   return dim3((unsigned)((threads + kBlock - 1) / kBlock), 1, 1);
 }
-
-template <typename R, typename TI, typename TO>
-void launch_fwd(const fcc_plan_s* p, int L, const VolSet& vs, int nvol, hipStream_t st) {
-  hipLaunchKernelGGL((k_fwd_level<R, TI, TO>), grid_for(p->n, nvol), dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L],
-                     p->hph + 3 * ((1 << L) - 1));
+dim3 grid_points(int n, int nvol) {  // one thread per point (gather row)
+  long long threads = (long long)n * n * n * nvol;
+  return dim3((unsigned)((threads + kBlock - 1) / kBlock), 1, 1);
+}
+const double2* phases(const fcc_plan_s* p, int L) { return p->hph + 3 * ((1 << L) - 1); }
+const NodeConst* nodes_of(const fcc_plan_s* p, int L) {
+  return (p->nodes && p->node_off[L] >= 0) ? static_cast<const NodeConst*>(p->nodes) + p->node_off[L] : nullptr;
 }
 
-template <typename R, typename TI>
-void fwd_dispatch_out(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int nvol, hipStream_t st) {
-  switch (to) {
-    case DT::F32C: launch_fwd<R, TI, float2>(p, L, vs, nvol, st); break;
-    case DT::F64C: launch_fwd<R, TI, double2>(p, L, vs, nvol, st); break;
-    default: break;
+template <typename R>
+void fwd_gather_dispatch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, int nvol, hipStream_t st) {
+  dim3 g = grid_points(p->n, nvol);
+  const double2* h = phases(p, L);
+  const NodeConst* nc = nodes_of(p, L);
+  switch (ti) {
+    case DT::F32R: hipLaunchKernelGGL((k_fwd_gather<R, float>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc); break;
+    case DT::F64R: hipLaunchKernelGGL((k_fwd_gather<R, double>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc); break;
+    case DT::F32C: hipLaunchKernelGGL((k_fwd_gather<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc); break;
+    case DT::F64C: hipLaunchKernelGGL((k_fwd_gather<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc); break;
   }
 }
 template <typename R>
-void fwd_dispatch(const fcc_plan_s* p, int L, DT ti, DT to, const VolSet& vs, int nvol, hipStream_t st) {
-  switch (ti) {
-    case DT::F32R: fwd_dispatch_out<R, float>(p, L, to, vs, nvol, st); break;
-    case DT::F64R: fwd_dispatch_out<R, double>(p, L, to, vs, nvol, st); break;
-    case DT::F32C: fwd_dispatch_out<R, float2>(p, L, to, vs, nvol, st); break;
-    case DT::F64C: fwd_dispatch_out<R, double2>(p, L, to, vs, nvol, st); break;
-  }
+void fwd_dct2_dispatch(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int nvol, hipStream_t st) {
+  dim3 g = grid_cubes(p->n, nvol);
+  const double2* h = phases(p, L);
+  const NodeConst* nc = nodes_of(p, L);
+  if (to == DT::F32C)
+    hipLaunchKernelGGL((k_fwd_dct2<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, h, nc);
+  else
+    hipLaunchKernelGGL((k_fwd_dct2<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, h, nc);
 }
 
 template <typename R>
 void inv_dct2_dispatch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, int nvol, hipStream_t st) {
-  const double2* h = p->hph + 3 * ((1 << L) - 1);
+  dim3 g = grid_cubes(p->n, nvol);
+  const double2* h = phases(p, L);
+  const NodeConst* nc = nodes_of(p, L);
   if (ti == DT::F32C)
-    hipLaunchKernelGGL((k_inv_dct2<R, float2>), grid_for(p->n, nvol), dim3(kBlock), 0, st, vs, nvol, p->n, L, h);
+    hipLaunchKernelGGL((k_inv_dct2<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, h, nc);
   else
-    hipLaunchKernelGGL((k_inv_dct2<R, double2>), grid_for(p->n, nvol), dim3(kBlock), 0, st, vs, nvol, p->n, L, h);
+    hipLaunchKernelGGL((k_inv_dct2<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, h, nc);
 }
 template <typename R>
 void inv_basis_dispatch(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int nvol, hipStream_t st) {
-  const double2* h = p->hph + 3 * ((1 << L) - 1);
-  dim3 g = grid_for(p->n, nvol);
+  dim3 g = grid_points(p->n, nvol);
+  const double2* h = phases(p, L);
+  const NodeConst* nc = nodes_of(p, L);
   switch (to) {
-    case DT::F32R: hipLaunchKernelGGL((k_inv_basis<R, float>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h); break;
-    case DT::F64R: hipLaunchKernelGGL((k_inv_basis<R, double>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h); break;
-    case DT::F32C: hipLaunchKernelGGL((k_inv_basis<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h); break;
-    case DT::F64C: hipLaunchKernelGGL((k_inv_basis<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h); break;
+    case DT::F32R: hipLaunchKernelGGL((k_inv_basis<R, float>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc); break;
+    case DT::F64R: hipLaunchKernelGGL((k_inv_basis<R, double>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc); break;
+    case DT::F32C: hipLaunchKernelGGL((k_inv_basis<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc); break;
+    case DT::F64C: hipLaunchKernelGGL((k_inv_basis<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc); break;
   }
 }
 
@@ -777,17 +887,26 @@ fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
     return launch_status("forward n=1 launch");
   }
   VolPtrs src = in;
+  DT src_t = in_type(p);
   for (int L = 0; L < p->D; ++L) {
-    bool last = L == p->D - 1;
-    VolPtrs dst = last ? out : ((L & 1) ? ws1 : ws0);
-    DT ti = L == 0 ? in_type(p) : buf_type(p, L);
+    const bool last = L == p->D - 1;
+    VolPtrs a = (L & 1) ? ws1 : ws0;
+    // pass 1: basis-change gather into a; pass 2: DCT_2 on the cubes of a,
+    // in place (or into the user's output at the last level)
+    if (arith64(p, L))
+      fwd_gather_dispatch<double>(p, L, src_t, VolSet{src, a}, nvol, st);
+    else
+      fwd_gather_dispatch<float>(p, L, src_t, VolSet{src, a}, nvol, st);
+    if (tm) tm->mark(st);
+    VolPtrs dst = last ? out : a;
     DT to = last ? cplx_type(p) : buf_type(p, L + 1);
     if (arith64(p, L))
-      fwd_dispatch<double>(p, L, ti, to, VolSet{src, dst}, nvol, st);
+      fwd_dct2_dispatch<double>(p, L, to, VolSet{a, dst}, nvol, st);
     else
-      fwd_dispatch<float>(p, L, ti, to, VolSet{src, dst}, nvol, st);
+      fwd_dct2_dispatch<float>(p, L, to, VolSet{a, dst}, nvol, st);
     if (tm) tm->mark(st);
-    src = dst;
+    src = a;
+    src_t = buf_type(p, L + 1);
   }
   return launch_status("forward level launch");
 }
@@ -1087,6 +1206,26 @@ fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precis
     }
   }
   if (s == FCC_OK && p->D > 0) {
+    // FP64 node constants for the levels with at most kNodeTableMax nodes
+    long long total = 0;
+    for (int L = 0; L < p->D; ++L) {
+      p->node_off[L] = -1;
+      if ((1LL << (3 * L)) <= kNodeTableMax) {
+        p->node_off[L] = total;
+        total += 1LL << (3 * L);
+      }
+    }
+    hipError_t e = hipMalloc(&p->nodes, sizeof(NodeConst) * total);
+    if (e != hipSuccess) s = hip_fail(e, "hipMalloc(node table)", __LINE__);
+    for (int L = 0; s == FCC_OK && L < p->D; ++L)
+      if (p->node_off[L] >= 0) {
+        const long long cnt = 1LL << (3 * L);
+        hipLaunchKernelGGL(k_node_table, dim3(unsigned((cnt + 63) / 64)), dim3(64), 0, st,
+                           static_cast<NodeConst*>(p->nodes) + p->node_off[L], L, phases(p, L));
+        s = launch_status("node table launch");
+      }
+  }
+  if (s == FCC_OK && p->D > 0) {
     size_t N = size_t(n) * n * n;
     p->ws_bytes = N * (p->stages64 ? sizeof(double2) : sizeof(float2));
     for (int b = 0; b < 2 && s == FCC_OK; ++b) {
@@ -1129,6 +1268,7 @@ fcc_status fcc_dct_destroy(fcc_plan_t p) {
   }
   dense_free(p);
   if (p->resid) (void)hipFree(p->resid);
+  if (p->nodes) (void)hipFree(p->nodes);
   if (p->hph) (void)hipFree(p->hph);
   for (void* w : p->ws)
     if (w) (void)hipFree(w);
@@ -1161,7 +1301,7 @@ fcc_status fcc_dct_time_launches(fcc_plan_t p, const void* in, void* out, int di
   if (!p || !in || !out || !count || reps < 1 || (direction != 1 && direction != -1)) return FCC_ERR_INVALID_ARG;
   if (!aligned16(in) || !aligned16(out) || in == out) return FCC_ERR_INVALID_ARG;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  const int slots = (p->n == 1 || p->dense) ? 1 : (direction > 0 ? p->D : 2 * p->D);
+  const int slots = (p->n == 1 || p->dense) ? 1 : 2 * p->D;
   *count = slots;
   if (!ms || cap < slots) return ms ? FCC_ERR_INVALID_ARG : FCC_OK;
   (void)hipGetLastError();

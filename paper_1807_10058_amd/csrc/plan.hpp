@@ -33,6 +33,8 @@ struct fcc_plan_s {
   float* rowscale = nullptr;      // per-row input scales (FP16 split), rows_cap entries
   int rows_cap = 0;
   unsigned long long* resid = nullptr;  // 2 words for fcc_dct_roundtrip_residual
+  void* nodes = nullptr;                // FP64 node constants of the upper levels
+  long long node_off[16] = {};          // per level offset into nodes, -1 if none
 };
 
 namespace fcc {
