@@ -39,10 +39,12 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="plan with the built-in schedule instead of searching it first (setup, untimed)")
     return ap.parse_args()
 
 
-def launch_bytes(n, prec, stages64, real_in, direction):
+def launch_bytes(n, prec, stages64, real_in, direction, tail_levels):
     """Algorithmic bytes of each launch slot of a single-volume transform (each
     element read once and written once)."""
     N = n ** 3
@@ -50,18 +52,20 @@ def launch_bytes(n, prec, stages64, real_in, direction):
     io_r = 8 if prec == 0 else 4
     st = 16 if stages64 else 8
     D = n.bit_length() - 1
+    Lt = max(0, D - tail_levels)  # levels Lt.. run in one fused LDS launch
+    rin = io_r if real_in else io_c
     out = []
     if direction > 0:
-        for L in range(D):
-            bi = (io_r if real_in else io_c) if L == 0 else st
-            bo = io_c if L == D - 1 else st
+        for L in range(Lt):
+            bi = rin if L == 0 else st
             out.append(("k_fwd_gather L%d" % L, N * (bi + st)))
-            out.append(("k_fwd_dct2 L%d" % L, N * (st + bo)))
+            out.append(("k_fwd_dct2 L%d" % L, N * (st + st)))
+        out.append(("k_fwd_tail L%d-%d" % (Lt, D - 1), N * ((rin if Lt == 0 else st) + io_c)))
     else:
-        for k, L in enumerate(range(D - 1, -1, -1)):
-            bi = io_c if k == 0 else st
-            out.append(("k_inv_dct2 L%d" % L, N * (bi + st)))
-            bo = (io_r if real_in else io_c) if L == 0 else st
+        out.append(("k_inv_tail L%d-%d" % (D - 1, Lt), N * (io_c + (rin if Lt == 0 else st))))
+        for L in range(Lt - 1, -1, -1):
+            out.append(("k_inv_dct2 L%d" % L, N * (st + st)))
+            bo = rin if L == 0 else st
             out.append(("k_inv_basis L%d" % L, N * (st + bo)))
     return out
 
@@ -123,8 +127,13 @@ def single_volume(args, name):
     rdt = torch.float64 if prec == fcc.FCC_PREC_FP64 else torch.float32
     cdt = torch.complex128 if prec == fcc.FCC_PREC_FP64 else torch.complex64
     t0 = time.perf_counter()
+    if not args.no_autotune:
+        fcc.fcc_dct_autotune(n, prec=prec, flags=fcc.FCC_REAL_INPUT, reps=5)
+    tune_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
     plan = fcc.fcc_dct_plan(n, prec=prec, flags=fcc.FCC_REAL_INPUT)
     plan_s = time.perf_counter() - t0
+    sched = fcc.fcc_dct_get_tuning(plan)
     stages64 = prec == fcc.FCC_PREC_FP64 or n > 4
     x = torch.from_numpy(np.ascontiguousarray(x_np)).to(dev, rdt)
     X = torch.empty(n ** 3, dtype=cdt, device=dev)
@@ -141,7 +150,8 @@ def single_volume(args, name):
     for d in ([1] if direction == 1 else [1, -1]):
         src, dst = (x, X) if d == 1 else (X, y)
         times = fcc.fcc_dct_time_launches(plan, src, dst, d, reps=max(5, min(args.steps, 50)))
-        for (kname, nbytes), t in zip(launch_bytes(n, prec, stages64, True, d), times):
+        tail = sched["tail_levels"][0 if d == 1 else 1]
+        for (kname, nbytes), t in zip(launch_bytes(n, prec, stages64, True, d, tail), times):
             slots.append((kname, nbytes, t))
     kname, nbytes, tdom = max(slots, key=lambda s: s[2])
     achieved = nbytes / (tdom * 1e-3) / 1e9
@@ -158,7 +168,8 @@ def single_volume(args, name):
         acc["roundtrip_max_rel_fp64_gpu"] = fcc.fcc_dct_roundtrip_residual(plan, x, y)
     cfg = {"workload": desc, "n": n, "points": points, "io_dtype": "f64" if prec == 0 else "f32",
            "stages": "f64" if stages64 else "f32", "direction": "forward" if direction == 1 else "forward+inverse",
-           "plan_seconds": round(plan_s, 3), "wall_seconds_timed": round(wall, 4)}
+           "plan_seconds": round(plan_s, 3), "autotune_seconds": round(tune_s, 3), "schedule": sched,
+           "wall_seconds_timed": round(wall, 4)}
     extra = {"launches_ms": {s[0]: round(s[2], 5) for s in slots}, "accuracy": acc}
     return points, ms, "f64" if stages64 else "f32", cfg, roof, extra, (x_np, n)
 
@@ -186,6 +197,12 @@ def batched(args, name):
                 "forward then inverse in one graph replay")
     points = int(sum(n ** 3 for n in ns))
     cache = {}
+    t0 = time.perf_counter()
+    if not args.no_autotune:
+        for n in sorted(set(ns)):
+            if n > 1:
+                fcc.fcc_dct_autotune(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT, reps=3)
+    tune_s = time.perf_counter() - t0
 
     def plan_for(n, prec):
         if (n, prec) not in cache:
@@ -258,7 +275,7 @@ def batched(args, name):
                 "launch_ms": main["ms_per_step"], "algorithmic_bytes": nbytes}
         dtype = "f64"
     cfg = {"workload": desc, "volumes": len(ns), "points": points, "io_dtype": "f32",
-           "sizes": {str(k): ns.count(k) for k in sorted(set(ns))}}
+           "sizes": {str(k): ns.count(k) for k in sorted(set(ns))}, "autotune_seconds": round(tune_s, 3)}
     extra = {"variants": res, "accuracy": main["accuracy"]}
     big = max(range(len(ns)), key=lambda i: ns[i])
     return points, main["ms_per_step"], dtype, cfg, roof, extra, (xs_np[big], ns[big])

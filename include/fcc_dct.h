@@ -118,15 +118,66 @@ fcc_status fcc_dct_destroy(fcc_plan_t plan);
 /* Static description of a status code. */
 const char* fcc_status_string(fcc_status s);
 
+/* ---- schedule tuning ---------------------------------------------------- */
+
+/* How a plan schedules the levels of eq. FastAlgorithm on the GPU.  Tile and
+ * map choices change no result bit (every output row is summed in the same
+ * order).  A different tail depth evaluates the same expressions, at the same
+ * stage precision, in another kernel and may differ in the last bits.  Index
+ * [0] is the forward transform, [1] the inverse.
+ *   tail_levels[d] : the last 1..3 levels (node sizes <= 2^tail_levels) run
+ *                    fused in one launch with the data resident in LDS.
+ *   tile[d][L][.]  : at levels L = 0, 1 the gather pass of the basis change
+ *                    walks the cubes of a node in tiles of 2^t0 x 2^t1 x 2^t2
+ *                    cubes (log2 sizes; {0,0,0} = plain lexicographic order).
+ *                    Each side is clamped to the node's n / 2^(L+1) cubes.
+ *   map[d][L]      : FCC_MAP_XCD numbers the blocks of that gather pass so
+ *                    that each XCD takes one contiguous range of rows;
+ *                    FCC_MAP_F_INNER puts the 8 rows of a cube next to each
+ *                    other (otherwise the row's position in its cube is the
+ *                    slowest index). */
+enum { FCC_MAP_XCD = 1u << 0, FCC_MAP_F_INNER = 1u << 1 };
+typedef struct {
+  int tail_levels[2];
+  int tile[2][2][3];
+  unsigned map[2][2];
+} fcc_tuning;
+
+/* fcc_dct_plan with an explicit schedule.  tuning == NULL takes the schedule
+ * fcc_dct_plan would take (see fcc_dct_autotune).  Errors: those of
+ * fcc_dct_plan, and FCC_ERR_INVALID_ARG for tail_levels outside 1..3, a tile
+ * size outside 0..9 or unknown map bits. */
+fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_precision prec,
+                              unsigned flags, const fcc_tuning* tuning, void* hip_stream);
+
+/* The schedule a plan runs with. */
+fcc_status fcc_dct_get_tuning(fcc_plan_t plan, fcc_tuning* out);
+
+/* Search the schedule for (n, prec, flags) on the current device: the fused
+ * tail depth of each direction first (whole-transform time), then tile shape
+ * and block map of the level-0 and level-1 gather passes one at a time
+ * (time of that launch), each candidate timed `reps` times on synthetic data
+ * with HIP events on `hip_stream`.  The winner is written to *best (may be
+ * NULL) and remembered for the process: later fcc_dct_plan calls for the same
+ * (device, n, prec, flags) use it.  Without a search, fcc_dct_plan uses
+ * built-in defaults.  Allocates and frees its own buffers and synchronises
+ * `hip_stream`.  Errors: those of fcc_dct_plan, FCC_ERR_INVALID_ARG for
+ * reps < 1. */
+fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsigned flags, int reps,
+                            fcc_tuning* best, void* hip_stream);
+
 /* ---- measurement ------------------------------------------------------- */
 
 /* Per-launch timing of one direction of the fast path: enqueues `reps`
  * transforms of `in` into `out` (direction +1 forward, -1 inverse) on
  * `hip_stream` with HIP events recorded around every kernel launch, waits for
  * them, and writes the average duration in ms of each launch slot to ms[k].
- * Slots in launch order: forward = level 0..D-1; inverse = (DCT_2^{-1} pass,
- * C pass) for level D-1 down to 0; n = 1 has one slot.  *count receives the
- * number of slots; with ms == NULL only *count is set.
+ * Slots in launch order, with Lt = D - tail_levels (at least 0) of the
+ * direction: forward = (B gather pass, DCT_2 pass) for levels 0..Lt-1, then
+ * the fused tail; inverse = the fused tail, then (DCT_2^{-1} pass, C gather
+ * pass) for levels Lt-1 down to 0.  n = 1 and the dense precisions have one
+ * slot.  *count receives the number of slots; with ms == NULL only *count is
+ * set.
  * Errors: FCC_ERR_INVALID_ARG (cap too small, bad pointers or direction),
  * FCC_ERR_HIP. */
 fcc_status fcc_dct_time_launches(fcc_plan_t plan, const void* in, void* out, int direction, int reps,

@@ -12,6 +12,7 @@ _LIB_PATH = os.path.join(_HERE, "libfccdct.so")
 FCC_OK = 0
 FCC_PREC_FP64, FCC_PREC_FP32, FCC_PREC_SPLIT_BF16, FCC_PREC_SPLIT_FP16 = 0, 1, 2, 3
 FCC_REAL_INPUT, FCC_STAGES_FP32, FCC_STAGES_FP64, FCC_LEVEL0_FP32 = 1, 2, 4, 8
+FCC_MAP_XCD, FCC_MAP_F_INNER = 1, 2
 
 # torch is loaded first so that libfccdct.so binds to the HIP runtime torch
 # already carries (same soname): one HIP/HSA runtime per process.
@@ -32,9 +33,36 @@ class _LevelTables(ctypes.Structure):
                 ("c_pid", ctypes.POINTER(ctypes.c_ushort))]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("tail_levels", ctypes.c_int * 2), ("tile", ((ctypes.c_int * 3) * 2) * 2),
+                ("map", (ctypes.c_uint * 2) * 2)]
+
+
+def _tuning_to_c(t):
+    c = _Tuning()
+    for d in range(2):
+        c.tail_levels[d] = int(t["tail_levels"][d])
+        for L in range(2):
+            c.map[d][L] = int(t["map"][d][L])
+            for a in range(3):
+                c.tile[d][L][a] = int(t["tile"][d][L][a])
+    return c
+
+
+def _tuning_from_c(c):
+    return {"tail_levels": [c.tail_levels[0], c.tail_levels[1]],
+            "tile": [[[c.tile[d][L][a] for a in range(3)] for L in range(2)] for d in range(2)],
+            "map": [[c.map[d][L] for L in range(2)] for d in range(2)]}
+
+
 _vp = ctypes.c_void_p
 _lib.fcc_dct_plan.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                               ctypes.c_uint, _vp]
+_lib.fcc_dct_plan_tuned.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                    ctypes.c_uint, ctypes.POINTER(_Tuning), _vp]
+_lib.fcc_dct_get_tuning.argtypes = [_vp, ctypes.POINTER(_Tuning)]
+_lib.fcc_dct_autotune.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_uint,
+                                  ctypes.c_int, ctypes.POINTER(_Tuning), _vp]
 _lib.fcc_dct_forward.argtypes = [_vp, _vp, _vp, _vp]
 _lib.fcc_dct_inverse.argtypes = [_vp, _vp, _vp, _vp]
 _lib.fcc_dct_batched.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
@@ -46,7 +74,7 @@ _lib.fcc_dct_time_launches.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int
 _lib.fcc_status_string.argtypes = [ctypes.c_int]
 _lib.fcc_status_string.restype = ctypes.c_char_p
 _lib.fcc_asp_tables.argtypes = [ctypes.c_int, ctypes.POINTER(_LevelTables)]
-for _f in ("fcc_dct_plan", "fcc_dct_forward", "fcc_dct_inverse", "fcc_dct_batched", "fcc_dct_destroy",
+for _f in ("fcc_dct_plan", "fcc_dct_plan_tuned", "fcc_dct_get_tuning", "fcc_dct_autotune", "fcc_dct_forward", "fcc_dct_inverse", "fcc_dct_batched", "fcc_dct_destroy",
            "fcc_asp_tables", "fcc_dct_time_launches", "fcc_dct_roundtrip_residual"):
     getattr(_lib, _f).restype = ctypes.c_int
 
@@ -108,6 +136,32 @@ def fcc_dct_plan(n, rst=None, prec=FCC_PREC_FP32, flags=FCC_REAL_INPUT, stream=N
     st = _stream(stream) if stream is not None or _torch_cuda() else None
     _check(_lib.fcc_dct_plan(ctypes.byref(h), int(n), r, int(prec), int(flags), st), "fcc_dct_plan")
     return Plan(h.value, int(n), int(prec), int(flags))
+
+
+def fcc_dct_plan_tuned(n, rst=None, prec=FCC_PREC_FP32, flags=FCC_REAL_INPUT, tuning=None, stream=None):
+    """fcc_dct_plan with an explicit schedule: a dict with keys tail_levels [fwd, inv],
+    tile [dir][level][3] (log2 sizes) and map [dir][level] (FCC_MAP_* bits), or None."""
+    h = _vp()
+    r = None if rst is None else (ctypes.c_double * 3)(*[float(v) for v in rst])
+    t = None if tuning is None else ctypes.byref(_tuning_to_c(tuning))
+    st = _stream(stream) if stream is not None or _torch_cuda() else None
+    _check(_lib.fcc_dct_plan_tuned(ctypes.byref(h), int(n), r, int(prec), int(flags), t, st), "fcc_dct_plan_tuned")
+    return Plan(h.value, int(n), int(prec), int(flags))
+
+
+def fcc_dct_get_tuning(plan):
+    c = _Tuning()
+    _check(_lib.fcc_dct_get_tuning(plan.handle, ctypes.byref(c)), "fcc_dct_get_tuning")
+    return _tuning_from_c(c)
+
+
+def fcc_dct_autotune(n, rst=None, prec=FCC_PREC_FP32, flags=FCC_REAL_INPUT, reps=5, stream=None):
+    """Search the schedule for (n, prec, flags); later plans of that kind use it."""
+    r = None if rst is None else (ctypes.c_double * 3)(*[float(v) for v in rst])
+    c = _Tuning()
+    _check(_lib.fcc_dct_autotune(int(n), r, int(prec), int(flags), int(reps), ctypes.byref(c), _stream(stream)),
+           "fcc_dct_autotune")
+    return _tuning_from_c(c)
 
 
 def _torch_cuda():

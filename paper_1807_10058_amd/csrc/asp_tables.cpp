@@ -111,7 +111,21 @@ struct PolyPool {
     return s;
   }
   const Coef& at(uint32_t id) const { return polys[id]; }
-  uint32_t intern(const Coef& p) {
+  // The exact coefficients are rationals whose denominators divide 144 (the
+  // orbit weights 1/24, 1/|O| of the product and reduction formulas); the
+  // computed ones carry rounding that depends on the order in which threads
+  // derived them.  Snapping to k/144 makes every interned value, and so the
+  // tables, independent of thread timing.  Values that are not that close to
+  // such a rational are kept as computed.
+  static Coef snap(Coef p) {
+    for (double& v : p) {
+      const double q = std::nearbyint(v * 144.0);
+      if (std::fabs(v * 144.0 - q) < 1e-7) v = q / 144.0;
+    }
+    return p;
+  }
+  uint32_t intern(const Coef& raw) {
+    const Coef p = snap(raw);
     thread_local uint64_t cache_gen = 0;
     thread_local std::unordered_map<QKey, uint32_t, QHash> cache;
     if (cache_gen != generation) {

@@ -339,6 +339,10 @@ fcc_status dense_prepare(fcc_plan_s* p, hipStream_t st) {
     sub.stages64 = true;
     sub.lv = p->lv;
     sub.hph = p->hph;
+    sub.tune = p->tune;
+    sub.tail_Lt[0] = p->tail_Lt[0];
+    sub.tail_Lt[1] = p->tail_Lt[1];
+    sub.tlv = p->tlv;
     // all N unit vectors in one launch sequence; pointer arrays on the device
     if (hipMalloc(&E, sizeof(double2) * N * N) != hipSuccess) return fail(FCC_ERR_OOM);
     if (hipMalloc(&scratch, sizeof(double2) * N * N * 2) != hipSuccess) return fail(FCC_ERR_OOM);

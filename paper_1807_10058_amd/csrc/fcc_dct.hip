@@ -323,28 +323,40 @@ __device__ __forceinline__ cx<R> ldc(const double2& v) {
 }
 
 // Thread t (within one volume) -> one row of the level's gather: node J (the
-// 8^L nodes vary fastest), then cube, then f.  At level 0 (1) a wavefront
-// covers 64 (8) consecutive cubes of one f = one table slice; from level 2 on
-// it covers 64 nodes of one row.
+// 8^L nodes vary fastest), then cube (in the side's cube order) and f.  With
+// f outermost, a wavefront at level 0 (1) covers the 64 (8) cubes of one table
+// slice for one f; with f_inner the 8 f of a slice follow each other.  From
+// level 2 on a wavefront covers 64 nodes of one row.
 struct RowIdx {
   int J[3], a[3], cube, f;
 };
-__device__ __forceinline__ RowIdx row_of(long long t, int n, int L) {
+__device__ __forceinline__ RowIdx row_of(long long t, int n, int L, CubeOrder ord, int S, int f_inner) {
   const int mask = (1 << L) - 1;
   const int jf = int(t & ((1LL << (3 * L)) - 1));
   const long long rest = t >> (3 * L);
-  const int m = (n >> L) >> 1;
-  const long long cubes = (long long)m * m * m;
+  const int lgm = __ffs(n) - 2 - L;  // log2 of m = n / 2^(L+1)
   RowIdx r;
-  r.f = int(rest / cubes);
-  r.cube = int(rest - (long long)r.f * cubes);
+  if (f_inner) {
+    const long long sf = rest / S;  // slice * 8 + f
+    r.f = int(sf & 7);
+    r.cube = int((sf >> 3) * S + (rest - sf * S));
+  } else {
+    r.f = int(rest >> (3 * lgm));
+    r.cube = int(rest & ((1LL << (3 * lgm)) - 1));
+  }
   r.J[0] = jf >> (2 * L);
   r.J[1] = (jf >> L) & mask;
   r.J[2] = jf & mask;
-  r.a[0] = r.cube / (m * m);
-  r.a[1] = (r.cube / m) % m;
-  r.a[2] = r.cube % m;
+  cube_abc(r.cube, lgm, ord, r.a);
   return r;
+}
+
+// Block index of a gather launch (GatherMap::xcd: blocks i, i+8, i+16, ... run
+// on one XCD and get one contiguous range).
+__device__ __forceinline__ long long gather_block(int xcd) {
+  if (!xcd) return blockIdx.x;
+  const unsigned nb = gridDim.x, i = blockIdx.x, x = i & 7u, l = i >> 3, per = nb >> 3, rem = nb & 7u;
+  return (long long)x * per + min(x, rem) + l;
 }
 
 template <typename R>
@@ -365,16 +377,16 @@ __device__ __forceinline__ void load_mono(const NodeConst* nodes, const double2*
 // the node, one thread per row, stored at node-local position def + 2 abc.
 template <typename R, typename TI>
 __global__ __launch_bounds__(256) void k_fwd_gather(VolSet vs, int nvol, int n, int L, DevLevel lv,
-                                                    const double2* __restrict__ hph, const NodeConst* nodes) {
+                                                    const double2* __restrict__ hph, const NodeConst* nodes, GatherMap gm) {
   __shared__ double sp[kMaxPoly * kNumMono];
   load_polys(lv, sp);
   const long long N = (long long)n * n * n;
-  const long long tg = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long tg = gather_block(gm.xcd) * blockDim.x + threadIdx.x;
   if (tg >= N * nvol) return;
   const long long vol = tg / N, t = tg - vol * N;
   const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, vol));
   cx<R>* __restrict__ out = static_cast<cx<R>*>(vol_ptr(vs.out, vol));
-  const RowIdx ri = row_of(t, n, L);
+  const RowIdx ri = row_of(t, n, L, lv.b.order, lv.S, gm.f_inner);
   cx<R> mono[kNumMono];
   load_mono(nodes, hph, L, ri.J, mono);
   const int slice = ri.cube / lv.S, j = ri.cube - slice * lv.S;
@@ -486,21 +498,283 @@ __global__ __launch_bounds__(256) void k_inv_dct2(VolSet vs, int nvol, int n, in
 // one thread per output kappa = i + 2 abc.
 template <typename R, typename TO>
 __global__ __launch_bounds__(256) void k_inv_basis(VolSet vs, int nvol, int n, int L, DevLevel lv,
-                                                   const double2* __restrict__ hph, const NodeConst* nodes) {
+                                                   const double2* __restrict__ hph, const NodeConst* nodes, GatherMap gm) {
   __shared__ double sp[kMaxPoly * kNumMono];
   load_polys(lv, sp);
   const long long N = (long long)n * n * n;
-  const long long tg = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long tg = gather_block(gm.xcd) * blockDim.x + threadIdx.x;
   if (tg >= N * nvol) return;
   const long long vol = tg / N, t = tg - vol * N;
   const cx<R>* __restrict__ in = static_cast<const cx<R>*>(vol_ptr(vs.in, vol));
   TO* __restrict__ out = static_cast<TO*>(vol_ptr(vs.out, vol));
-  const RowIdx ri = row_of(t, n, L);
+  const RowIdx ri = row_of(t, n, L, lv.c.order, lv.S, gm.f_inner);
   cx<R> mono[kNumMono];
   load_mono(nodes, hph, L, ri.J, mono);
   const int slice = ri.cube / lv.S, j = ri.cube - slice * lv.S;
   const cx<R> x = gather_row<R, cx<R>>(in, n, L, ri.J, lv.c, lv.S, slice * 8 + ri.f, j, sp, lv.nconst, mono);
   IO<TO, R>::st(out, gpos(n, L, ri.J, ((ri.f >> 2) & 1) + 2 * ri.a[0], ((ri.f >> 1) & 1) + 2 * ri.a[1], (ri.f & 1) + 2 * ri.a[2]), x);
+}
+
+// ---------------------------------------------------------------------------
+// Fused tail: the last levels (node size nl0 <= kTailNl) of a group of G <= kTailG
+// sibling nodes (consecutive J_z) run in LDS, one thread per 2x2x2 cube of
+// every sub-level.  Sub-level l of the tail is global level Lt + l; its
+// sub-nodes j' in [0, 2^l)^3 own the node-local positions j' + 2^l b, exactly
+// as the global layout nests.
+// ---------------------------------------------------------------------------
+constexpr int kTailNl = 8;
+constexpr int kTailG = 2;
+constexpr int kTailPts = kTailNl * kTailNl * kTailNl;
+constexpr int kTailCubes = kTailPts / 8;  // cubes of one node at every sub-level
+
+struct TailLevels {
+  DevLevel lv[4];             // CSR tables (S = 1) of node sizes nl0, nl0/2, ...
+  const NodeConst* nodes[4];  // node tables of global levels Lt + l, or null
+  const double2* hph[4];      // phase tables of global levels Lt + l
+};
+
+__device__ __forceinline__ int lpos(int nl0, int l, const int jp[3], int x, int y, int z) {
+  return (((jp[0] + (x << l)) * nl0) + (jp[1] + (y << l))) * nl0 + (jp[2] + (z << l));
+}
+
+// One CSR row gathered from an LDS node buffer.
+template <typename R>
+__device__ __forceinline__ cx<R> lds_row(const cx<R>* buf, int nl0, int l, const int jp[3], const DevSide& sd, int r,
+                                         const double* sp, int nconst, const cx<R> mono[kNumMono]) {
+  const int e0 = sd.start[r], len = sd.len[r];
+  cx<R> acc{R(0), R(0)};
+  for (int e = 0; e < len; ++e) {
+    const uint32_t s = sd.src[e0 + e];
+    acc = acc + poly_value(sp, nconst, sd.pid[e0 + e], mono) *
+                    buf[lpos(nl0, l, jp, int(s >> 20), int((s >> 10) & 1023u), int(s & 1023u))];
+  }
+  return acc;
+}
+
+struct TailGeom {
+  int n, Lt, nl0, k, G;
+};
+// block -> (volume, first node J of the group)
+__device__ __forceinline__ void tail_block(const TailGeom& tg, long long blk, long long* vol, int J[3]) {
+  const long long groups = (1LL << (3 * tg.Lt)) / tg.G;
+  *vol = blk / groups;
+  const long long jf = (blk - *vol * groups) * tg.G;  // J_z fastest
+  const int mask = (1 << tg.Lt) - 1;
+  J[0] = int(jf >> (2 * tg.Lt));
+  J[1] = int((jf >> tg.Lt) & mask);
+  J[2] = int(jf & mask);
+}
+// thread -> (node g of the group, sub-node j', cube a) at sub-level l; G3 = global node
+struct TailCube {
+  int g, jp[3], a[3], G3[3];
+};
+__device__ __forceinline__ TailCube tail_cube(const TailGeom& tg, const int J[3], int l, int t) {
+  const int cpn = tg.nl0 * tg.nl0 * tg.nl0 / 8;  // cubes per node
+  const int m = (tg.nl0 >> l) >> 1, sub = 1 << l;
+  TailCube c;
+  c.g = t / cpn;
+  const int rr = t - c.g * cpn;
+  const int jf = rr & ((1 << (3 * l)) - 1), cube = rr >> (3 * l);
+  c.jp[0] = jf >> (2 * l);
+  c.jp[1] = (jf >> l) & (sub - 1);
+  c.jp[2] = jf & (sub - 1);
+  c.a[0] = cube / (m * m);
+  c.a[1] = (cube / m) % m;
+  c.a[2] = cube % m;
+  c.G3[0] = J[0] + (c.jp[0] << tg.Lt);
+  c.G3[1] = J[1] + (c.jp[1] << tg.Lt);
+  c.G3[2] = J[2] + c.g + (c.jp[2] << tg.Lt);
+  return c;
+}
+__device__ __forceinline__ long long node_index(const int G3[3], int Lg) {
+  return ((long long)G3[0] << (2 * Lg)) | ((long long)G3[1] << Lg) | G3[2];
+}
+template <typename R>
+__device__ __forceinline__ void tail_mono(const TailLevels& tl, int l, int Lg, const int G3[3], cx<R> mono[kNumMono]) {
+  if (tl.nodes[l]) {
+    const NodeConst& nc = tl.nodes[l][node_index(G3, Lg)];
+#pragma unroll
+    for (int q = 0; q < kNumMono; ++q) mono[q] = ldc<R>(nc.mono[q]);
+  } else {
+    cx<R> P[3][7];
+    node_powers(tl.hph[l], Lg, G3, P);
+    node_monomials(P, mono);
+  }
+}
+template <typename R>
+__device__ __forceinline__ void tail_A(const TailLevels& tl, int l, int Lg, const int G3[3], cx<R> a4[4][4],
+                                       cx<R> a3[3][3]) {
+  if (tl.nodes[l]) {
+    const NodeConst& nc = tl.nodes[l][node_index(G3, Lg)];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a4[i / 4][i % 4] = ldc<R>(nc.a4[i]);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) a3[i / 3][i % 3] = ldc<R>(nc.a3[i]);
+  } else {
+    cx<R> Q[3][3];
+    node_pos_powers(tl.hph[l], Lg, G3, Q);
+    build_A(Q, a4, a3);
+  }
+}
+
+template <typename R, typename TI>
+__device__ __forceinline__ void tail_load(const TailGeom& tg, const int J[3], const TI* in, cx<R>* buf) {
+  const int npts = tg.nl0 * tg.nl0 * tg.nl0;
+  for (int t = threadIdx.x; t < tg.G * npts; t += blockDim.x) {
+    const int g = t % tg.G, a = t / tg.G;
+    const int ax = a / (tg.nl0 * tg.nl0), ay = (a / tg.nl0) % tg.nl0, az = a % tg.nl0;
+    const long long gp = ((long long)(J[0] + (ax << tg.Lt)) * tg.n + (J[1] + (ay << tg.Lt))) * tg.n +
+                         (J[2] + g + (az << tg.Lt));
+    buf[g * npts + a] = IO<TI, R>::ld(in, gp);
+  }
+}
+template <typename R, typename TO>
+__device__ __forceinline__ void tail_store(const TailGeom& tg, const int J[3], const cx<R>* buf, TO* out) {
+  const int npts = tg.nl0 * tg.nl0 * tg.nl0;
+  for (int t = threadIdx.x; t < tg.G * npts; t += blockDim.x) {
+    const int g = t % tg.G, a = t / tg.G;
+    const int ax = a / (tg.nl0 * tg.nl0), ay = (a / tg.nl0) % tg.nl0, az = a % tg.nl0;
+    const long long gp = ((long long)(J[0] + (ax << tg.Lt)) * tg.n + (J[1] + (ay << tg.Lt))) * tg.n +
+                         (J[2] + g + (az << tg.Lt));
+    IO<TO, R>::st(out, gp, buf[g * npts + a]);
+  }
+}
+
+// Every thread owns at most one cube per sub-level (the block has at least
+// G * nl0^3 / 8 threads), so each sub-level reads its cube into registers,
+// waits, and writes back into the same LDS buffer.
+template <typename R, typename TI, typename TO>
+__global__ __launch_bounds__(kTailG * kTailCubes) void k_fwd_tail(VolSet vs, TailGeom tg, TailLevels tl) {
+  __shared__ cx<R> buf[kTailG * kTailPts];
+  __shared__ double sp[kMaxPoly * kNumMono];
+  long long vol;
+  int J[3];
+  tail_block(tg, blockIdx.x, &vol, J);
+  tail_load<R>(tg, J, static_cast<const TI*>(vol_ptr(vs.in, vol)), buf);
+  const int npts = tg.nl0 * tg.nl0 * tg.nl0, ncubes = tg.G * npts / 8;
+  const int t = threadIdx.x;
+  for (int l = 0; l < tg.k; ++l) {
+    const int Lg = tg.Lt + l;
+    const DevLevel& lv = tl.lv[l];
+    __syncthreads();
+    for (int i = t; i < lv.npoly * kNumMono; i += blockDim.x) sp[i] = lv.poly[i];
+    __syncthreads();
+    TailCube c{};
+    cx<R> tt[8];
+    if (t < ncubes) {
+      c = tail_cube(tg, J, l, t);
+      const int m = (tg.nl0 >> l) >> 1;
+      const int cube = (c.a[0] * m + c.a[1]) * m + c.a[2];
+      const cx<R>* src = buf + c.g * npts;
+      cx<R> mono[kNumMono];
+      tail_mono<R>(tl, l, Lg, c.G3, mono);
+      cx<R> y[8];
+#pragma unroll
+      for (int f = 0; f < 8; ++f) y[f] = lds_row(src, tg.nl0, l, c.jp, lv.b, cube * 8 + f, sp, lv.nconst, mono);
+      if (tl.nodes[l]) {
+        const NodeConst& nc = tl.nodes[l][node_index(c.G3, Lg)];
+        const int c4[4] = {1, 3, 4, 6}, c3[3] = {2, 5, 7};
+        tt[0] = y[0];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          cx<R> acc{R(0), R(0)};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc = acc + ldc<R>(nc.a4[i * 4 + j]) * y[c4[j]];
+          tt[c4[i]] = acc;
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          cx<R> acc{R(0), R(0)};
+#pragma unroll
+          for (int j = 0; j < 3; ++j) acc = acc + ldc<R>(nc.a3[i * 3 + j]) * y[c3[j]];
+          tt[c3[i]] = acc;
+        }
+      } else {
+        cx<R> Q[3][3];
+        node_pos_powers(tl.hph[l], Lg, c.G3, Q);
+        apply_A(Q, y, tt);
+      }
+      hadamard8(tt);
+    }
+    __syncthreads();
+    if (t < ncubes) {
+      cx<R>* dst = buf + c.g * npts;
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        dst[lpos(tg.nl0, l, c.jp, ((i >> 2) & 1) + 2 * c.a[0], ((i >> 1) & 1) + 2 * c.a[1], (i & 1) + 2 * c.a[2])] = tt[i];
+    }
+  }
+  __syncthreads();
+  tail_store<R>(tg, J, buf, static_cast<TO*>(vol_ptr(vs.out, vol)));
+}
+
+template <typename R, typename TI, typename TO>
+__global__ __launch_bounds__(kTailG * kTailCubes) void k_inv_tail(VolSet vs, TailGeom tg, TailLevels tl) {
+  __shared__ cx<R> buf[kTailG * kTailPts];
+  __shared__ double sp[kMaxPoly * kNumMono];
+  long long vol;
+  int J[3];
+  tail_block(tg, blockIdx.x, &vol, J);
+  tail_load<R>(tg, J, static_cast<const TI*>(vol_ptr(vs.in, vol)), buf);
+  const int npts = tg.nl0 * tg.nl0 * tg.nl0, ncubes = tg.G * npts / 8;
+  const int t = threadIdx.x;
+  const int c4[4] = {1, 3, 4, 6}, c3[3] = {2, 5, 7};
+  for (int l = tg.k - 1; l >= 0; --l) {
+    const int Lg = tg.Lt + l;
+    const DevLevel& lv = tl.lv[l];
+    __syncthreads();
+    for (int i = t; i < lv.npoly * kNumMono; i += blockDim.x) sp[i] = lv.poly[i];
+    // DCT_2^{-1} on this thread's cube, in place
+    TailCube c{};
+    int cube = 0;
+    if (t < ncubes) {
+      c = tail_cube(tg, J, l, t);
+      const int m = (tg.nl0 >> l) >> 1;
+      cube = (c.a[0] * m + c.a[1]) * m + c.a[2];
+      cx<R>* b = buf + c.g * npts;
+      cx<R> z[8];
+      int p[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        p[i] = lpos(tg.nl0, l, c.jp, ((i >> 2) & 1) + 2 * c.a[0], ((i >> 1) & 1) + 2 * c.a[1], (i & 1) + 2 * c.a[2]);
+        z[i] = b[p[i]];
+      }
+      hadamard8(z);
+      cx<R> a4[4][4], a3[3][3];
+      tail_A<R>(tl, l, Lg, c.G3, a4, a3);
+      cx<R> b4[4], b3[3];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) b4[i] = R(0.125) * z[c4[i]];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) b3[i] = R(0.125) * z[c3[i]];
+      solve_small<R, 4>(a4, b4);
+      solve_small<R, 3>(a3, b3);
+      b[p[0]] = R(0.125) * z[0];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) b[p[c4[i]]] = b4[i];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) b[p[c3[i]]] = b3[i];
+    }
+    __syncthreads();
+    // C gather: the 8 outputs kappa = i + 2 abc of this thread's cube
+    cx<R> x[8];
+    if (t < ncubes) {
+      const cx<R>* src = buf + c.g * npts;
+      cx<R> mono[kNumMono];
+      tail_mono<R>(tl, l, Lg, c.G3, mono);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) x[i] = lds_row(src, tg.nl0, l, c.jp, lv.c, cube * 8 + i, sp, lv.nconst, mono);
+    }
+    __syncthreads();
+    if (t < ncubes) {
+      cx<R>* dst = buf + c.g * npts;
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        dst[lpos(tg.nl0, l, c.jp, ((i >> 2) & 1) + 2 * c.a[0], ((i >> 1) & 1) + 2 * c.a[1], (i & 1) + 2 * c.a[2])] = x[i];
+    }
+  }
+  __syncthreads();
+  tail_store<R>(tg, J, buf, static_cast<TO*>(vol_ptr(vs.out, vol)));
 }
 
 // n = 1: the transform is the 1x1 matrix [T_0] = [1].
@@ -544,6 +818,18 @@ __global__ __launch_bounds__(256) void k_residual(const T* __restrict__ x, const
   }
 }
 
+// Synthetic operand in [-1, 1): a hash of the index (autotuning input).
+template <typename T>
+__global__ void k_fill(T* x, long long count, unsigned seed) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x) {
+    unsigned h = unsigned(i) * 2654435761u ^ (unsigned(i >> 32) + seed) * 2246822519u;
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    x[i] = T(int(h >> 8) - (1 << 23)) / T(1 << 23);
+  }
+}
+
 __global__ void k_zero2(unsigned long long* p) {
   if (threadIdx.x < 2) p[threadIdx.x] = 0ull;
 }
@@ -575,9 +861,18 @@ namespace {
 
 enum class DT { F32R, F64R, F32C, F64C };
 
+// Coefficient polynomials of one node size on one device, in the fixed
+// monomial order, constants first.
+struct DevPolys {
+  const double* poly = nullptr;
+  int npoly = 0, nconst = 0;
+  uint16_t zero_pid = 0;        // the zero polynomial that pads sliced tables
+  std::vector<uint16_t> newid;  // host polynomial id -> device id
+};
 struct DevTablesCache {
   std::mutex mu;
-  std::map<std::array<int, 3>, DevLevel> levels;  // (device, nl, cubes per slice)
+  std::map<std::array<int, 2>, DevPolys> polys;  // (device, nl)
+  std::map<std::array<int, 5>, DevSide> sides;   // (device, nl, cubes per slice, side, cube order)
   std::vector<void*> owned;
 };
 DevTablesCache& cache() {
@@ -608,8 +903,10 @@ fcc_status launch_status(const char* what) {
   return e == hipSuccess ? FCC_OK : hip_fail(e, what, 0);
 }
 
+// Device copy of v; the allocation is recorded in *own (the table cache's list
+// by default: kept until the process ends).
 template <typename T>
-fcc_status upload(const std::vector<T>& v, const T** out) {
+fcc_status upload(const std::vector<T>& v, const T** out, std::vector<void*>* own = nullptr) {
   void* p = nullptr;
   size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
   HIPCHK(hipMalloc(&p, bytes));
@@ -620,23 +917,34 @@ fcc_status upload(const std::vector<T>& v, const T** out) {
       return hip_fail(e, "hipMemcpy(tables)", __LINE__);
     }
   }
-  cache().owned.push_back(p);
+  (own ? own : &cache().owned)->push_back(p);
   *out = static_cast<const T*>(p);
   return FCC_OK;
 }
 
 // Sliced copy of one side's gather rows (see DevSide).  rowptr is the CSR of
 // rows cube * 8 + f; zero_pid names a polynomial equal to zero.
+// Sliced device copy of one side (B or C) of the tables, cube order `ord`.
 fcc_status upload_side(const std::vector<int>& rowptr, const std::vector<uint32_t>& src,
-                       const std::vector<uint16_t>& pid, int S, uint16_t zero_pid, DevSide* out) {
+                       const std::vector<uint16_t>& pid, const DevPolys& dp, int S, CubeOrder ord, DevSide* out,
+                       std::vector<void*>* own) {
   const int rows = int(rowptr.size()) - 1, cubes = rows / 8, slices = (cubes + S - 1) / S;
+  int m = 1, lgm = 0;
+  while (m * m * m < cubes) m *= 2, ++lgm;
+  // natural cube index of the q-th cube in the slice order
+  std::vector<int> nat(cubes);
+  for (int q = 0; q < cubes; ++q) {
+    int a[3];
+    cube_abc(q, lgm, ord, a);
+    nat[q] = (a[0] * m + a[1]) * m + a[2];
+  }
   std::vector<int> start(size_t(slices) * 8), len(size_t(slices) * 8);
   size_t total = 0;
   for (int sl = 0; sl < slices; ++sl)
     for (int f = 0; f < 8; ++f) {
       int mx = 0;
       for (int j = 0; j < S && sl * S + j < cubes; ++j) {
-        const int r = (sl * S + j) * 8 + f;
+        const int r = nat[sl * S + j] * 8 + f;
         mx = std::max(mx, rowptr[r + 1] - rowptr[r]);
       }
       start[size_t(sl) * 8 + f] = int(total);
@@ -645,30 +953,33 @@ fcc_status upload_side(const std::vector<int>& rowptr, const std::vector<uint32_
     }
   if (total > 0x7fffffffu) return FCC_ERR_UNSUPPORTED;
   std::vector<uint32_t> ssrc(total, 0u);
-  std::vector<uint16_t> spid(total, zero_pid);
+  std::vector<uint16_t> spid(total, dp.zero_pid);
   for (int sl = 0; sl < slices; ++sl)
     for (int f = 0; f < 8; ++f)
       for (int j = 0; j < S && sl * S + j < cubes; ++j) {
-        const int r = (sl * S + j) * 8 + f;
+        const int r = nat[sl * S + j] * 8 + f;
         for (int e = 0; e < rowptr[r + 1] - rowptr[r]; ++e) {
           const size_t q = size_t(start[size_t(sl) * 8 + f]) + size_t(e) * S + j;
           ssrc[q] = src[rowptr[r] + e];
-          spid[q] = pid[rowptr[r] + e];
+          spid[q] = dp.newid[pid[rowptr[r] + e]];
         }
       }
   fcc_status s;
-  if ((s = upload(start, &out->start)) != FCC_OK) return s;
-  if ((s = upload(len, &out->len)) != FCC_OK) return s;
-  if ((s = upload(ssrc, &out->src)) != FCC_OK) return s;
-  return upload(spid, &out->pid);
+  if ((s = upload(start, &out->start, own)) != FCC_OK) return s;
+  if ((s = upload(len, &out->len, own)) != FCC_OK) return s;
+  if ((s = upload(ssrc, &out->src, own)) != FCC_OK) return s;
+  out->order = ord;
+  return upload(spid, &out->pid, own);
 }
 
-fcc_status device_level(int dev, int nl, int S, DevLevel* out) {
+// The polynomials of node size nl on device dev (cached; caller holds the
+// cache lock).
+fcc_status device_polys(int dev, int nl, const DevPolys** out) {
   auto& C = cache();
-  std::array<int, 3> key{dev, nl, S};
-  auto it = C.levels.find(key);
-  if (it != C.levels.end()) {
-    *out = it->second;
+  std::array<int, 2> key{dev, nl};
+  auto it = C.polys.find(key);
+  if (it != C.polys.end()) {
+    *out = &it->second;
     return FCC_OK;
   }
   const LevelTables* T = level_tables(nl);
@@ -689,7 +1000,7 @@ fcc_status device_level(int dev, int nl, int S, DevLevel* out) {
     if (sl < 0) return FCC_ERR_UNSUPPORTED;
     for (int p = 0; p < T->npoly; ++p) fixed[size_t(p) * kNumMono + sl] = T->poly[size_t(p) * T->nmono + q];
   }
-  std::vector<int> order(T->npoly), newid(T->npoly);
+  std::vector<int> order(T->npoly);
   for (int p = 0; p < T->npoly; ++p) order[p] = p;
   auto is_const = [&](int p) {
     for (int q = 1; q < kNumMono; ++q)
@@ -702,27 +1013,61 @@ fcc_status device_level(int dev, int nl, int S, DevLevel* out) {
   // one extra constant polynomial equal to zero pads the sliced tables
   order.insert(order.begin() + nconst, -1);
   ++nconst;
-  const uint16_t zero_pid = uint16_t(nconst - 1);
-  newid.resize(T->npoly + 1);
+  DevPolys dp;
+  dp.zero_pid = uint16_t(nconst - 1);
+  dp.newid.resize(T->npoly);
   std::vector<double> poly(fixed.size() + kNumMono, 0.0);
   for (int i = 0; i <= T->npoly; ++i) {
     if (order[i] < 0) continue;
-    newid[order[i]] = i;
+    dp.newid[order[i]] = uint16_t(i);
     for (int q = 0; q < kNumMono; ++q) poly[size_t(i) * kNumMono + q] = fixed[size_t(order[i]) * kNumMono + q];
   }
-  std::vector<uint16_t> bp(T->b_pid.size()), cp(T->c_pid.size());
-  for (size_t e = 0; e < bp.size(); ++e) bp[e] = (uint16_t)newid[T->b_pid[e]];
-  for (size_t e = 0; e < cp.size(); ++e) cp[e] = (uint16_t)newid[T->c_pid[e]];
+  dp.nconst = nconst;
+  dp.npoly = T->npoly + 1;
+  if (dp.npoly > kMaxPoly) return FCC_ERR_UNSUPPORTED;
+  fcc_status s = upload(poly, &dp.poly);
+  if (s != FCC_OK) return s;
+  *out = &C.polys.emplace(key, std::move(dp)).first->second;
+  return FCC_OK;
+}
+
+// One side (0 = B, 1 = C) of node size nl, S cubes per slice, cube order ord.
+// With own == nullptr the tables are cached for the process; otherwise they
+// are built afresh and their allocations appended to *own for the caller to
+// free.  The caller holds the cache lock.
+fcc_status device_side(int dev, int nl, int S, int side, CubeOrder ord, DevSide* out, std::vector<void*>* own) {
+  auto& C = cache();
+  std::array<int, 5> key{dev, nl, S, side, (ord.la << 16) | (ord.lb << 8) | ord.lc};
+  if (!own) {
+    auto it = C.sides.find(key);
+    if (it != C.sides.end()) {
+      *out = it->second;
+      return FCC_OK;
+    }
+  }
+  const LevelTables* T = level_tables(nl);
+  if (!T) return FCC_ERR_OOM;
+  const DevPolys* dp = nullptr;
+  fcc_status s = device_polys(dev, nl, &dp);
+  if (s != FCC_OK) return s;
+  s = side == 0 ? upload_side(T->b_rowptr, T->b_src, T->b_pid, *dp, S, ord, out, own)
+                : upload_side(T->c_rowptr, T->c_src, T->c_pid, *dp, S, ord, out, own);
+  if (s == FCC_OK && !own) C.sides.emplace(key, *out);
+  return s;
+}
+
+// Both sides of node size nl (cached), B in order ob and C in order oc.
+fcc_status device_level(int dev, int nl, int S, CubeOrder ob, CubeOrder oc, DevLevel* out) {
+  const DevPolys* dp = nullptr;
+  fcc_status s = device_polys(dev, nl, &dp);
+  if (s != FCC_OK) return s;
   DevLevel lv{};
-  fcc_status s;
-  if ((s = upload_side(T->b_rowptr, T->b_src, bp, S, zero_pid, &lv.b)) != FCC_OK) return s;
-  if ((s = upload_side(T->c_rowptr, T->c_src, cp, S, zero_pid, &lv.c)) != FCC_OK) return s;
-  if ((s = upload(poly, &lv.poly)) != FCC_OK) return s;
-  lv.nconst = nconst;
-  lv.npoly = T->npoly + 1;
-  if (lv.npoly > kMaxPoly) return FCC_ERR_UNSUPPORTED;
+  if ((s = device_side(dev, nl, S, 0, ob, &lv.b, nullptr)) != FCC_OK) return s;
+  if ((s = device_side(dev, nl, S, 1, oc, &lv.c, nullptr)) != FCC_OK) return s;
+  lv.poly = dp->poly;
+  lv.npoly = dp->npoly;
+  lv.nconst = dp->nconst;
   lv.S = S;
-  C.levels.emplace(key, lv);
   *out = lv;
   return FCC_OK;
 }
@@ -799,16 +1144,26 @@ const NodeConst* nodes_of(const fcc_plan_s* p, int L) {
   return (p->nodes && p->node_off[L] >= 0) ? static_cast<const NodeConst*>(p->nodes) + p->node_off[L] : nullptr;
 }
 
+// thread map of the gather pass of direction d (0 forward, 1 inverse) at level L
+// (f_inner needs whole slices: the node must have at least S cubes)
+GatherMap gmap(const fcc_plan_s* p, int d, int L) {
+  if (L > 1) return GatherMap{0, 0};
+  const unsigned m = p->tune.map[d][L];
+  const long long half = p->n >> (L + 1), cubes = half * half * half;
+  const bool whole = cubes >= p->lv[L].S;
+  return GatherMap{int(m & FCC_MAP_XCD), int(whole && (m & FCC_MAP_F_INNER) != 0)};
+}
+
 template <typename R>
 void fwd_gather_dispatch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, int nvol, hipStream_t st) {
   dim3 g = grid_points(p->n, nvol);
   const double2* h = phases(p, L);
   const NodeConst* nc = nodes_of(p, L);
   switch (ti) {
-    case DT::F32R: hipLaunchKernelGGL((k_fwd_gather<R, float>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc); break;
-    case DT::F64R: hipLaunchKernelGGL((k_fwd_gather<R, double>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc); break;
-    case DT::F32C: hipLaunchKernelGGL((k_fwd_gather<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc); break;
-    case DT::F64C: hipLaunchKernelGGL((k_fwd_gather<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc); break;
+    case DT::F32R: hipLaunchKernelGGL((k_fwd_gather<R, float>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 0, L)); break;
+    case DT::F64R: hipLaunchKernelGGL((k_fwd_gather<R, double>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 0, L)); break;
+    case DT::F32C: hipLaunchKernelGGL((k_fwd_gather<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 0, L)); break;
+    case DT::F64C: hipLaunchKernelGGL((k_fwd_gather<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 0, L)); break;
   }
 }
 template <typename R>
@@ -838,11 +1193,72 @@ void inv_basis_dispatch(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int
   const double2* h = phases(p, L);
   const NodeConst* nc = nodes_of(p, L);
   switch (to) {
-    case DT::F32R: hipLaunchKernelGGL((k_inv_basis<R, float>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc); break;
-    case DT::F64R: hipLaunchKernelGGL((k_inv_basis<R, double>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc); break;
-    case DT::F32C: hipLaunchKernelGGL((k_inv_basis<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc); break;
-    case DT::F64C: hipLaunchKernelGGL((k_inv_basis<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc); break;
+    case DT::F32R: hipLaunchKernelGGL((k_inv_basis<R, float>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 1, L)); break;
+    case DT::F64R: hipLaunchKernelGGL((k_inv_basis<R, double>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 1, L)); break;
+    case DT::F32C: hipLaunchKernelGGL((k_inv_basis<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 1, L)); break;
+    case DT::F64C: hipLaunchKernelGGL((k_inv_basis<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 1, L)); break;
   }
+}
+
+TailLevels tail_levels(const fcc_plan_s* p, int Lt) {
+  TailLevels tl{};
+  for (int l = 0; l < p->D - Lt; ++l) {
+    tl.lv[l] = p->tlv[Lt + l];
+    tl.nodes[l] = nodes_of(p, Lt + l);
+    tl.hph[l] = phases(p, Lt + l);
+  }
+  return tl;
+}
+// As many sibling nodes per block as the LDS buffer holds (within one row of
+// J_z), fewer while the launch would have under 2048 blocks.
+TailGeom tail_geom(const fcc_plan_s* p, int Lt, int nvol) {
+  TailGeom g;
+  g.n = p->n;
+  g.Lt = Lt;
+  g.nl0 = p->n >> Lt;
+  g.k = p->D - Lt;
+  g.G = std::min(kTailG * kTailPts / (g.nl0 * g.nl0 * g.nl0), 1 << Lt);
+  while (g.G > 1 && (1LL << (3 * g.Lt)) / g.G * nvol < 2048) g.G >>= 1;
+  return g;
+}
+dim3 tail_grid(const TailGeom& g, int nvol) { return dim3(unsigned(((1LL << (3 * g.Lt)) / g.G) * nvol)); }
+dim3 tail_block_dim(const TailGeom& g) { return dim3(unsigned(std::max(64, g.G * g.nl0 * g.nl0 * g.nl0 / 8))); }
+template <typename R, typename TI>
+void fwd_tail_out(const fcc_plan_s* p, DT to, const VolSet& vs, int nvol, hipStream_t st) {
+  const TailGeom g = tail_geom(p, p->tail_Lt[0], nvol);
+  const TailLevels tl = tail_levels(p, p->tail_Lt[0]);
+  if (to == DT::F32C)
+    hipLaunchKernelGGL((k_fwd_tail<R, TI, float2>), tail_grid(g, nvol), tail_block_dim(g), 0, st, vs, g, tl);
+  else
+    hipLaunchKernelGGL((k_fwd_tail<R, TI, double2>), tail_grid(g, nvol), tail_block_dim(g), 0, st, vs, g, tl);
+}
+template <typename R>
+void fwd_tail_dispatch(const fcc_plan_s* p, DT ti, DT to, const VolSet& vs, int nvol, hipStream_t st) {
+  switch (ti) {
+    case DT::F32R: fwd_tail_out<R, float>(p, to, vs, nvol, st); break;
+    case DT::F64R: fwd_tail_out<R, double>(p, to, vs, nvol, st); break;
+    case DT::F32C: fwd_tail_out<R, float2>(p, to, vs, nvol, st); break;
+    case DT::F64C: fwd_tail_out<R, double2>(p, to, vs, nvol, st); break;
+  }
+}
+template <typename R, typename TI>
+void inv_tail_out(const fcc_plan_s* p, DT to, const VolSet& vs, int nvol, hipStream_t st) {
+  const TailGeom g = tail_geom(p, p->tail_Lt[1], nvol);
+  const TailLevels tl = tail_levels(p, p->tail_Lt[1]);
+  const dim3 gr = tail_grid(g, nvol), bd = tail_block_dim(g);
+  switch (to) {
+    case DT::F32R: hipLaunchKernelGGL((k_inv_tail<R, TI, float>), gr, bd, 0, st, vs, g, tl); break;
+    case DT::F64R: hipLaunchKernelGGL((k_inv_tail<R, TI, double>), gr, bd, 0, st, vs, g, tl); break;
+    case DT::F32C: hipLaunchKernelGGL((k_inv_tail<R, TI, float2>), gr, bd, 0, st, vs, g, tl); break;
+    case DT::F64C: hipLaunchKernelGGL((k_inv_tail<R, TI, double2>), gr, bd, 0, st, vs, g, tl); break;
+  }
+}
+template <typename R>
+void inv_tail_dispatch(const fcc_plan_s* p, DT ti, DT to, const VolSet& vs, int nvol, hipStream_t st) {
+  if (ti == DT::F32C)
+    inv_tail_out<R, float2>(p, to, vs, nvol, st);
+  else
+    inv_tail_out<R, double2>(p, to, vs, nvol, st);
 }
 
 template <typename TI, typename TO>
@@ -888,8 +1304,8 @@ fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
   }
   VolPtrs src = in;
   DT src_t = in_type(p);
-  for (int L = 0; L < p->D; ++L) {
-    const bool last = L == p->D - 1;
+  for (int L = 0; L < p->tail_Lt[0]; ++L) {
+    const bool last = false;
     VolPtrs a = (L & 1) ? ws1 : ws0;
     // pass 1: basis-change gather into a; pass 2: DCT_2 on the cubes of a,
     // in place (or into the user's output at the last level)
@@ -908,6 +1324,12 @@ fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
     src = a;
     src_t = buf_type(p, L + 1);
   }
+  // the last levels (node size <= kTailNl) in one LDS-resident launch
+  if (p->stages64)
+    fwd_tail_dispatch<double>(p, src_t, cplx_type(p), VolSet{src, out}, nvol, st);
+  else
+    fwd_tail_dispatch<float>(p, src_t, cplx_type(p), VolSet{src, out}, nvol, st);
+  if (tm) tm->mark(st);
   return launch_status("forward level launch");
 }
 
@@ -919,10 +1341,21 @@ fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
     copy1_dispatch(cplx_type(p), real_or_cplx, VolSet{in, out}, nvol, st);
     return launch_status("inverse n=1 launch");
   }
-  VolPtrs cur = in;
-  bool cur_is_user = true;
+  // the last levels first, in one LDS-resident launch
+  {
+    const int Lt = p->tail_Lt[1];
+    VolPtrs dst = Lt == 0 ? out : ws0;
+    DT to = Lt == 0 ? real_or_cplx : buf_type(p, Lt);
+    if (p->stages64)
+      inv_tail_dispatch<double>(p, cplx_type(p), to, VolSet{in, dst}, nvol, st);
+    else
+      inv_tail_dispatch<float>(p, cplx_type(p), to, VolSet{in, dst}, nvol, st);
+    if (tm) tm->mark(st);
+  }
+  VolPtrs cur = ws0;
+  bool cur_is_user = false;
   int which = 0;  // scratch array holding the current level's data
-  for (int L = p->D - 1; L >= 0; --L) {
+  for (int L = p->tail_Lt[1] - 1; L >= 0; --L) {
     VolPtrs a = which ? ws1 : ws0;
     VolPtrs b = which ? ws0 : ws1;
     // the DCT_2^{-1} pass reads level L+1's result (or the user's X) and
@@ -995,7 +1428,8 @@ void free_batch(BatchExec* b) {
 
 bool same_config(const fcc_plan_s* a, const fcc_plan_s* b) {
   return a->n == b->n && a->prec == b->prec && a->flags == b->flags && a->stages64 == b->stages64 &&
-         a->dense == b->dense && a->rst[0] == b->rst[0] && a->rst[1] == b->rst[1] && a->rst[2] == b->rst[2];
+         a->dense == b->dense && a->rst[0] == b->rst[0] && a->rst[1] == b->rst[1] && a->rst[2] == b->rst[2] &&
+         std::memcmp(&a->tune, &b->tune, sizeof a->tune) == 0;
 }
 
 // Resources of one group, allocated before capture (no allocation or
@@ -1142,8 +1576,73 @@ fcc_status fcc_asp_tables(int nl, fcc_level_tables* out) {
   return FCC_OK;
 }
 
+namespace {
+// Built-in schedule: the autotuner's choice on MI355X at n = 128 and 256.
+fcc_tuning default_tuning(int n) {
+  fcc_tuning t{};
+  t.tail_levels[0] = n <= 64 ? 1 : 2;
+  t.tail_levels[1] = 1;
+  for (int a = 0; a < 3; ++a) {
+    t.tile[0][0][a] = 2;  // forward level 0: 4x4x4 cube tiles
+    t.tile[0][1][a] = 1;  // forward level 1: 2x2x2
+    t.tile[1][0][a] = 2;  // inverse levels 0 and 1: 4x4x4, the 8 rows of a cube together
+    t.tile[1][1][a] = 2;
+  }
+  t.map[1][0] = FCC_MAP_F_INNER;
+  t.map[1][1] = FCC_MAP_F_INNER;
+  return t;
+}
+bool valid_tuning(const fcc_tuning& t) {
+  for (int d = 0; d < 2; ++d) {
+    if (t.tail_levels[d] < 1 || t.tail_levels[d] > 3) return false;
+    for (int L = 0; L < 2; ++L) {
+      if (t.map[d][L] & ~unsigned(FCC_MAP_XCD | FCC_MAP_F_INNER)) return false;
+      for (int a = 0; a < 3; ++a)
+        if (t.tile[d][L][a] < 0 || t.tile[d][L][a] > 9) return false;
+    }
+  }
+  return true;
+}
+// The plan's copy of the schedule, tile sides clamped to its node sizes.
+void resolve_tuning(fcc_plan_s* p, const fcc_tuning& t) {
+  p->tune = t;
+  for (int d = 0; d < 2; ++d) {
+    p->tail_Lt[d] = std::max(0, p->D - t.tail_levels[d]);
+    for (int L = 0; L < 2; ++L)
+      for (int a = 0; a < 3; ++a) p->tune.tile[d][L][a] = std::min(t.tile[d][L][a], std::max(0, p->D - L - 1));
+  }
+}
+// Cube order of the gather tables of direction d at level L.
+CubeOrder tile_order(const fcc_plan_s* p, int d, int L) {
+  if (L > 1) return CubeOrder{0, 0, 0};
+  return CubeOrder{p->tune.tile[d][L][0], p->tune.tile[d][L][1], p->tune.tile[d][L][2]};
+}
+int slice_cubes(int L) { return L == 0 ? 64 : (L == 1 ? 8 : 1); }
+
+// Schedules found by fcc_dct_autotune, per (device, n, precision, flags).
+std::mutex& tuned_mu() {
+  static std::mutex m;
+  return m;
+}
+std::map<std::array<int, 4>, fcc_tuning>& tuned() {
+  static std::map<std::array<int, 4>, fcc_tuning> t;
+  return t;
+}
+}  // namespace
+
 fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precision prec, unsigned flags,
                         void* hip_stream) {
+  return fcc_dct_plan_tuned(plan, n, rst, prec, flags, nullptr, hip_stream);
+}
+
+fcc_status fcc_dct_get_tuning(fcc_plan_t p, fcc_tuning* out) {
+  if (!p || !out) return FCC_ERR_INVALID_ARG;
+  *out = p->tune;
+  return FCC_OK;
+}
+
+fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_precision prec, unsigned flags,
+                              const fcc_tuning* tuning, void* hip_stream) {
   if (!plan) return FCC_ERR_INVALID_ARG;
   *plan = nullptr;
   if (!is_pow2(n)) return FCC_ERR_NOT_POW2;
@@ -1151,6 +1650,7 @@ fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precis
   if ((flags & FCC_STAGES_FP32) && (flags & FCC_STAGES_FP64)) return FCC_ERR_INVALID_ARG;
   if (flags & ~(unsigned)(FCC_REAL_INPUT | FCC_STAGES_FP32 | FCC_STAGES_FP64 | FCC_LEVEL0_FP32))
     return FCC_ERR_INVALID_ARG;
+  if (tuning && !valid_tuning(*tuning)) return FCC_ERR_INVALID_ARG;
   if ((prec == FCC_PREC_SPLIT_BF16 || prec == FCC_PREC_SPLIT_FP16) && n > 8) return FCC_ERR_UNSUPPORTED;
   double r[3] = {0.125, 0.0, 0.375};
   if (rst)
@@ -1182,17 +1682,42 @@ fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precis
   // the well-conditioned children, but it raises the round-trip error from
   // ~5e-8 to ~4e-6 at n = 32..128 (measured), so it is not the default.
   p->level0_fp32 = (flags & FCC_LEVEL0_FP32) && prec == FCC_PREC_FP32 && p->stages64 && p->D >= 2;
+  {
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+      delete p;
+      return hip_fail(e, "hipGetDevice", __LINE__);
+    }
+  }
+  if (tuning) {
+    resolve_tuning(p, *tuning);
+  } else {
+    fcc_tuning t = default_tuning(n);
+    {
+      std::lock_guard<std::mutex> lock(tuned_mu());
+      auto it = tuned().find({p->device, n, int(prec), int(flags)});
+      if (it != tuned().end()) t = it->second;
+    }
+    resolve_tuning(p, t);
+  }
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   fcc_status s = FCC_OK;
   (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
   {
     std::lock_guard<std::mutex> lock(cache().mu);
-    hipError_t e = hipGetDevice(&p->device);
-    if (e != hipSuccess) s = hip_fail(e, "hipGetDevice", __LINE__);
     for (int L = 0; s == FCC_OK && L < p->D; ++L) {
       DevLevel lv;
-      s = device_level(p->device, n >> L, L == 0 ? 64 : (L == 1 ? 8 : 1), &lv);
+      s = device_level(p->device, n >> L, slice_cubes(L), tile_order(p, 0, L), tile_order(p, 1, L), &lv);
       p->lv.push_back(lv);
+    }
+    // plain-order tables with one cube per slice for every level a fused
+    // tail may cover (node sizes <= 8); levels >= 2 have them already
+    p->tlv.resize(p->D);
+    for (int L = std::max(0, p->D - 3); s == FCC_OK && L < p->D; ++L) {
+      if (L >= 2)
+        p->tlv[L] = p->lv[L];
+      else
+        s = device_level(p->device, n >> L, 1, CubeOrder{0, 0, 0}, CubeOrder{0, 0, 0}, &p->tlv[L]);
     }
   }
   if (s == FCC_OK && p->D > 0) {
@@ -1296,15 +1821,13 @@ fcc_status fcc_dct_inverse(fcc_plan_t p, const void* X, void* x, void* hip_strea
                          static_cast<hipStream_t>(hip_stream));
 }
 
-fcc_status fcc_dct_time_launches(fcc_plan_t p, const void* in, void* out, int direction, int reps, float* ms,
-                                 int cap, int* count, void* hip_stream) {
-  if (!p || !in || !out || !count || reps < 1 || (direction != 1 && direction != -1)) return FCC_ERR_INVALID_ARG;
-  if (!aligned16(in) || !aligned16(out) || in == out) return FCC_ERR_INVALID_ARG;
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  const int slots = (p->n == 1 || p->dense) ? 1 : 2 * p->D;
-  *count = slots;
-  if (!ms || cap < slots) return ms ? FCC_ERR_INVALID_ARG : FCC_OK;
-  (void)hipGetLastError();
+namespace {
+// Average duration (ms) of each launch slot of `reps` transforms in direction
+// +1 (forward) or -1 (inverse), timed with events around every launch.
+fcc_status time_slots(const fcc_plan_s* p, const void* in, void* out, int direction, int reps, hipStream_t st,
+                      std::vector<float>* ms) {
+  const int slots = (p->n == 1 || p->dense) ? 1 : 2 * p->tail_Lt[direction > 0 ? 0 : 1] + 1;
+  ms->assign(slots, 0.f);
   std::vector<hipEvent_t> ev(size_t(slots + 1) * reps, nullptr);
   fcc_status s = FCC_OK;
   for (auto& e : ev) {
@@ -1340,10 +1863,160 @@ fcc_status fcc_dct_time_launches(fcc_plan_t p, const void* in, void* out, int di
         (void)hipEventElapsedTime(&t, ev[size_t(r) * (slots + 1) + k], ev[size_t(r) * (slots + 1) + k + 1]);
         acc += t;
       }
-      ms[k] = float(acc / reps);
+      (*ms)[k] = float(acc / reps);
     }
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
+  return s;
+}
+}  // namespace
+
+fcc_status fcc_dct_time_launches(fcc_plan_t p, const void* in, void* out, int direction, int reps, float* ms,
+                                 int cap, int* count, void* hip_stream) {
+  if (!p || !in || !out || !count || reps < 1 || (direction != 1 && direction != -1)) return FCC_ERR_INVALID_ARG;
+  if (!aligned16(in) || !aligned16(out) || in == out) return FCC_ERR_INVALID_ARG;
+  const int slots = (p->n == 1 || p->dense) ? 1 : 2 * p->tail_Lt[direction > 0 ? 0 : 1] + 1;
+  *count = slots;
+  if (!ms || cap < slots) return ms ? FCC_ERR_INVALID_ARG : FCC_OK;
+  (void)hipGetLastError();
+  std::vector<float> v;
+  fcc_status s = time_slots(p, in, out, direction, reps, static_cast<hipStream_t>(hip_stream), &v);
+  if (s == FCC_OK) std::copy(v.begin(), v.end(), ms);
+  return s;
+}
+
+fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsigned flags, int reps,
+                            fcc_tuning* best, void* hip_stream) {
+  if (reps < 1) return FCC_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  fcc_plan_t p = nullptr;
+  fcc_status s = fcc_dct_plan_tuned(&p, n, rst, prec, flags, nullptr, hip_stream);
+  if (s != FCC_OK) return s;
+  if (!p->dense && p->D >= 2) {
+    // synthetic operands: the forward input and a complex array for the
+    // forward output / inverse input
+    const long long N = (long long)n * n * n;
+    const size_t el = (p->prec == FCC_PREC_FP64) ? sizeof(double) : sizeof(float);
+    void* a = nullptr;
+    void* b = nullptr;
+    hipError_t e = hipMalloc(&a, 2 * el * N);
+    if (e == hipSuccess) e = hipMalloc(&b, 2 * el * N);
+    if (e != hipSuccess) s = hip_fail(e, "hipMalloc(autotune operands)", __LINE__);
+    if (s == FCC_OK) {
+      const unsigned blocks = unsigned(std::min<long long>((2 * N + 255) / 256, 65535));
+      if (el == sizeof(double)) {
+        hipLaunchKernelGGL(k_fill<double>, dim3(blocks), dim3(256), 0, st, static_cast<double*>(a), 2 * N, 1u);
+        hipLaunchKernelGGL(k_fill<double>, dim3(blocks), dim3(256), 0, st, static_cast<double*>(b), 2 * N, 2u);
+      } else {
+        hipLaunchKernelGGL(k_fill<float>, dim3(blocks), dim3(256), 0, st, static_cast<float*>(a), 2 * N, 1u);
+        hipLaunchKernelGGL(k_fill<float>, dim3(blocks), dim3(256), 0, st, static_cast<float*>(b), 2 * N, 2u);
+      }
+      s = launch_status("autotune fill");
+    }
+    std::vector<float> ms;
+    auto total = [&](int d, double* out) {
+      fcc_status r = d == 0 ? time_slots(p, a, b, 1, reps, st, &ms) : time_slots(p, b, a, -1, reps, st, &ms);
+      double t = 0.0;
+      for (float v : ms) t += v;
+      *out = t;
+      return r;
+    };
+    for (int d = 0; d < 2 && s == FCC_OK; ++d) {
+      // 1. fused tail depth, by whole-direction time
+      int best_k = p->tune.tail_levels[d];
+      double best_t = 1e30;
+      for (int k = 1; k <= std::min(3, p->D) && s == FCC_OK; ++k) {
+        p->tune.tail_levels[d] = k;
+        p->tail_Lt[d] = std::max(0, p->D - k);
+        double t = 0.0;
+        s = total(d, &t);
+        if (verbose()) std::fprintf(stderr, "fcc_autotune n=%d dir=%d tail_levels=%d: %.4f ms\n", n, d, k, t);
+        if (s == FCC_OK && t < best_t) best_t = t, best_k = k;
+      }
+      p->tune.tail_levels[d] = best_k;
+      p->tail_Lt[d] = std::max(0, p->D - best_k);
+      // 2. tile shape and block map of the level-0 and level-1 gather passes,
+      // by the time of that launch
+      static const int tiles0[][3] = {{0, 0, 0}, {2, 2, 2}, {1, 2, 3}, {0, 3, 3}, {3, 3, 3}, {2, 2, 4}};
+      static const int tiles1[][3] = {{0, 0, 0}, {1, 1, 1}, {0, 1, 2}, {2, 2, 2}};
+      for (int L = 0; L < 2 && L < p->tail_Lt[d] && s == FCC_OK; ++L) {
+        const int lgm = p->D - L - 1;
+        const int slot = d == 0 ? 2 * L : 2 * (p->tail_Lt[d] - L);
+        const int ntiles = L == 0 ? 6 : 4;
+        DevSide& cur = d == 0 ? p->lv[L].b : p->lv[L].c;
+        DevSide best_side = cur;
+        fcc_tuning best_t2 = p->tune;
+        double best_ms = 1e30;
+        std::vector<void*> keep;  // allocations of the winning side if not cached
+        for (int ti = 0; ti < ntiles && s == FCC_OK; ++ti) {
+          const int* tt = L == 0 ? tiles0[ti] : tiles1[ti];
+          const CubeOrder o{std::min(tt[0], lgm), std::min(tt[1], lgm), std::min(tt[2], lgm)};
+          bool dup = false;  // the same clamped shape as an earlier candidate
+          for (int tj = 0; tj < ti; ++tj) {
+            const int* uu = L == 0 ? tiles0[tj] : tiles1[tj];
+            dup |= std::min(uu[0], lgm) == o.la && std::min(uu[1], lgm) == o.lb && std::min(uu[2], lgm) == o.lc;
+          }
+          if (dup) continue;
+          std::vector<void*> own;
+          DevSide cand{};
+          {
+            std::lock_guard<std::mutex> lock(cache().mu);
+            std::array<int, 5> key{p->device, n >> L, slice_cubes(L), d, (o.la << 16) | (o.lb << 8) | o.lc};
+            auto it = cache().sides.find(key);
+            if (it != cache().sides.end())
+              cand = it->second;
+            else
+              s = device_side(p->device, n >> L, slice_cubes(L), d, o, &cand, &own);
+          }
+          bool won = false;
+          for (unsigned mp = 0; mp < 4 && s == FCC_OK; ++mp) {
+            cur = cand;
+            p->tune.tile[d][L][0] = o.la;
+            p->tune.tile[d][L][1] = o.lb;
+            p->tune.tile[d][L][2] = o.lc;
+            p->tune.map[d][L] = mp;
+            s = d == 0 ? time_slots(p, a, b, 1, reps, st, &ms) : time_slots(p, b, a, -1, reps, st, &ms);
+            if (s != FCC_OK) break;
+            if (verbose())
+              std::fprintf(stderr, "fcc_autotune n=%d dir=%d level=%d tile=(%d,%d,%d) map=%u: %.4f ms\n", n, d, L, o.la,
+                           o.lb, o.lc, mp, ms[slot]);
+            if (ms[slot] < best_ms) {
+              best_ms = ms[slot];
+              best_side = cand;
+              best_t2 = p->tune;
+              won = true;
+            }
+          }
+          if (won) {
+            for (void* q : keep) (void)hipFree(q);
+            keep = own;
+          } else {
+            for (void* q : own) (void)hipFree(q);
+          }
+        }
+        cur = best_side;
+        p->tune = best_t2;
+        if (!keep.empty()) {
+          // the winner becomes the cached table of its key
+          std::lock_guard<std::mutex> lock(cache().mu);
+          const CubeOrder o{best_t2.tile[d][L][0], best_t2.tile[d][L][1], best_t2.tile[d][L][2]};
+          cache().sides.emplace(std::array<int, 5>{p->device, n >> L, slice_cubes(L), d,
+                                                   (o.la << 16) | (o.lb << 8) | o.lc},
+                                best_side);
+          cache().owned.insert(cache().owned.end(), keep.begin(), keep.end());
+        }
+      }
+    }
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+  }
+  fcc_tuning t = p->tune;
+  if (s == FCC_OK) {
+    std::lock_guard<std::mutex> lock(tuned_mu());
+    tuned()[{p->device, n, int(prec), int(flags)}] = t;
+    if (best) *best = t;
+  }
+  fcc_dct_destroy(p);
   return s;
 }
 

@@ -94,6 +94,21 @@ struct IO<cx<R2>, R> {
 // c = (sigma, tau, rho) of the node, in that order.
 constexpr int kNumMono = 5;
 
+// Order of a node's m^3 cubes in the sliced tables and in the thread map of
+// the gather passes: tiles of 2^la x 2^lb x 2^lc cubes in lexicographic tile
+// order, lexicographic inside a tile.  (0,0,0) is the plain order (a*m+b)*m+c.
+struct CubeOrder {
+  int la, lb, lc;
+};
+__host__ __device__ __forceinline__ void cube_abc(int q, int lgm, CubeOrder o, int a[3]) {
+  const int li = o.la + o.lb + o.lc;
+  const int inner = q & ((1 << li) - 1), tile = q >> li;
+  const int ntc = lgm - o.lc, ntb = lgm - o.lb;
+  a[2] = ((tile & ((1 << ntc) - 1)) << o.lc) | (inner & ((1 << o.lc) - 1));
+  a[1] = (((tile >> ntc) & ((1 << ntb) - 1)) << o.lb) | ((inner >> o.lc) & ((1 << o.lb) - 1));
+  a[0] = ((tile >> (ntc + ntb)) << o.la) | (inner >> (o.lb + o.lc));
+}
+
 // Device view of the basis-change tables of one node size, sliced for the
 // wavefronts that read them: the rows of S consecutive cubes form a slice; for
 // each def (or i) the slice stores max-length entries interleaved cube by cube
@@ -105,6 +120,7 @@ struct DevSide {
   const int* len;       // per (slice * 8 + f)
   const uint32_t* src;  // packed node-local position
   const uint16_t* pid;  // coefficient polynomial
+  CubeOrder order;      // cube order of the slices
 };
 struct DevLevel {
   DevSide b, c;        // forward B_nl, inverse C_nl
@@ -112,6 +128,14 @@ struct DevLevel {
   int npoly;
   int nconst;          // ids below nconst are constants
   int S;               // cubes per slice
+};
+
+// Thread map of a gather pass.  xcd: the blocks that the hardware deals
+// round-robin to the 8 XCDs are renumbered so that each XCD works through one
+// contiguous range of rows.  f_inner: the 8 rows f of one table slice are
+// consecutive (otherwise f is the slowest index).
+struct GatherMap {
+  int xcd, f_inner;
 };
 
 // Where the volumes of one launch live: one volume at `one` (arr == nullptr)

@@ -35,6 +35,9 @@ struct fcc_plan_s {
   unsigned long long* resid = nullptr;  // 2 words for fcc_dct_roundtrip_residual
   void* nodes = nullptr;                // FP64 node constants of the upper levels
   long long node_off[16] = {};          // per level offset into nodes, -1 if none
+  fcc_tuning tune{};                    // the schedule, sizes clamped to this n
+  int tail_Lt[2] = {0, 0};              // first level of the fused LDS tail: [0] forward, [1] inverse
+  std::vector<fcc::DevLevel> tlv;       // per level from min(tail_Lt) on: plain-order tables, S = 1
 };
 
 namespace fcc {

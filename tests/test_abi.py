@@ -66,3 +66,32 @@ def test_tables_reject_bad_sizes():
     for nl in (1, 3, 2048):
         with pytest.raises(fcc.FccError):
             fcc.fcc_asp_tables(nl)
+
+
+def _tuning(**kw):
+    t = {"tail_levels": [1, 1], "tile": [[[0, 0, 0], [0, 0, 0]], [[0, 0, 0], [0, 0, 0]]], "map": [[0, 0], [0, 0]]}
+    t.update(kw)
+    return t
+
+
+@pytest.mark.parametrize("bad", [
+    {"tail_levels": [0, 1]}, {"tail_levels": [1, 4]},
+    {"tile": [[[0, 0, -1], [0, 0, 0]], [[0, 0, 0], [0, 0, 0]]]},
+    {"tile": [[[0, 0, 0], [0, 0, 0]], [[0, 10, 0], [0, 0, 0]]]},
+    {"map": [[4, 0], [0, 0]]},
+])
+def test_plan_tuned_rejects_bad_schedules(bad):
+    # validated before any device work, so this runs without a GPU
+    with pytest.raises(fcc.FccError) as e:
+        fcc.fcc_dct_plan_tuned(8, tuning=_tuning(**bad), stream=0)
+    assert e.value.status == 1
+
+
+def test_tuning_entry_points_reject_bad_arguments():
+    lib = ctypes.CDLL(fcc.lib_path())
+    lib.fcc_dct_get_tuning.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    buf = ctypes.create_string_buffer(256)
+    assert lib.fcc_dct_get_tuning(None, buf) == 1
+    with pytest.raises(fcc.FccError) as e:
+        fcc.fcc_dct_autotune(8, reps=0, stream=0)
+    assert e.value.status == 1

@@ -1,0 +1,109 @@
+"""Schedules (fused-tail depth, tile shape and block map of the upper gather
+passes) through the C ABI: tile and map choices give bit-identical results,
+every tail depth matches the oracle, and the autotuner's choice is what later
+plans use."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1807_10058_amd as fcc
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+gu = pytest.importorskip("tests.gpu_util")
+
+
+def tuning(tail=(1, 1), tiles=((0, 0, 0), (0, 0, 0), (0, 0, 0), (0, 0, 0)), maps=(0, 0, 0, 0)):
+    """tiles/maps in the order (fwd L0, fwd L1, inv L0, inv L1)."""
+    return {"tail_levels": list(tail),
+            "tile": [[list(tiles[0]), list(tiles[1])], [list(tiles[2]), list(tiles[3])]],
+            "map": [[maps[0], maps[1]], [maps[2], maps[3]]]}
+
+
+SCHEDULES = [
+    tuning(),
+    tuning(tiles=((2, 2, 2), (1, 1, 1), (2, 2, 2), (2, 2, 2)), maps=(0, 0, 2, 2)),
+    tuning(tiles=((1, 2, 3), (0, 1, 2), (3, 3, 3), (1, 1, 1)), maps=(1, 3, 1, 3)),
+    tuning(tiles=((9, 9, 9), (9, 9, 9), (0, 3, 3), (2, 2, 4)), maps=(3, 2, 0, 1)),
+]
+
+
+def run(n, prec, flags, t, x):
+    plan = fcc.fcc_dct_plan_tuned(n, prec=prec, flags=flags, tuning=t)
+    real = bool(flags & fcc.FCC_REAL_INPUT)
+    X = torch.empty(n ** 3, dtype=gu.cdtype(prec), device=gu.DEV)
+    y = torch.empty_like(x)
+    fcc.fcc_dct_forward(plan, x, X)
+    fcc.fcc_dct_inverse(plan, X, y)
+    torch.cuda.synchronize()
+    out = X.cpu().numpy(), y.cpu().numpy(), fcc.fcc_dct_get_tuning(plan)
+    fcc.fcc_dct_destroy(plan)
+    assert real == (not torch.is_complex(x))
+    return out
+
+
+@pytest.mark.parametrize("n,prec", [(4, fcc.FCC_PREC_FP64), (16, fcc.FCC_PREC_FP32), (64, fcc.FCC_PREC_FP32),
+                                    (32, fcc.FCC_PREC_FP64)])
+def test_tile_and_map_choices_are_bit_identical(n, prec):
+    x = torch.from_numpy(workloads.uniform_fp64(n, 7)).to(gu.DEV, gu.rdtype(prec))
+    X0, y0, _ = run(n, prec, fcc.FCC_REAL_INPUT, SCHEDULES[0], x)
+    for t in SCHEDULES[1:]:
+        X1, y1, got = run(n, prec, fcc.FCC_REAL_INPUT, t, x)
+        assert np.array_equal(X0.view(np.uint8), X1.view(np.uint8)), (n, t)
+        assert np.array_equal(y0.view(np.uint8), y1.view(np.uint8)), (n, t)
+        lgm0 = max(0, n.bit_length() - 2)  # tile sides clamp to the node's cubes per side
+        assert all(v <= lgm0 for v in got["tile"][0][0])
+
+
+@pytest.mark.parametrize("tail", [(1, 1), (2, 3), (3, 2)])
+def test_every_tail_depth_matches_the_oracle(tail):
+    n = 16
+    x = workloads.uniform_fp64(n, 11)
+    ref = oracle.forward(x, n)
+    xt = torch.from_numpy(x).to(gu.DEV)
+    X, y, got = run(n, fcc.FCC_PREC_FP64, fcc.FCC_REAL_INPUT, tuning(tail=tail), xt)
+    assert got["tail_levels"] == list(tail)
+    assert gu.maxrel(X, ref) <= 1e-11
+    assert gu.maxrel(y, x) <= 1e-10
+
+
+@pytest.mark.parametrize("tail", [(1, 1), (3, 3)])
+def test_tail_depth_at_n64_fp32_sampled(tail):
+    n = 64
+    x = workloads.gaussian_field(n, 1)
+    rows = gu.sample_rows(n, 24, 3)
+    ref = oracle.forward_rows(x.astype(np.float64), n, rows)
+    X, y, _ = run(n, fcc.FCC_PREC_FP32, fcc.FCC_REAL_INPUT, tuning(tail=tail), torch.from_numpy(x).to(gu.DEV))
+    assert gu.maxrel(X[rows], ref) <= 1e-5
+    assert gu.maxrel(y, x) <= 1e-5
+
+
+def test_autotune_choice_is_used_by_later_plans():
+    n = 32
+    best = fcc.fcc_dct_autotune(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT, reps=2)
+    assert 1 <= best["tail_levels"][0] <= 3 and 1 <= best["tail_levels"][1] <= 3
+    plan = fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT)
+    assert fcc.fcc_dct_get_tuning(plan) == best
+    x = workloads.uniform_fp64(n, 5).astype(np.float32)
+    rows = gu.sample_rows(n, 16, 4)
+    X = torch.empty(n ** 3, dtype=torch.complex64, device=gu.DEV)
+    fcc.fcc_dct_forward(plan, torch.from_numpy(x).to(gu.DEV), X)
+    torch.cuda.synchronize()
+    assert gu.maxrel(X.cpu().numpy()[rows], oracle.forward_rows(x.astype(np.float64), n, rows)) <= 1e-5
+    fcc.fcc_dct_destroy(plan)
+
+
+def test_batched_groups_respect_schedules():
+    # two plans of the same n with different schedules in one batched call
+    n = 16
+    plans = [fcc.fcc_dct_plan_tuned(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT, tuning=t)
+             for t in (SCHEDULES[0], tuning(tail=(3, 2), tiles=((2, 2, 2),) * 4, maps=(2, 1, 2, 1)))]
+    xs = [workloads.uniform_fp64(n, 20 + i).astype(np.float32) for i in range(2)]
+    ins = [torch.from_numpy(x).to(gu.DEV) for x in xs]
+    outs = [torch.empty(n ** 3, dtype=torch.complex64, device=gu.DEV) for _ in xs]
+    fcc.fcc_dct_batched(plans, ins, outs, 1)
+    torch.cuda.synchronize()
+    for x, X in zip(xs, outs):
+        assert gu.maxrel(X.cpu().numpy(), oracle.forward(x.astype(np.float64), n)) <= 1e-5
