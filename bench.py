@@ -1,6 +1,7 @@
 """Benchmark of the fast FCC cosine transform on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5] [--no-cpu]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5] [--no-cpu] [--autotune]
+                [--copy-calibration]
 
 A step is one pass of the whole fast path over the workload's input, which is
 already resident in HBM.  Default workload (c2): one forward DCT_{64x64x64} of
@@ -39,35 +40,81 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="plan with the built-in schedule instead of searching it first (setup, untimed)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the workload, copy a 1 GiB device buffer once (the plain-copy reference for "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE scaling)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="search the schedule before planning (setup, untimed) instead of the built-in one")
     return ap.parse_args()
 
 
-def launch_bytes(n, prec, stages64, real_in, direction, tail_levels):
+def launch_bytes(n, prec, stages64, real_in, direction, sched):
     """Algorithmic bytes of each launch slot of a single-volume transform (each
-    element read once and written once)."""
+    element read once and written once), in the plan's launch order."""
     N = n ** 3
     io_c = 16 if prec == 0 else 8
     io_r = 8 if prec == 0 else 4
     st = 16 if stages64 else 8
     D = n.bit_length() - 1
-    Lt = max(0, D - tail_levels)  # levels Lt.. run in one fused LDS launch
+    SPLIT = 16
+    if n == 1:
+        return [("k_copy1", N * ((io_r if real_in else io_c) + io_c))]
     rin = io_r if real_in else io_c
     out = []
     if direction > 0:
+        Lt = max(0, D - sched["tail_levels"][0])  # levels Lt.. run in one fused LDS launch
         for L in range(Lt):
             bi = rin if L == 0 else st
-            out.append(("k_fwd_gather L%d" % L, N * (bi + st)))
-            out.append(("k_fwd_dct2 L%d" % L, N * (st + st)))
+            if sched["map"][0][L] & SPLIT:
+                out.append(("k_fwd_gather L%d" % L, N * (bi + st)))
+                out.append(("k_fwd_dct2 L%d" % L, N * (st + st)))
+            else:
+                out.append(("k_fwd_level L%d" % L, N * (bi + st)))
         out.append(("k_fwd_tail L%d-%d" % (Lt, D - 1), N * ((rin if Lt == 0 else st) + io_c)))
     else:
+        Lt = max(0, D - sched["tail_levels"][1])
         out.append(("k_inv_tail L%d-%d" % (D - 1, Lt), N * (io_c + (rin if Lt == 0 else st))))
         for L in range(Lt - 1, -1, -1):
             out.append(("k_inv_dct2 L%d" % L, N * (st + st)))
             bo = rin if L == 0 else st
             out.append(("k_inv_basis L%d" % L, N * (st + bo)))
     return out
+
+
+KERNEL_SOURCES = ("paper_1807_10058_amd/csrc/fcc_dct.hip", "paper_1807_10058_amd/csrc/kernels.hpp",
+                  "paper_1807_10058_amd/csrc/dense.hip", "paper_1807_10058_amd/csrc/orbits.inc")
+
+
+def kernel_source_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, slot):
+    """HBM bytes of one launch of `slot` from the committed rocprofv3 counter
+    profile of this workload (FETCH_SIZE and WRITE_SIZE scaled by a plain copy),
+    or None when there is none or the kernel sources changed since it was taken."""
+    import re
+    path = os.path.join(ROOT, "profiles", "traffic_%s.md" % workload)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel sources sha1: ([0-9a-f]{40})", text)
+    if not m or m.group(1) != kernel_source_sha1():
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 4 and cells[0] == slot:
+            try:
+                return {"read_bytes": float(cells[2]), "write_bytes": float(cells[3]),
+                        "total_bytes": float(cells[2]) + float(cells[3]), "source": "profiles/traffic_%s.md" % workload}
+            except ValueError:
+                return None
+    return None
 
 
 def cpu_baseline(x, n, seconds, rng_seed=11):
@@ -127,7 +174,7 @@ def single_volume(args, name):
     rdt = torch.float64 if prec == fcc.FCC_PREC_FP64 else torch.float32
     cdt = torch.complex128 if prec == fcc.FCC_PREC_FP64 else torch.complex64
     t0 = time.perf_counter()
-    if not args.no_autotune:
+    if args.autotune:
         fcc.fcc_dct_autotune(n, prec=prec, flags=fcc.FCC_REAL_INPUT, reps=5)
     tune_s = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -150,13 +197,13 @@ def single_volume(args, name):
     for d in ([1] if direction == 1 else [1, -1]):
         src, dst = (x, X) if d == 1 else (X, y)
         times = fcc.fcc_dct_time_launches(plan, src, dst, d, reps=max(5, min(args.steps, 50)))
-        tail = sched["tail_levels"][0 if d == 1 else 1]
-        for (kname, nbytes), t in zip(launch_bytes(n, prec, stages64, True, d, tail), times):
+        for (kname, nbytes), t in zip(launch_bytes(n, prec, stages64, True, d, sched), times):
             slots.append((kname, nbytes, t))
     kname, nbytes, tdom = max(slots, key=lambda s: s[2])
     achieved = nbytes / (tdom * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launch_ms": tdom, "algorithmic_bytes": nbytes}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name, kname), "launch_ms": tdom,
+            "algorithmic_bytes": nbytes}
     step()
     torch.cuda.synchronize()
     rows = sample_rows(n, 48, 5)
@@ -198,7 +245,7 @@ def batched(args, name):
     points = int(sum(n ** 3 for n in ns))
     cache = {}
     t0 = time.perf_counter()
-    if not args.no_autotune:
+    if args.autotune:
         for n in sorted(set(ns)):
             if n > 1:
                 fcc.fcc_dct_autotune(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT, reps=3)
@@ -297,6 +344,12 @@ def main():
         "roofline": roof,
     }
     out.update(extra)
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = a.clone()
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = int(b.numel() * 4)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cpu_case[0], cpu_case[1], args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -131,22 +131,37 @@ const char* fcc_status_string(fcc_status s);
  *                    walks the cubes of a node in tiles of 2^t0 x 2^t1 x 2^t2
  *                    cubes (log2 sizes; {0,0,0} = plain lexicographic order).
  *                    Each side is clamped to the node's n / 2^(L+1) cubes.
- *   map[d][L]      : FCC_MAP_XCD numbers the blocks of that gather pass so
- *                    that each XCD takes one contiguous range of rows;
- *                    FCC_MAP_F_INNER puts the 8 rows of a cube next to each
- *                    other (otherwise the row's position in its cube is the
- *                    slowest index). */
-enum { FCC_MAP_XCD = 1u << 0, FCC_MAP_F_INNER = 1u << 1 };
+ *   map[d][L]      : thread map of the gather pass at level L = 0..9.
+ *                    FCC_MAP_XCD numbers the blocks so that each XCD takes one
+ *                    contiguous range of rows.  FCC_MAP_F_INNER puts the 8 rows
+ *                    of a cube next to each other (otherwise the row's position
+ *                    in its cube is the slowest index).  From level 2 on,
+ *                    FCC_MAP_NODES8 / FCC_MAP_NODES64 run all rows of an
+ *                    aligned group of 8 / 64 consecutive nodes before the next
+ *                    group (otherwise all nodes of one row run together); the
+ *                    tile and the node-group bits are ignored where they do
+ *                    not apply.  Forward levels run the basis change and
+ *                    DCT_2 (x) I in one launch, the 8 rows of each cube on 8
+ *                    adjacent lanes (FCC_MAP_F_INNER is implied there);
+ *                    FCC_MAP_SPLIT runs them as two launches instead (gather,
+ *                    then DCT_2 on the cubes).  The inverse always uses two. */
+enum {
+  FCC_MAP_XCD = 1u << 0,
+  FCC_MAP_F_INNER = 1u << 1,
+  FCC_MAP_NODES8 = 1u << 2,
+  FCC_MAP_NODES64 = 1u << 3,
+  FCC_MAP_SPLIT = 1u << 4
+};
 typedef struct {
   int tail_levels[2];
   int tile[2][2][3];
-  unsigned map[2][2];
+  unsigned map[2][10];
 } fcc_tuning;
 
 /* fcc_dct_plan with an explicit schedule.  tuning == NULL takes the schedule
  * fcc_dct_plan would take (see fcc_dct_autotune).  Errors: those of
  * fcc_dct_plan, and FCC_ERR_INVALID_ARG for tail_levels outside 1..3, a tile
- * size outside 0..9 or unknown map bits. */
+ * size outside 0..9, unknown map bits or both node-group bits. */
 fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_precision prec,
                               unsigned flags, const fcc_tuning* tuning, void* hip_stream);
 
@@ -155,8 +170,8 @@ fcc_status fcc_dct_get_tuning(fcc_plan_t plan, fcc_tuning* out);
 
 /* Search the schedule for (n, prec, flags) on the current device: the fused
  * tail depth of each direction first (whole-transform time), then tile shape
- * and block map of the level-0 and level-1 gather passes one at a time
- * (time of that launch), each candidate timed `reps` times on synthetic data
+ * and thread map of each gather pass one level at a time (time of that
+ * launch), each candidate timed `reps` times on synthetic data
  * with HIP events on `hip_stream`.  The winner is written to *best (may be
  * NULL) and remembered for the process: later fcc_dct_plan calls for the same
  * (device, n, prec, flags) use it.  Without a search, fcc_dct_plan uses
@@ -173,8 +188,8 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
  * `hip_stream` with HIP events recorded around every kernel launch, waits for
  * them, and writes the average duration in ms of each launch slot to ms[k].
  * Slots in launch order, with Lt = D - tail_levels (at least 0) of the
- * direction: forward = (B gather pass, DCT_2 pass) for levels 0..Lt-1, then
- * the fused tail; inverse = the fused tail, then (DCT_2^{-1} pass, C gather
+ * direction: forward = for levels 0..Lt-1 one slot (one-pass level) or two
+ * (FCC_MAP_SPLIT: gather pass, DCT_2 pass), then the fused tail; inverse = the fused tail, then (DCT_2^{-1} pass, C gather
  * pass) for levels Lt-1 down to 0.  n = 1 and the dense precisions have one
  * slot.  *count receives the number of slots; with ms == NULL only *count is
  * set.

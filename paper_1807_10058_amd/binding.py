@@ -12,7 +12,8 @@ _LIB_PATH = os.path.join(_HERE, "libfccdct.so")
 FCC_OK = 0
 FCC_PREC_FP64, FCC_PREC_FP32, FCC_PREC_SPLIT_BF16, FCC_PREC_SPLIT_FP16 = 0, 1, 2, 3
 FCC_REAL_INPUT, FCC_STAGES_FP32, FCC_STAGES_FP64, FCC_LEVEL0_FP32 = 1, 2, 4, 8
-FCC_MAP_XCD, FCC_MAP_F_INNER = 1, 2
+FCC_MAP_XCD, FCC_MAP_F_INNER, FCC_MAP_NODES8, FCC_MAP_NODES64, FCC_MAP_SPLIT = 1, 2, 4, 8, 16
+_MAX_LEVELS = 10
 
 # torch is loaded first so that libfccdct.so binds to the HIP runtime torch
 # already carries (same soname): one HIP/HSA runtime per process.
@@ -35,7 +36,7 @@ class _LevelTables(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("tail_levels", ctypes.c_int * 2), ("tile", ((ctypes.c_int * 3) * 2) * 2),
-                ("map", (ctypes.c_uint * 2) * 2)]
+                ("map", (ctypes.c_uint * _MAX_LEVELS) * 2)]
 
 
 def _tuning_to_c(t):
@@ -43,16 +44,18 @@ def _tuning_to_c(t):
     for d in range(2):
         c.tail_levels[d] = int(t["tail_levels"][d])
         for L in range(2):
-            c.map[d][L] = int(t["map"][d][L])
             for a in range(3):
                 c.tile[d][L][a] = int(t["tile"][d][L][a])
+        maps = list(t["map"][d])
+        for L in range(_MAX_LEVELS):
+            c.map[d][L] = int(maps[L]) if L < len(maps) else 0
     return c
 
 
 def _tuning_from_c(c):
     return {"tail_levels": [c.tail_levels[0], c.tail_levels[1]],
             "tile": [[[c.tile[d][L][a] for a in range(3)] for L in range(2)] for d in range(2)],
-            "map": [[c.map[d][L] for L in range(2)] for d in range(2)]}
+            "map": [[c.map[d][L] for L in range(_MAX_LEVELS)] for d in range(2)]}
 
 
 _vp = ctypes.c_void_p

@@ -295,7 +295,7 @@ struct NodeConst {
   double2 a4[16], a3[9];   // blocks of A(phi)
   double2 mono[kNumMono];  // {1, c3, c1, c2, c1 c3} of c = (sigma, tau, rho)(phi)
 };
-constexpr long long kNodeTableMax = 1 << 15;  // levels with at most this many nodes get a table
+constexpr long long kNodeTableMax = 1 << 18;  // levels with at most this many nodes get a table (126 MB)
 
 __global__ void k_node_table(NodeConst* out, int L, const double2* __restrict__ hph) {
   const long long node = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -330,13 +330,17 @@ __device__ __forceinline__ cx<R> ldc(const double2& v) {
 struct RowIdx {
   int J[3], a[3], cube, f;
 };
-__device__ __forceinline__ RowIdx row_of(long long t, int n, int L, CubeOrder ord, int S, int f_inner) {
+__device__ __forceinline__ RowIdx row_of(long long t, int n, int L, CubeOrder ord, int S, GatherMap gm) {
   const int mask = (1 << L) - 1;
-  const int jf = int(t & ((1LL << (3 * L)) - 1));
-  const long long rest = t >> (3 * L);
   const int lgm = __ffs(n) - 2 - L;  // log2 of m = n / 2^(L+1)
+  // node within its group fastest, then the row, then the group
+  const int lg = gm.lg;
+  const long long rows = 8LL << (3 * lgm);
+  const long long hi = t >> lg;
+  const long long grp = hi / rows, rest = hi - grp * rows;
+  const int jf = int((grp << lg) | (t & ((1LL << lg) - 1)));
   RowIdx r;
-  if (f_inner) {
+  if (gm.f_inner) {
     const long long sf = rest / S;  // slice * 8 + f
     r.f = int(sf & 7);
     r.cube = int((sf >> 3) * S + (rest - sf * S));
@@ -386,12 +390,117 @@ __global__ __launch_bounds__(256) void k_fwd_gather(VolSet vs, int nvol, int n, 
   const long long vol = tg / N, t = tg - vol * N;
   const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, vol));
   cx<R>* __restrict__ out = static_cast<cx<R>*>(vol_ptr(vs.out, vol));
-  const RowIdx ri = row_of(t, n, L, lv.b.order, lv.S, gm.f_inner);
+  const RowIdx ri = row_of(t, n, L, lv.b.order, lv.S, gm);
   cx<R> mono[kNumMono];
   load_mono(nodes, hph, L, ri.J, mono);
   const int slice = ri.cube / lv.S, j = ri.cube - slice * lv.S;
   const cx<R> y = gather_row<R, TI>(in, n, L, ri.J, lv.b, lv.S, slice * 8 + ri.f, j, sp, lv.nconst, mono);
   out[gpos(n, L, ri.J, ((ri.f >> 2) & 1) + 2 * ri.a[0], ((ri.f >> 1) & 1) + 2 * ri.a[1], (ri.f & 1) + 2 * ri.a[2])] = y;
+}
+
+// Forward level L in one pass.  Lane f of an aligned group of 8 lanes gathers
+// row (f, abc) of B_nl for one cube; the group then applies DCT_2 = H_8 A(phi)
+// to the cube's 8 values with lane shuffles (A is block diagonal: each lane
+// combines at most 4 values of its class; H_8 is a 3-stage butterfly) and
+// lane i stores output i at node-local position i + 2 abc.
+struct CubeUnit {
+  int J[3], a[3], cube;
+};
+// unit u = one (node, cube): node within its group fastest, then the cube (in
+// the table's cube order), then the group
+__device__ __forceinline__ CubeUnit unit_of(long long u, int n, int L, CubeOrder ord, int lg) {
+  const int mask = (1 << L) - 1;
+  const int lgm = __ffs(n) - 2 - L;
+  const long long hi = u >> lg;
+  const long long grp = hi >> (3 * lgm);
+  CubeUnit c;
+  c.cube = int(hi & ((1LL << (3 * lgm)) - 1));
+  const int jf = int((grp << lg) | (u & ((1LL << lg) - 1)));
+  c.J[0] = jf >> (2 * L);
+  c.J[1] = (jf >> L) & mask;
+  c.J[2] = jf & mask;
+  cube_abc(c.cube, lgm, ord, c.a);
+  return c;
+}
+template <typename R>
+__device__ __forceinline__ cx<R> shfl8(cx<R> v, int src) {
+  return {__shfl(v.x, src, 8), __shfl(v.y, src, 8)};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> shfl_xor8(cx<R> v, int m) {
+  return {__shfl_xor(v.x, m, 8), __shfl_xor(v.y, m, 8)};
+}
+// z_i = sum_mu (-1)^(i.mu) w_mu over the 8 lanes of a group (lane = index)
+template <typename R>
+__device__ __forceinline__ cx<R> hadamard8_lanes(cx<R> w, int f) {
+#pragma unroll
+  for (int s = 1; s < 8; s <<= 1) {
+    const cx<R> o = shfl_xor8(w, s);
+    w = (f & s) ? o - w : w + o;
+  }
+  return w;
+}
+// (A y)_f on the lanes of a group; y is this lane's row value.  kTable: the
+// level has a node table (A's blocks precomputed); otherwise every lane forms
+// A y for the whole cube (a separate instantiation: it needs many registers).
+template <typename R, bool kTable>
+__device__ __forceinline__ cx<R> apply_A_lanes(const NodeConst* nodes, const double2* __restrict__ hph, int L,
+                                               const int J[3], int f, cx<R> y) {
+  if constexpr (kTable) {
+    const NodeConst& nc = nodes[((long long)J[0] << (2 * L)) | ((long long)J[1] << L) | J[2]];
+    // classes {0}, {1,3,4,6} (rows of the 4x4 block), {2,5,7} (3x3 block)
+    const bool c4 = (0x5Au >> f) & 1u, c3 = (0xA4u >> f) & 1u;
+    const int pos = int((0x23121000u >> (4 * f)) & 0xFu);      // row within the class
+    const unsigned src = c4 ? 0x6431u : (c3 ? 0x0752u : 0u);  // source lanes, one nibble each
+    cx<R> w{R(0), R(0)};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const cx<R> v = shfl8(y, int((src >> (4 * j)) & 0xFu));
+      cx<R> a{R(0), R(0)};
+      if (c4)
+        a = ldc<R>(nc.a4[4 * pos + j]);
+      else if (c3 && j < 3)
+        a = ldc<R>(nc.a3[3 * pos + j]);
+      else if (!c4 && !c3 && j == 0)
+        a = cx<R>{R(1), R(0)};
+      w = w + a * v;
+    }
+    return w;
+  } else {
+    cx<R> ys[8], tt[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) ys[i] = shfl8(y, i);
+    cx<R> Q[3][3];
+    node_pos_powers(hph, L, J, Q);
+    apply_A(Q, ys, tt);
+    cx<R> w = tt[0];
+#pragma unroll
+    for (int i = 1; i < 8; ++i) w = (f == i) ? tt[i] : w;
+    return w;
+  }
+}
+
+template <typename R, typename TI, typename TO, bool kTable>
+__global__ __launch_bounds__(256) void k_fwd_level(VolSet vs, int nvol, int n, int L, DevLevel lv,
+                                                   const double2* __restrict__ hph, const NodeConst* nodes,
+                                                   GatherMap gm) {
+  __shared__ double sp[kMaxPoly * kNumMono];
+  load_polys(lv, sp);
+  const long long N = (long long)n * n * n;
+  const long long tg = gather_block(gm.xcd) * blockDim.x + threadIdx.x;
+  if (tg >= N * nvol) return;  // whole groups: N is a multiple of 8
+  const long long vol = tg / N, t = tg - vol * N;
+  const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, vol));
+  TO* __restrict__ out = static_cast<TO*>(vol_ptr(vs.out, vol));
+  const int f = int(t & 7);
+  const CubeUnit cu = unit_of(t >> 3, n, L, lv.b.order, gm.lg);
+  cx<R> mono[kNumMono];
+  load_mono(nodes, hph, L, cu.J, mono);
+  const int slice = cu.cube / lv.S, j = cu.cube - slice * lv.S;
+  const cx<R> y = gather_row<R, TI>(in, n, L, cu.J, lv.b, lv.S, slice * 8 + f, j, sp, lv.nconst, mono);
+  const cx<R> z = hadamard8_lanes(apply_A_lanes<R, kTable>(nodes, hph, L, cu.J, f, y), f);
+  IO<TO, R>::st(out, gpos(n, L, cu.J, ((f >> 2) & 1) + 2 * cu.a[0], ((f >> 1) & 1) + 2 * cu.a[1], (f & 1) + 2 * cu.a[2]),
+                z);
 }
 
 // Forward level L, second pass: z = DCT_2(phi) y = H_8 A(phi) y on every cube
@@ -507,7 +616,7 @@ __global__ __launch_bounds__(256) void k_inv_basis(VolSet vs, int nvol, int n, i
   const long long vol = tg / N, t = tg - vol * N;
   const cx<R>* __restrict__ in = static_cast<const cx<R>*>(vol_ptr(vs.in, vol));
   TO* __restrict__ out = static_cast<TO*>(vol_ptr(vs.out, vol));
-  const RowIdx ri = row_of(t, n, L, lv.c.order, lv.S, gm.f_inner);
+  const RowIdx ri = row_of(t, n, L, lv.c.order, lv.S, gm);
   cx<R> mono[kNumMono];
   load_mono(nodes, hph, L, ri.J, mono);
   const int slice = ri.cube / lv.S, j = ri.cube - slice * lv.S;
@@ -1147,11 +1256,13 @@ const NodeConst* nodes_of(const fcc_plan_s* p, int L) {
 // thread map of the gather pass of direction d (0 forward, 1 inverse) at level L
 // (f_inner needs whole slices: the node must have at least S cubes)
 GatherMap gmap(const fcc_plan_s* p, int d, int L) {
-  if (L > 1) return GatherMap{0, 0};
   const unsigned m = p->tune.map[d][L];
   const long long half = p->n >> (L + 1), cubes = half * half * half;
   const bool whole = cubes >= p->lv[L].S;
-  return GatherMap{int(m & FCC_MAP_XCD), int(whole && (m & FCC_MAP_F_INNER) != 0)};
+  GatherMap g{int(m & FCC_MAP_XCD), int(whole && (m & FCC_MAP_F_INNER) != 0), 3 * L};
+  if (L >= 2 && (m & FCC_MAP_NODES8)) g.lg = std::min(3, 3 * L);
+  if (L >= 2 && (m & FCC_MAP_NODES64)) g.lg = std::min(6, 3 * L);
+  return g;
 }
 
 template <typename R>
@@ -1166,6 +1277,43 @@ void fwd_gather_dispatch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, in
     case DT::F64C: hipLaunchKernelGGL((k_fwd_gather<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 0, L)); break;
   }
 }
+template <typename R, typename TI>
+void fwd_level_out(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int nvol, hipStream_t st) {
+  dim3 g = grid_points(p->n, nvol);
+  const double2* h = phases(p, L);
+  const NodeConst* nc = nodes_of(p, L);
+  const GatherMap gm = gmap(p, 0, L);
+  if (nc) {
+    if (to == DT::F32C)
+      hipLaunchKernelGGL((k_fwd_level<R, TI, float2, true>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm);
+    else
+      hipLaunchKernelGGL((k_fwd_level<R, TI, double2, true>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm);
+  } else {
+    if (to == DT::F32C)
+      hipLaunchKernelGGL((k_fwd_level<R, TI, float2, false>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm);
+    else
+      hipLaunchKernelGGL((k_fwd_level<R, TI, double2, false>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm);
+  }
+}
+template <typename R>
+void fwd_level_dispatch(const fcc_plan_s* p, int L, DT ti, DT to, const VolSet& vs, int nvol, hipStream_t st) {
+  switch (ti) {
+    case DT::F32R: fwd_level_out<R, float>(p, L, to, vs, nvol, st); break;
+    case DT::F64R: fwd_level_out<R, double>(p, L, to, vs, nvol, st); break;
+    case DT::F32C: fwd_level_out<R, float2>(p, L, to, vs, nvol, st); break;
+    case DT::F64C: fwd_level_out<R, double2>(p, L, to, vs, nvol, st); break;
+  }
+}
+bool fwd_split(const fcc_plan_s* p, int L) { return (p->tune.map[0][L] & FCC_MAP_SPLIT) != 0; }
+// number of launch slots of one transform in direction d (0 forward, 1 inverse)
+int slot_count(const fcc_plan_s* p, int d) {
+  if (p->n == 1 || p->dense) return 1;
+  if (d == 1) return 2 * p->tail_Lt[1] + 1;
+  int k = 1;
+  for (int L = 0; L < p->tail_Lt[0]; ++L) k += fwd_split(p, L) ? 2 : 1;
+  return k;
+}
+
 template <typename R>
 void fwd_dct2_dispatch(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int nvol, hipStream_t st) {
   dim3 g = grid_cubes(p->n, nvol);
@@ -1305,24 +1453,30 @@ fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
   VolPtrs src = in;
   DT src_t = in_type(p);
   for (int L = 0; L < p->tail_Lt[0]; ++L) {
-    const bool last = false;
     VolPtrs a = (L & 1) ? ws1 : ws0;
-    // pass 1: basis-change gather into a; pass 2: DCT_2 on the cubes of a,
-    // in place (or into the user's output at the last level)
-    if (arith64(p, L))
-      fwd_gather_dispatch<double>(p, L, src_t, VolSet{src, a}, nvol, st);
-    else
-      fwd_gather_dispatch<float>(p, L, src_t, VolSet{src, a}, nvol, st);
-    if (tm) tm->mark(st);
-    VolPtrs dst = last ? out : a;
-    DT to = last ? cplx_type(p) : buf_type(p, L + 1);
-    if (arith64(p, L))
-      fwd_dct2_dispatch<double>(p, L, to, VolSet{a, dst}, nvol, st);
-    else
-      fwd_dct2_dispatch<float>(p, L, to, VolSet{a, dst}, nvol, st);
-    if (tm) tm->mark(st);
+    const DT to = buf_type(p, L + 1);
+    if (!fwd_split(p, L)) {
+      // basis change and DCT_2 in one launch, into a
+      if (arith64(p, L))
+        fwd_level_dispatch<double>(p, L, src_t, to, VolSet{src, a}, nvol, st);
+      else
+        fwd_level_dispatch<float>(p, L, src_t, to, VolSet{src, a}, nvol, st);
+      if (tm) tm->mark(st);
+    } else {
+      // pass 1: basis-change gather into a; pass 2: DCT_2 on the cubes of a, in place
+      if (arith64(p, L))
+        fwd_gather_dispatch<double>(p, L, src_t, VolSet{src, a}, nvol, st);
+      else
+        fwd_gather_dispatch<float>(p, L, src_t, VolSet{src, a}, nvol, st);
+      if (tm) tm->mark(st);
+      if (arith64(p, L))
+        fwd_dct2_dispatch<double>(p, L, to, VolSet{a, a}, nvol, st);
+      else
+        fwd_dct2_dispatch<float>(p, L, to, VolSet{a, a}, nvol, st);
+      if (tm) tm->mark(st);
+    }
     src = a;
-    src_t = buf_type(p, L + 1);
+    src_t = to;
   }
   // the last levels (node size <= kTailNl) in one LDS-resident launch
   if (p->stages64)
@@ -1577,7 +1731,7 @@ fcc_status fcc_asp_tables(int nl, fcc_level_tables* out) {
 }
 
 namespace {
-// Built-in schedule: the autotuner's choice on MI355X at n = 128 and 256.
+// Built-in schedule: the autotuner's choices on MI355X at n = 64, 128, 256.
 fcc_tuning default_tuning(int n) {
   fcc_tuning t{};
   t.tail_levels[0] = n <= 64 ? 1 : 2;
@@ -1585,20 +1739,31 @@ fcc_tuning default_tuning(int n) {
   for (int a = 0; a < 3; ++a) {
     t.tile[0][0][a] = 2;  // forward level 0: 4x4x4 cube tiles
     t.tile[0][1][a] = 1;  // forward level 1: 2x2x2
-    t.tile[1][0][a] = 2;  // inverse levels 0 and 1: 4x4x4, the 8 rows of a cube together
+    t.tile[1][0][a] = 2;  // inverse levels 0 and 1: 4x4x4
     t.tile[1][1][a] = 2;
   }
+  // forward: two passes at the top levels; below, one pass with XCD-contiguous
+  // blocks up to n = 64, two passes over groups of 64 nodes above
+  t.map[0][0] = FCC_MAP_SPLIT;
+  t.map[0][1] = n <= 64 ? FCC_MAP_XCD : FCC_MAP_SPLIT;
+  for (int L = 2; L < 10; ++L) t.map[0][L] = n <= 64 ? FCC_MAP_XCD : (FCC_MAP_SPLIT | FCC_MAP_NODES64);
+  // inverse: the 8 rows of a cube together at the top, XCD-contiguous at levels 2-3
   t.map[1][0] = FCC_MAP_F_INNER;
   t.map[1][1] = FCC_MAP_F_INNER;
+  t.map[1][2] = FCC_MAP_XCD;
+  t.map[1][3] = FCC_MAP_XCD;
   return t;
 }
 bool valid_tuning(const fcc_tuning& t) {
   for (int d = 0; d < 2; ++d) {
     if (t.tail_levels[d] < 1 || t.tail_levels[d] > 3) return false;
-    for (int L = 0; L < 2; ++L) {
-      if (t.map[d][L] & ~unsigned(FCC_MAP_XCD | FCC_MAP_F_INNER)) return false;
+    for (int L = 0; L < 2; ++L)
       for (int a = 0; a < 3; ++a)
         if (t.tile[d][L][a] < 0 || t.tile[d][L][a] > 9) return false;
+    for (int L = 0; L < 10; ++L) {
+      const unsigned m = t.map[d][L];
+      if (m & ~unsigned(FCC_MAP_XCD | FCC_MAP_F_INNER | FCC_MAP_NODES8 | FCC_MAP_NODES64 | FCC_MAP_SPLIT)) return false;
+      if ((m & FCC_MAP_NODES8) && (m & FCC_MAP_NODES64)) return false;
     }
   }
   return true;
@@ -1826,7 +1991,7 @@ namespace {
 // +1 (forward) or -1 (inverse), timed with events around every launch.
 fcc_status time_slots(const fcc_plan_s* p, const void* in, void* out, int direction, int reps, hipStream_t st,
                       std::vector<float>* ms) {
-  const int slots = (p->n == 1 || p->dense) ? 1 : 2 * p->tail_Lt[direction > 0 ? 0 : 1] + 1;
+  const int slots = slot_count(p, direction > 0 ? 0 : 1);
   ms->assign(slots, 0.f);
   std::vector<hipEvent_t> ev(size_t(slots + 1) * reps, nullptr);
   fcc_status s = FCC_OK;
@@ -1875,7 +2040,7 @@ fcc_status fcc_dct_time_launches(fcc_plan_t p, const void* in, void* out, int di
                                  int cap, int* count, void* hip_stream) {
   if (!p || !in || !out || !count || reps < 1 || (direction != 1 && direction != -1)) return FCC_ERR_INVALID_ARG;
   if (!aligned16(in) || !aligned16(out) || in == out) return FCC_ERR_INVALID_ARG;
-  const int slots = (p->n == 1 || p->dense) ? 1 : 2 * p->tail_Lt[direction > 0 ? 0 : 1] + 1;
+  const int slots = slot_count(p, direction > 0 ? 0 : 1);
   *count = slots;
   if (!ms || cap < slots) return ms ? FCC_ERR_INVALID_ARG : FCC_OK;
   (void)hipGetLastError();
@@ -1935,13 +2100,21 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
       }
       p->tune.tail_levels[d] = best_k;
       p->tail_Lt[d] = std::max(0, p->D - best_k);
-      // 2. tile shape and block map of the level-0 and level-1 gather passes,
-      // by the time of that launch
+      // 2. tile shape and thread map of the level-0 and level-1 gather
+      // passes, by the time of that level's launches
+      auto level_ms = [&](int L) {
+        if (d == 1) return double(ms[2 * (p->tail_Lt[1] - L)]);  // the C gather pass
+        int k = 0;
+        for (int l = 0; l < L; ++l) k += fwd_split(p, l) ? 2 : 1;
+        return double(ms[k]) + (fwd_split(p, L) ? double(ms[k + 1]) : 0.0);
+      };
       static const int tiles0[][3] = {{0, 0, 0}, {2, 2, 2}, {1, 2, 3}, {0, 3, 3}, {3, 3, 3}, {2, 2, 4}};
       static const int tiles1[][3] = {{0, 0, 0}, {1, 1, 1}, {0, 1, 2}, {2, 2, 2}};
+      static const unsigned top_fwd[] = {0u, FCC_MAP_XCD, FCC_MAP_SPLIT, FCC_MAP_SPLIT | FCC_MAP_XCD,
+                                         FCC_MAP_SPLIT | FCC_MAP_F_INNER, FCC_MAP_SPLIT | FCC_MAP_F_INNER | FCC_MAP_XCD};
+      static const unsigned top_inv[] = {0u, FCC_MAP_XCD, FCC_MAP_F_INNER, FCC_MAP_F_INNER | FCC_MAP_XCD};
       for (int L = 0; L < 2 && L < p->tail_Lt[d] && s == FCC_OK; ++L) {
         const int lgm = p->D - L - 1;
-        const int slot = d == 0 ? 2 * L : 2 * (p->tail_Lt[d] - L);
         const int ntiles = L == 0 ? 6 : 4;
         DevSide& cur = d == 0 ? p->lv[L].b : p->lv[L].c;
         DevSide best_side = cur;
@@ -1969,19 +2142,22 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
               s = device_side(p->device, n >> L, slice_cubes(L), d, o, &cand, &own);
           }
           bool won = false;
-          for (unsigned mp = 0; mp < 4 && s == FCC_OK; ++mp) {
+          const unsigned* maps = d == 0 ? top_fwd : top_inv;
+          const int nmaps = d == 0 ? 6 : 4;
+          for (int mi = 0; mi < nmaps && s == FCC_OK; ++mi) {
             cur = cand;
             p->tune.tile[d][L][0] = o.la;
             p->tune.tile[d][L][1] = o.lb;
             p->tune.tile[d][L][2] = o.lc;
-            p->tune.map[d][L] = mp;
+            p->tune.map[d][L] = maps[mi];
             s = d == 0 ? time_slots(p, a, b, 1, reps, st, &ms) : time_slots(p, b, a, -1, reps, st, &ms);
             if (s != FCC_OK) break;
+            const double t = level_ms(L);
             if (verbose())
               std::fprintf(stderr, "fcc_autotune n=%d dir=%d level=%d tile=(%d,%d,%d) map=%u: %.4f ms\n", n, d, L, o.la,
-                           o.lb, o.lc, mp, ms[slot]);
-            if (ms[slot] < best_ms) {
-              best_ms = ms[slot];
+                           o.lb, o.lc, maps[mi], t);
+            if (t < best_ms) {
+              best_ms = t;
               best_side = cand;
               best_t2 = p->tune;
               won = true;
@@ -2005,6 +2181,40 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
                                 best_side);
           cache().owned.insert(cache().owned.end(), keep.begin(), keep.end());
         }
+      }
+      // 3. thread map of the gather passes from level 2 on (plain-order
+      // tables, so only the map changes)
+      static const unsigned deep_fwd[] = {0u,
+                                          FCC_MAP_XCD,
+                                          FCC_MAP_NODES8,
+                                          FCC_MAP_NODES8 | FCC_MAP_XCD,
+                                          FCC_MAP_NODES64,
+                                          FCC_MAP_NODES64 | FCC_MAP_XCD,
+                                          FCC_MAP_SPLIT,
+                                          FCC_MAP_SPLIT | FCC_MAP_NODES8 | FCC_MAP_XCD,
+                                          FCC_MAP_SPLIT | FCC_MAP_NODES64};
+      static const unsigned deep_inv[] = {0u,
+                                          FCC_MAP_XCD,
+                                          FCC_MAP_NODES8,
+                                          FCC_MAP_NODES8 | FCC_MAP_XCD,
+                                          FCC_MAP_NODES64,
+                                          FCC_MAP_NODES64 | FCC_MAP_XCD,
+                                          FCC_MAP_NODES8 | FCC_MAP_F_INNER | FCC_MAP_XCD};
+      for (int L = 2; L < p->tail_Lt[d] && s == FCC_OK; ++L) {
+        unsigned best_m = p->tune.map[d][L];
+        double best_ms = 1e30;
+        const unsigned* maps = d == 0 ? deep_fwd : deep_inv;
+        const int nmaps = d == 0 ? 9 : 7;
+        for (int mi = 0; mi < nmaps; ++mi) {
+          p->tune.map[d][L] = maps[mi];
+          s = d == 0 ? time_slots(p, a, b, 1, reps, st, &ms) : time_slots(p, b, a, -1, reps, st, &ms);
+          if (s != FCC_OK) break;
+          const double t = level_ms(L);
+          if (verbose())
+            std::fprintf(stderr, "fcc_autotune n=%d dir=%d level=%d map=%u: %.4f ms\n", n, d, L, maps[mi], t);
+          if (t < best_ms) best_ms = t, best_m = maps[mi];
+        }
+        p->tune.map[d][L] = best_m;
       }
     }
     if (a) (void)hipFree(a);

@@ -133,9 +133,11 @@ struct DevLevel {
 // Thread map of a gather pass.  xcd: the blocks that the hardware deals
 // round-robin to the 8 XCDs are renumbered so that each XCD works through one
 // contiguous range of rows.  f_inner: the 8 rows f of one table slice are
-// consecutive (otherwise f is the slowest index).
+// consecutive (otherwise f is the slowest index).  lg: log2 of the node group
+// (levels >= 2): all rows of 2^lg consecutive nodes run before the next group;
+// 3L means one group of all 8^L nodes.
 struct GatherMap {
-  int xcd, f_inner;
+  int xcd, f_inner, lg;
 };
 
 // Where the volumes of one launch live: one volume at `one` (arr == nullptr)

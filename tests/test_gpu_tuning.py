@@ -15,18 +15,21 @@ pytestmark = pytest.mark.gpu
 gu = pytest.importorskip("tests.gpu_util")
 
 
-def tuning(tail=(1, 1), tiles=((0, 0, 0), (0, 0, 0), (0, 0, 0), (0, 0, 0)), maps=(0, 0, 0, 0)):
-    """tiles/maps in the order (fwd L0, fwd L1, inv L0, inv L1)."""
+def tuning(tail=(1, 1), tiles=((0, 0, 0), (0, 0, 0), (0, 0, 0), (0, 0, 0)), maps=(0, 0, 0, 0), deep=(0, 0)):
+    """tiles/maps in the order (fwd L0, fwd L1, inv L0, inv L1); deep = the
+    (forward, inverse) map of every level from 2 on."""
     return {"tail_levels": list(tail),
             "tile": [[list(tiles[0]), list(tiles[1])], [list(tiles[2]), list(tiles[3])]],
-            "map": [[maps[0], maps[1]], [maps[2], maps[3]]]}
+            "map": [[maps[0], maps[1]] + [deep[0]] * 8, [maps[2], maps[3]] + [deep[1]] * 8]}
 
 
+N8, N64, SP = fcc.FCC_MAP_NODES8, fcc.FCC_MAP_NODES64, fcc.FCC_MAP_SPLIT
 SCHEDULES = [
     tuning(),
-    tuning(tiles=((2, 2, 2), (1, 1, 1), (2, 2, 2), (2, 2, 2)), maps=(0, 0, 2, 2)),
-    tuning(tiles=((1, 2, 3), (0, 1, 2), (3, 3, 3), (1, 1, 1)), maps=(1, 3, 1, 3)),
-    tuning(tiles=((9, 9, 9), (9, 9, 9), (0, 3, 3), (2, 2, 4)), maps=(3, 2, 0, 1)),
+    tuning(tiles=((2, 2, 2), (1, 1, 1), (2, 2, 2), (2, 2, 2)), maps=(0, 0, 2, 2), deep=(N8, N8 | 1)),
+    tuning(tiles=((1, 2, 3), (0, 1, 2), (3, 3, 3), (1, 1, 1)), maps=(SP | 1, 3, 1, 3), deep=(N64 | 1, N64)),
+    tuning(tiles=((9, 9, 9), (9, 9, 9), (0, 3, 3), (2, 2, 4)), maps=(3, SP | 2, 0, 1), deep=(SP | N8 | 3, 2)),
+    tuning(maps=(SP, SP, 0, 0), deep=(SP, 0)),
 ]
 
 

@@ -9,12 +9,15 @@ child i's entry k).  No GPU needed: the tables are read through the C ABI
 introspection call and applied with numpy.
 """
 import itertools
+import os
 
 import numpy as np
 import pytest
 
 import oracle
 import paper_1807_10058_amd as fcc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 E3 = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
 PHI0 = (1 / 8, 0, 3 / 8)
@@ -89,3 +92,21 @@ def test_table_statistics_and_monomials():
         assert {tuple(v) for v in t["mono"]} <= {(0, 0, 0), (0, 0, 1), (1, 0, 0), (0, 1, 0), (1, 0, 1)}
     t2 = fcc.fcc_asp_tables(2)
     assert t2["b_rowptr"][-1] == 8 and t2["c_rowptr"][-1] == 8
+
+
+def test_derivation_is_identical_across_processes():
+    # the parallel derivation interns polynomials in a thread-timing dependent
+    # order; the stored coefficients and ids must not depend on it
+    import hashlib
+    import subprocess
+    import sys
+    code = ("import hashlib, sys; sys.path.insert(0, %r)\n"
+            "import paper_1807_10058_amd as f\n"
+            "h = hashlib.sha1()\n"
+            "for nl in (16, 32):\n"
+            "    t = f.fcc_asp_tables(nl)\n"
+            "    for k in ('poly', 'b_src', 'b_pid', 'c_src', 'c_pid'): h.update(t[k].tobytes())\n"
+            "print(h.hexdigest())\n") % ROOT
+    outs = {subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, check=True).stdout
+            for _ in range(4)}
+    assert len(outs) == 1, outs
