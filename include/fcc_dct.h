@@ -185,8 +185,9 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
 
 /* Per-launch timing of one direction of the fast path: enqueues `reps`
  * transforms of `in` into `out` (direction +1 forward, -1 inverse) on
- * `hip_stream` with HIP events recorded around every kernel launch, waits for
- * them, and writes the average duration in ms of each launch slot to ms[k].
+ * `hip_stream`, each kernel launched with its own start and stop event
+ * (recorded at the kernel's start and end), waits for them, and writes the
+ * average duration in ms of each launch slot to ms[k].
  * Slots in launch order, with Lt = D - tail_levels (at least 0) of the
  * direction: forward = for levels 0..Lt-1 one slot (one-pass level) or two
  * (FCC_MAP_SPLIT: gather pass, DCT_2 pass), then the fused tail; inverse = the fused tail, then (DCT_2^{-1} pass, C gather

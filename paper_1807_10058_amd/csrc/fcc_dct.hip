@@ -2,6 +2,7 @@
 // radix-2x2x2 fast FCC cosine transform of Sec. IV-B (eq. FastAlgorithm) and
 // its inverse, one launch per level (two for the inverse), FP64 or FP32
 // stages.  Layout and per-thread work are described in kernels.hpp.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -250,34 +251,52 @@ __device__ __forceinline__ void load_polys(const DevLevel& lv, double* sp) {
   __syncthreads();
 }
 
-// Gather sum_e coef(pid_e) in[J + 2^L src_e] over one sliced row, four entries
-// in flight at a time.
+// Gather sum_e coef(pid_e) in[J + 2^L src_e] over one sliced row, in entry
+// order.  Software pipelined in chunks of 8: the table entries of chunk c+1
+// are loaded while the data of chunk c is in flight, so a row of len entries
+// costs about len/8 dependent memory round trips.
 template <typename R, typename TI>
 __device__ __forceinline__ cx<R> gather_row(const TI* __restrict__ in, int n, int L, const int J[3], const DevSide& sd,
                                             int S, int r, int j, const double* sp, int nconst,
                                             const cx<R> mono[kNumMono]) {
+  constexpr int U = 8;
   const int e0 = sd.start[r] + j, len = sd.len[r];
   cx<R> acc{R(0), R(0)};
-  int e = 0;
-  for (; e + 4 <= len; e += 4) {
-    uint32_t s4[4];
-    uint16_t p4[4];
+  if (len <= 0) return acc;
+  uint32_t s8[U];
+  uint16_t p8[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      s4[u] = sd.src[e0 + (e + u) * S];
-      p4[u] = sd.pid[e0 + (e + u) * S];
-    }
-    cx<R> v4[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      v4[u] = IO<TI, R>::ld(in, gpos(n, L, J, int(s4[u] >> 20), int((s4[u] >> 10) & 1023u), int(s4[u] & 1023u)));
-#pragma unroll
-    for (int u = 0; u < 4; ++u) acc = acc + poly_value(sp, nconst, p4[u], mono) * v4[u];
+  for (int u = 0; u < U; ++u) {
+    const int e = min(u, len - 1);  // past the row's end: repeat its last entry, unused
+    s8[u] = sd.src[e0 + e * S];
+    p8[u] = sd.pid[e0 + e * S];
   }
-  for (; e < len; ++e) {
-    const uint32_t s = sd.src[e0 + e * S];
-    const cx<R> v = IO<TI, R>::ld(in, gpos(n, L, J, int(s >> 20), int((s >> 10) & 1023u), int(s & 1023u)));
-    acc = acc + poly_value(sp, nconst, sd.pid[e0 + e * S], mono) * v;
+  for (int c = 0; c < len; c += U) {
+    cx<R> v8[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      v8[u] = IO<TI, R>::ld(in, gpos(n, L, J, int(s8[u] >> 20), int((s8[u] >> 10) & 1023u), int(s8[u] & 1023u)));
+    uint32_t sn[U];
+    uint16_t pn[U];
+    const bool more = c + U < len;
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = min(c + U + u, len - 1);
+        sn[u] = sd.src[e0 + e * S];
+        pn[u] = sd.pid[e0 + e * S];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (c + u < len) acc = acc + poly_value(sp, nconst, p8[u], mono) * v8[u];
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        s8[u] = sn[u];
+        p8[u] = pn[u];
+      }
+    }
   }
   return acc;
 }
@@ -1239,6 +1258,27 @@ bool arith64(const fcc_plan_s* p, int L) { return p->stages64 && !(p->level0_fp3
 
 constexpr int kBlock = 256;
 
+// Per-launch timing.  While a timer is active on this thread, every kernel of
+// the transform is launched with its own start and stop event
+// (hipExtLaunchKernelGGL records them at the kernel's start and end), so a
+// slot's time is the kernel's own duration without the gaps between launches.
+struct LaunchTimer {
+  std::vector<hipEvent_t>* ev = nullptr;  // 2 per launch
+  size_t next = 0;
+};
+thread_local LaunchTimer* t_timer = nullptr;
+template <typename... KArgs, typename... Args>
+void launch(void (*kernel)(KArgs...), dim3 grid, dim3 block, unsigned shmem, hipStream_t st, Args... args) {
+  LaunchTimer* tm = t_timer;
+  if (tm && tm->next + 2 <= tm->ev->size()) {
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, st, (*tm->ev)[tm->next], (*tm->ev)[tm->next + 1], 0, args...);
+    tm->next += 2;
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, shmem, st, args...);
+  }
+}
+
+
 dim3 grid_cubes(int n, int nvol) {  // one thread per 2x2x2 cube
   long long h = n >> 1;
   long long threads = h * h * h * nvol;
@@ -1271,10 +1311,10 @@ void fwd_gather_dispatch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, in
   const double2* h = phases(p, L);
   const NodeConst* nc = nodes_of(p, L);
   switch (ti) {
-    case DT::F32R: hipLaunchKernelGGL((k_fwd_gather<R, float>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 0, L)); break;
-    case DT::F64R: hipLaunchKernelGGL((k_fwd_gather<R, double>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 0, L)); break;
-    case DT::F32C: hipLaunchKernelGGL((k_fwd_gather<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 0, L)); break;
-    case DT::F64C: hipLaunchKernelGGL((k_fwd_gather<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 0, L)); break;
+    case DT::F32R: launch((k_fwd_gather<R, float>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 0, L)); break;
+    case DT::F64R: launch((k_fwd_gather<R, double>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 0, L)); break;
+    case DT::F32C: launch((k_fwd_gather<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 0, L)); break;
+    case DT::F64C: launch((k_fwd_gather<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 0, L)); break;
   }
 }
 template <typename R, typename TI>
@@ -1285,14 +1325,14 @@ void fwd_level_out(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int nvol
   const GatherMap gm = gmap(p, 0, L);
   if (nc) {
     if (to == DT::F32C)
-      hipLaunchKernelGGL((k_fwd_level<R, TI, float2, true>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm);
+      launch((k_fwd_level<R, TI, float2, true>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm);
     else
-      hipLaunchKernelGGL((k_fwd_level<R, TI, double2, true>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm);
+      launch((k_fwd_level<R, TI, double2, true>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm);
   } else {
     if (to == DT::F32C)
-      hipLaunchKernelGGL((k_fwd_level<R, TI, float2, false>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm);
+      launch((k_fwd_level<R, TI, float2, false>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm);
     else
-      hipLaunchKernelGGL((k_fwd_level<R, TI, double2, false>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm);
+      launch((k_fwd_level<R, TI, double2, false>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm);
   }
 }
 template <typename R>
@@ -1320,9 +1360,9 @@ void fwd_dct2_dispatch(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int 
   const double2* h = phases(p, L);
   const NodeConst* nc = nodes_of(p, L);
   if (to == DT::F32C)
-    hipLaunchKernelGGL((k_fwd_dct2<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, h, nc);
+    launch((k_fwd_dct2<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, h, nc);
   else
-    hipLaunchKernelGGL((k_fwd_dct2<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, h, nc);
+    launch((k_fwd_dct2<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, h, nc);
 }
 
 template <typename R>
@@ -1331,9 +1371,9 @@ void inv_dct2_dispatch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, int 
   const double2* h = phases(p, L);
   const NodeConst* nc = nodes_of(p, L);
   if (ti == DT::F32C)
-    hipLaunchKernelGGL((k_inv_dct2<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, h, nc);
+    launch((k_inv_dct2<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, h, nc);
   else
-    hipLaunchKernelGGL((k_inv_dct2<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, h, nc);
+    launch((k_inv_dct2<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, h, nc);
 }
 template <typename R>
 void inv_basis_dispatch(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int nvol, hipStream_t st) {
@@ -1341,10 +1381,10 @@ void inv_basis_dispatch(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int
   const double2* h = phases(p, L);
   const NodeConst* nc = nodes_of(p, L);
   switch (to) {
-    case DT::F32R: hipLaunchKernelGGL((k_inv_basis<R, float>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 1, L)); break;
-    case DT::F64R: hipLaunchKernelGGL((k_inv_basis<R, double>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 1, L)); break;
-    case DT::F32C: hipLaunchKernelGGL((k_inv_basis<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 1, L)); break;
-    case DT::F64C: hipLaunchKernelGGL((k_inv_basis<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 1, L)); break;
+    case DT::F32R: launch((k_inv_basis<R, float>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 1, L)); break;
+    case DT::F64R: launch((k_inv_basis<R, double>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 1, L)); break;
+    case DT::F32C: launch((k_inv_basis<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 1, L)); break;
+    case DT::F64C: launch((k_inv_basis<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 1, L)); break;
   }
 }
 
@@ -1376,9 +1416,9 @@ void fwd_tail_out(const fcc_plan_s* p, DT to, const VolSet& vs, int nvol, hipStr
   const TailGeom g = tail_geom(p, p->tail_Lt[0], nvol);
   const TailLevels tl = tail_levels(p, p->tail_Lt[0]);
   if (to == DT::F32C)
-    hipLaunchKernelGGL((k_fwd_tail<R, TI, float2>), tail_grid(g, nvol), tail_block_dim(g), 0, st, vs, g, tl);
+    launch((k_fwd_tail<R, TI, float2>), tail_grid(g, nvol), tail_block_dim(g), 0, st, vs, g, tl);
   else
-    hipLaunchKernelGGL((k_fwd_tail<R, TI, double2>), tail_grid(g, nvol), tail_block_dim(g), 0, st, vs, g, tl);
+    launch((k_fwd_tail<R, TI, double2>), tail_grid(g, nvol), tail_block_dim(g), 0, st, vs, g, tl);
 }
 template <typename R>
 void fwd_tail_dispatch(const fcc_plan_s* p, DT ti, DT to, const VolSet& vs, int nvol, hipStream_t st) {
@@ -1395,10 +1435,10 @@ void inv_tail_out(const fcc_plan_s* p, DT to, const VolSet& vs, int nvol, hipStr
   const TailLevels tl = tail_levels(p, p->tail_Lt[1]);
   const dim3 gr = tail_grid(g, nvol), bd = tail_block_dim(g);
   switch (to) {
-    case DT::F32R: hipLaunchKernelGGL((k_inv_tail<R, TI, float>), gr, bd, 0, st, vs, g, tl); break;
-    case DT::F64R: hipLaunchKernelGGL((k_inv_tail<R, TI, double>), gr, bd, 0, st, vs, g, tl); break;
-    case DT::F32C: hipLaunchKernelGGL((k_inv_tail<R, TI, float2>), gr, bd, 0, st, vs, g, tl); break;
-    case DT::F64C: hipLaunchKernelGGL((k_inv_tail<R, TI, double2>), gr, bd, 0, st, vs, g, tl); break;
+    case DT::F32R: launch((k_inv_tail<R, TI, float>), gr, bd, 0, st, vs, g, tl); break;
+    case DT::F64R: launch((k_inv_tail<R, TI, double>), gr, bd, 0, st, vs, g, tl); break;
+    case DT::F32C: launch((k_inv_tail<R, TI, float2>), gr, bd, 0, st, vs, g, tl); break;
+    case DT::F64C: launch((k_inv_tail<R, TI, double2>), gr, bd, 0, st, vs, g, tl); break;
   }
 }
 template <typename R>
@@ -1411,7 +1451,7 @@ void inv_tail_dispatch(const fcc_plan_s* p, DT ti, DT to, const VolSet& vs, int 
 
 template <typename TI, typename TO>
 void launch_copy1(const VolSet& vs, int nvol, hipStream_t st) {
-  hipLaunchKernelGGL((k_copy1<TI, TO>), dim3(unsigned((nvol + 63) / 64)), dim3(64), 0, st, vs, nvol);
+  launch((k_copy1<TI, TO>), dim3(unsigned((nvol + 63) / 64)), dim3(64), 0, st, vs, nvol);
 }
 void copy1_dispatch(DT ti, DT to, const VolSet& vs, int nvol, hipStream_t st) {
   auto go = [&](auto tag_in) {
@@ -1433,19 +1473,10 @@ void copy1_dispatch(DT ti, DT to, const VolSet& vs, int nvol, hipStream_t st) {
 
 // Optional per-launch timing: an event is recorded before the first launch and
 // after every launch, so slot k's duration is ev[k+1] - ev[k].
-struct LaunchTimer {
-  std::vector<hipEvent_t>* ev = nullptr;
-  size_t next = 0;
-  void mark(hipStream_t st) {
-    if (ev && next < ev->size()) (void)hipEventRecord((*ev)[next++], st);
-  }
-};
-
 // Enqueue the forward transform of nvol volumes that share plan p.
 // ws0/ws1: two scratch arrays of n^3 stage-precision complex per volume.
 fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0, VolPtrs ws1,
-                           hipStream_t st, LaunchTimer* tm = nullptr) {
-  if (tm) tm->mark(st);
+                           hipStream_t st) {
   if (p->n == 1) {
     copy1_dispatch(in_type(p), cplx_type(p), VolSet{in, out}, nvol, st);
     return launch_status("forward n=1 launch");
@@ -1461,20 +1492,17 @@ fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
         fwd_level_dispatch<double>(p, L, src_t, to, VolSet{src, a}, nvol, st);
       else
         fwd_level_dispatch<float>(p, L, src_t, to, VolSet{src, a}, nvol, st);
-      if (tm) tm->mark(st);
-    } else {
+        } else {
       // pass 1: basis-change gather into a; pass 2: DCT_2 on the cubes of a, in place
       if (arith64(p, L))
         fwd_gather_dispatch<double>(p, L, src_t, VolSet{src, a}, nvol, st);
       else
         fwd_gather_dispatch<float>(p, L, src_t, VolSet{src, a}, nvol, st);
-      if (tm) tm->mark(st);
-      if (arith64(p, L))
+          if (arith64(p, L))
         fwd_dct2_dispatch<double>(p, L, to, VolSet{a, a}, nvol, st);
       else
         fwd_dct2_dispatch<float>(p, L, to, VolSet{a, a}, nvol, st);
-      if (tm) tm->mark(st);
-    }
+        }
     src = a;
     src_t = to;
   }
@@ -1483,13 +1511,11 @@ fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
     fwd_tail_dispatch<double>(p, src_t, cplx_type(p), VolSet{src, out}, nvol, st);
   else
     fwd_tail_dispatch<float>(p, src_t, cplx_type(p), VolSet{src, out}, nvol, st);
-  if (tm) tm->mark(st);
   return launch_status("forward level launch");
 }
 
 fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0, VolPtrs ws1,
-                           hipStream_t st, LaunchTimer* tm = nullptr) {
-  if (tm) tm->mark(st);
+                           hipStream_t st) {
   DT real_or_cplx = (p->flags & FCC_REAL_INPUT) ? in_type(p) : cplx_type(p);
   if (p->n == 1) {
     copy1_dispatch(cplx_type(p), real_or_cplx, VolSet{in, out}, nvol, st);
@@ -1504,8 +1530,7 @@ fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
       inv_tail_dispatch<double>(p, cplx_type(p), to, VolSet{in, dst}, nvol, st);
     else
       inv_tail_dispatch<float>(p, cplx_type(p), to, VolSet{in, dst}, nvol, st);
-    if (tm) tm->mark(st);
-  }
+    }
   VolPtrs cur = ws0;
   bool cur_is_user = false;
   int which = 0;  // scratch array holding the current level's data
@@ -1519,15 +1544,13 @@ fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
       inv_dct2_dispatch<double>(p, L, ti, VolSet{cur, a}, nvol, st);
     else
       inv_dct2_dispatch<float>(p, L, ti, VolSet{cur, a}, nvol, st);
-    if (tm) tm->mark(st);
-    VolPtrs dst = L == 0 ? out : b;
+      VolPtrs dst = L == 0 ? out : b;
     DT to = L == 0 ? real_or_cplx : buf_type(p, L);
     if (arith64(p, L))
       inv_basis_dispatch<double>(p, L, to, VolSet{a, dst}, nvol, st);
     else
       inv_basis_dispatch<float>(p, L, to, VolSet{a, dst}, nvol, st);
-    if (tm) tm->mark(st);
-    cur = b;
+      cur = b;
     cur_is_user = false;
     which ^= 1;
   }
@@ -1993,7 +2016,10 @@ fcc_status time_slots(const fcc_plan_s* p, const void* in, void* out, int direct
                       std::vector<float>* ms) {
   const int slots = slot_count(p, direction > 0 ? 0 : 1);
   ms->assign(slots, 0.f);
-  std::vector<hipEvent_t> ev(size_t(slots + 1) * reps, nullptr);
+  // the dense path is one library launch sequence timed as a whole (events
+  // between launches); the fast path records a start and stop per kernel
+  const bool whole = p->dense;
+  std::vector<hipEvent_t> ev(size_t(2) * slots * reps, nullptr);
   fcc_status s = FCC_OK;
   for (auto& e : ev) {
     hipError_t he = hipEventCreate(&e);
@@ -2003,18 +2029,20 @@ fcc_status time_slots(const fcc_plan_s* p, const void* in, void* out, int direct
     }
   }
   for (int r = 0; r < reps && s == FCC_OK; ++r) {
-    std::vector<hipEvent_t> sub(ev.begin() + size_t(r) * (slots + 1), ev.begin() + size_t(r + 1) * (slots + 1));
-    LaunchTimer tm;
-    tm.ev = &sub;
-    if (p->dense) {
-      tm.mark(st);
+    std::vector<hipEvent_t> sub(ev.begin() + size_t(r) * 2 * slots, ev.begin() + size_t(r + 1) * 2 * slots);
+    if (whole) {
+      (void)hipEventRecord(sub[0], st);
       s = dense_run(p, direction > 0 ? p->dfwd : p->dinv, 1, nullptr, nullptr, in, out, p->rowscale, st);
-      tm.mark(st);
+      (void)hipEventRecord(sub[1], st);
       continue;
     }
-    s = direction > 0 ? enqueue_forward(p, 1, one_vol(in), one_vol(out), one_vol(p->ws[0]), one_vol(p->ws[1]), st, &tm)
-                      : enqueue_inverse(p, 1, one_vol(in), one_vol(out), one_vol(p->ws[0]), one_vol(p->ws[1]), st, &tm);
-    if (p->n == 1 && s == FCC_OK) (void)hipEventRecord(sub[1], st);
+    LaunchTimer tm;
+    tm.ev = &sub;
+    t_timer = &tm;
+    s = direction > 0 ? enqueue_forward(p, 1, one_vol(in), one_vol(out), one_vol(p->ws[0]), one_vol(p->ws[1]), st)
+                      : enqueue_inverse(p, 1, one_vol(in), one_vol(out), one_vol(p->ws[0]), one_vol(p->ws[1]), st);
+    t_timer = nullptr;
+    if (s == FCC_OK && tm.next != sub.size()) s = FCC_ERR_HIP;  // launch count differs from the slot count
   }
   if (s == FCC_OK) {
     hipError_t he = hipStreamSynchronize(st);
@@ -2025,7 +2053,7 @@ fcc_status time_slots(const fcc_plan_s* p, const void* in, void* out, int direct
       double acc = 0.0;
       for (int r = 0; r < reps; ++r) {
         float t = 0.f;
-        (void)hipEventElapsedTime(&t, ev[size_t(r) * (slots + 1) + k], ev[size_t(r) * (slots + 1) + k + 1]);
+        (void)hipEventElapsedTime(&t, ev[size_t(r) * 2 * slots + 2 * k], ev[size_t(r) * 2 * slots + 2 * k + 1]);
         acc += t;
       }
       (*ms)[k] = float(acc / reps);
