@@ -70,10 +70,16 @@ def launch_bytes(n, prec, stages64, real_in, direction, sched):
                 out.append(("k_fwd_dct2 L%d" % L, N * (st + st)))
             else:
                 out.append(("k_fwd_level L%d" % L, N * (bi + st)))
-        out.append(("k_fwd_tail L%d-%d" % (Lt, D - 1), N * ((rin if Lt == 0 else st) + io_c)))
+        if Lt == D - 1 and D >= 2:  # the last level alone: DCT_2 on the cubes
+            out.append(("k_fwd_dct2 L%d" % (D - 1), N * (st + io_c)))
+        else:
+            out.append(("k_fwd_tail L%d-%d" % (Lt, D - 1), N * ((rin if Lt == 0 else st) + io_c)))
     else:
         Lt = max(0, D - sched["tail_levels"][1])
-        out.append(("k_inv_tail L%d-%d" % (D - 1, Lt), N * (io_c + (rin if Lt == 0 else st))))
+        if Lt == D - 1 and D >= 2:  # the last level alone: DCT_2^-1 on the cubes
+            out.append(("k_inv_dct2 L%d" % (D - 1), N * (io_c + st)))
+        else:
+            out.append(("k_inv_tail L%d-%d" % (D - 1, Lt), N * (io_c + (rin if Lt == 0 else st))))
         for L in range(Lt - 1, -1, -1):
             out.append(("k_inv_dct2 L%d" % L, N * (st + st)))
             bo = rin if L == 0 else st

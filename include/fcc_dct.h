@@ -126,7 +126,9 @@ const char* fcc_status_string(fcc_status s);
  * stage precision, in another kernel and may differ in the last bits.  Index
  * [0] is the forward transform, [1] the inverse.
  *   tail_levels[d] : the last 1..3 levels (node sizes <= 2^tail_levels) run
- *                    fused in one launch with the data resident in LDS.
+ *                    fused in one launch with the data resident in LDS (the
+ *                    last level alone, where B_2 = C_2 = I, is a per-cube
+ *                    DCT_2 pass).
  *   tile[d][L][.]  : at levels L = 0, 1 the gather pass of the basis change
  *                    walks the cubes of a node in tiles of 2^t0 x 2^t1 x 2^t2
  *                    cubes (log2 sizes; {0,0,0} = plain lexicographic order).

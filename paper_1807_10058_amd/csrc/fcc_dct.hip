@@ -1506,6 +1506,14 @@ fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
     src = a;
     src_t = to;
   }
+  // the last level alone (node size 2, B_2 = I): DCT_2 on the cubes
+  if (p->tail_Lt[0] == p->D - 1 && p->D >= 2) {
+    if (arith64(p, p->D - 1))
+      fwd_dct2_dispatch<double>(p, p->D - 1, cplx_type(p), VolSet{src, out}, nvol, st);
+    else
+      fwd_dct2_dispatch<float>(p, p->D - 1, cplx_type(p), VolSet{src, out}, nvol, st);
+    return launch_status("forward level launch");
+  }
   // the last levels (node size <= kTailNl) in one LDS-resident launch
   if (p->stages64)
     fwd_tail_dispatch<double>(p, src_t, cplx_type(p), VolSet{src, out}, nvol, st);
@@ -1521,8 +1529,16 @@ fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
     copy1_dispatch(cplx_type(p), real_or_cplx, VolSet{in, out}, nvol, st);
     return launch_status("inverse n=1 launch");
   }
-  // the last levels first, in one LDS-resident launch
-  {
+  // the last level alone (node size 2, C_2 = I): DCT_2^{-1} on the cubes
+  // (its output type is the stage type of level D-1)
+  const bool last_only = p->tail_Lt[1] == p->D - 1 && p->D >= 2 && buf_type(p, p->D - 1) == stage_type(p);
+  if (last_only) {
+    if (arith64(p, p->D - 1))
+      inv_dct2_dispatch<double>(p, p->D - 1, cplx_type(p), VolSet{in, ws0}, nvol, st);
+    else
+      inv_dct2_dispatch<float>(p, p->D - 1, cplx_type(p), VolSet{in, ws0}, nvol, st);
+  } else {
+    // the last levels first, in one LDS-resident launch
     const int Lt = p->tail_Lt[1];
     VolPtrs dst = Lt == 0 ? out : ws0;
     DT to = Lt == 0 ? real_or_cplx : buf_type(p, Lt);
@@ -1530,7 +1546,7 @@ fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
       inv_tail_dispatch<double>(p, cplx_type(p), to, VolSet{in, dst}, nvol, st);
     else
       inv_tail_dispatch<float>(p, cplx_type(p), to, VolSet{in, dst}, nvol, st);
-    }
+  }
   VolPtrs cur = ws0;
   bool cur_is_user = false;
   int which = 0;  // scratch array holding the current level's data
@@ -1765,16 +1781,17 @@ fcc_tuning default_tuning(int n) {
     t.tile[1][0][a] = 2;  // inverse levels 0 and 1: 4x4x4
     t.tile[1][1][a] = 2;
   }
-  // forward: two passes at the top levels; below, one pass with XCD-contiguous
-  // blocks up to n = 64, two passes over groups of 64 nodes above
-  t.map[0][0] = FCC_MAP_SPLIT;
-  t.map[0][1] = n <= 64 ? FCC_MAP_XCD : FCC_MAP_SPLIT;
-  for (int L = 2; L < 10; ++L) t.map[0][L] = n <= 64 ? FCC_MAP_XCD : (FCC_MAP_SPLIT | FCC_MAP_NODES64);
-  // inverse: the 8 rows of a cube together at the top, XCD-contiguous at levels 2-3
-  t.map[1][0] = FCC_MAP_F_INNER;
-  t.map[1][1] = FCC_MAP_F_INNER;
-  t.map[1][2] = FCC_MAP_XCD;
-  t.map[1][3] = FCC_MAP_XCD;
+  // forward: gather and DCT_2 as two passes, groups of 64 nodes from level 2 on
+  for (int L = 0; L < 10; ++L) t.map[0][L] = L < 2 ? FCC_MAP_SPLIT : (FCC_MAP_SPLIT | FCC_MAP_NODES64);
+  // inverse: small n XCD-contiguous (groups of 64 nodes from level 2 on); larger
+  // n the 8 rows of a cube together at the top, XCD-contiguous at levels 2-3
+  if (n <= 64) {
+    t.map[1][0] = t.map[1][1] = FCC_MAP_XCD;
+    for (int L = 2; L < 10; ++L) t.map[1][L] = FCC_MAP_NODES64 | FCC_MAP_XCD;
+  } else {
+    t.map[1][0] = t.map[1][1] = FCC_MAP_F_INNER;
+    t.map[1][2] = t.map[1][3] = FCC_MAP_XCD;
+  }
   return t;
 }
 bool valid_tuning(const fcc_tuning& t) {
@@ -1921,14 +1938,16 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
   if (s == FCC_OK && p->D > 0) {
     // FP64 node constants for the levels with at most kNodeTableMax nodes
     long long total = 0;
+    // (not for the last level: with one cube per node, the 480 bytes of a
+    // table entry would cost more traffic than forming A from the phases)
     for (int L = 0; L < p->D; ++L) {
       p->node_off[L] = -1;
-      if ((1LL << (3 * L)) <= kNodeTableMax) {
+      if ((1LL << (3 * L)) <= kNodeTableMax && L < p->D - 1) {
         p->node_off[L] = total;
         total += 1LL << (3 * L);
       }
     }
-    hipError_t e = hipMalloc(&p->nodes, sizeof(NodeConst) * total);
+    hipError_t e = total > 0 ? hipMalloc(&p->nodes, sizeof(NodeConst) * total) : hipSuccess;
     if (e != hipSuccess) s = hip_fail(e, "hipMalloc(node table)", __LINE__);
     for (int L = 0; s == FCC_OK && L < p->D; ++L)
       if (p->node_off[L] >= 0) {
