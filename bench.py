@@ -105,7 +105,10 @@ def measured_traffic(workload, slot):
     profile of this workload (FETCH_SIZE and WRITE_SIZE scaled by a plain copy),
     or None when there is none or the kernel sources changed since it was taken."""
     import re
-    path = os.path.join(ROOT, "profiles", "traffic_%s.md" % workload)
+    name = {"c2": "traffic_c2_n64_forward.md", "c4": "traffic_c4_n256_forward_inverse.md"}.get(workload)
+    if not name:
+        return None
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -117,7 +120,7 @@ def measured_traffic(workload, slot):
         if len(cells) >= 4 and cells[0] == slot:
             try:
                 return {"read_bytes": float(cells[2]), "write_bytes": float(cells[3]),
-                        "total_bytes": float(cells[2]) + float(cells[3]), "source": "profiles/traffic_%s.md" % workload}
+                        "total_bytes": float(cells[2]) + float(cells[3]), "source": "profiles/" + name}
             except ValueError:
                 return None
     return None

@@ -120,11 +120,12 @@ const char* fcc_status_string(fcc_status s);
 
 /* ---- schedule tuning ---------------------------------------------------- */
 
-/* How a plan schedules the levels of eq. FastAlgorithm on the GPU.  Tile and
- * map choices change no result bit (every output row is summed in the same
- * order).  A different tail depth evaluates the same expressions, at the same
- * stage precision, in another kernel and may differ in the last bits.  Index
- * [0] is the forward transform, [1] the inverse.
+/* How a plan schedules the levels of eq. FastAlgorithm on the GPU.  Tiles,
+ * block numbering and node groups change no result bit (every output row is
+ * summed in the same order).  A different tail depth or FCC_MAP_SPLIT
+ * evaluates the same expressions, at the same stage precision, in another
+ * kernel and may differ in the last bits.  Index [0] is the forward
+ * transform, [1] the inverse.
  *   tail_levels[d] : the last 1..3 levels (node sizes <= 2^tail_levels) run
  *                    fused in one launch with the data resident in LDS (the
  *                    last level alone, where B_2 = C_2 = I, is a per-cube

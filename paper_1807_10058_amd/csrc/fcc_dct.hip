@@ -30,32 +30,8 @@ namespace fcc {
 // Per-node constants
 // ---------------------------------------------------------------------------
 
-// Powers h_d^k, k = -3..3, of the half phases h_d = exp(i pi phi_d) of node J
-// at level L (phi = ((r,s,t) + J) / 2^L); hph holds h_d for every J_d.
-template <typename R>
-__device__ __forceinline__ void node_powers(const double2* __restrict__ hph, int L, const int J[3],
-                                            cx<R> P[3][7]) {
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    double2 hv = hph[(d << L) + J[d]];
-    cx<R> h{R(hv.x), R(hv.y)};
-    cx<R> h2 = h * h;
-    cx<R> h3 = h2 * h;
-    P[d][3] = {R(1), R(0)};
-    P[d][4] = h;
-    P[d][5] = h2;
-    P[d][6] = h3;
-    P[d][2] = conj(h);
-    P[d][1] = conj(h2);
-    P[d][0] = conj(h3);
-  }
-}
-
-template <typename R>
-__device__ __forceinline__ cx<R> phase(const cx<R> P[3][7], int l0, int l1, int l2) {
-  return P[0][l0 + 3] * P[1][l1 + 3] * P[2][l2 + 3];
-}
-
+// The half phases h_d = exp(i pi phi_d) of node J at level L (phi = ((r,s,t) +
+// J) / 2^L): the phase table hph holds h_d for every J_d of the level.
 // Positive powers only: Q[d][k] = h_d^(k+1), k = 0..2; negative powers are
 // conjugates (|h_d| = 1).  Indices are compile-time constants at every use.
 template <typename R>
@@ -98,11 +74,45 @@ __device__ __forceinline__ void apply_A(const cx<R> Q[3][3], const cx<R> y[8], c
 
 // c = (sigma, tau, rho)(phi) = (T_100, T_010, T_001)(phi) and the five
 // monomials of the coefficient polynomials, in the fixed order
-// {1, c3, c1, c2, c1 c3} (the only ones the derivation produces).
+// {1, c3, c1, c2, c1 c3} (the only ones the derivation produces).  Each c_d is
+// an orbit sum of exp(2 pi i k.phi) = prod_d g_d^(k_d) with g_d = h_d^2 and
+// k_d in {-1, 0, 1} (the c-terms), so a node needs a few complex products.
+template <typename R, int l>
+__device__ __forceinline__ cx<R> gpow(cx<R> g) {
+  if constexpr (l > 0)
+    return g;
+  else
+    return conj(g);
+}
+template <typename R, int l0, int l1, int l2>
+__device__ __forceinline__ cx<R> gphase(const cx<R> g[3]) {
+  if constexpr (l0 != 0) {
+    cx<R> v = gpow<R, l0>(g[0]);
+    if constexpr (l1 != 0) v = v * gpow<R, l1>(g[1]);
+    if constexpr (l2 != 0) v = v * gpow<R, l2>(g[2]);
+    return v;
+  } else if constexpr (l1 != 0) {
+    cx<R> v = gpow<R, l1>(g[1]);
+    if constexpr (l2 != 0) v = v * gpow<R, l2>(g[2]);
+    return v;
+  } else if constexpr (l2 != 0) {
+    return gpow<R, l2>(g[2]);
+  } else {
+    return cx<R>{R(1), R(0)};
+  }
+}
 template <typename R>
-__device__ __forceinline__ void node_monomials(const cx<R> P[3][7], cx<R> mono[kNumMono]) {
+__device__ __forceinline__ void node_mono(const double2* __restrict__ hph, int L, const int J[3],
+                                          cx<R> mono[kNumMono]) {
+  cx<R> g[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double2 hv = hph[(d << L) + J[d]];
+    const cx<R> h{R(hv.x), R(hv.y)};
+    g[d] = h * h;
+  }
   cx<R> c[3] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
-#define FCC_ADD_C(d, l0, l1, l2, w) c[d] = c[d] + R(w) * phase(P, 2 * (l0), 2 * (l1), 2 * (l2));
+#define FCC_ADD_C(d, l0, l1, l2, w) c[d] = c[d] + R(w) * gphase<R, (l0), (l1), (l2)>(g);
   FCC_C_TERMS(FCC_ADD_C)
 #undef FCC_ADD_C
   mono[0] = {R(1), R(0)};
@@ -311,8 +321,7 @@ __device__ __forceinline__ cx<R> gather_row(const TI* __restrict__ in, int n, in
 // partial pivoting per cube, which stays accurate where A is ill conditioned;
 // applying a precomputed inverse raised the n = 256 round-trip error 1e4-fold.)
 struct NodeConst {
-  double2 a4[16], a3[9];   // blocks of A(phi)
-  double2 mono[kNumMono];  // {1, c3, c1, c2, c1 c3} of c = (sigma, tau, rho)(phi)
+  double2 a4[16], a3[9];  // blocks of A(phi)
 };
 constexpr long long kNodeTableMax = 1 << 18;  // levels with at most this many nodes get a table (126 MB)
 
@@ -330,10 +339,6 @@ __global__ void k_node_table(NodeConst* out, int L, const double2* __restrict__ 
     for (int j = 0; j < 4; ++j) nc.a4[4 * i + j] = make_double2(a4[i][j].x, a4[i][j].y);
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) nc.a3[3 * i + j] = make_double2(a3[i][j].x, a3[i][j].y);
-  cx<double> P[3][7], mono[kNumMono];
-  node_powers(hph, L, J, P);
-  node_monomials(P, mono);
-  for (int q = 0; q < kNumMono; ++q) nc.mono[q] = make_double2(mono[q].x, mono[q].y);
 }
 
 template <typename R>
@@ -383,17 +388,9 @@ __device__ __forceinline__ long long gather_block(int xcd) {
 }
 
 template <typename R>
-__device__ __forceinline__ void load_mono(const NodeConst* nodes, const double2* __restrict__ hph, int L,
-                                          const int J[3], cx<R> mono[kNumMono]) {
-  if (nodes) {
-    const NodeConst& nc = nodes[((long long)J[0] << (2 * L)) | ((long long)J[1] << L) | J[2]];
-#pragma unroll
-    for (int q = 0; q < kNumMono; ++q) mono[q] = ldc<R>(nc.mono[q]);
-  } else {
-    cx<R> P[3][7];
-    node_powers(hph, L, J, P);
-    node_monomials(P, mono);
-  }
+__device__ __forceinline__ void load_mono(const NodeConst*, const double2* __restrict__ hph, int L, const int J[3],
+                                          cx<R> mono[kNumMono]) {
+  node_mono(hph, L, J, mono);
 }
 
 // Forward level L, first pass: y(def, abc) = row (def,abc) of B_nl(c) applied to
@@ -719,15 +716,7 @@ __device__ __forceinline__ long long node_index(const int G3[3], int Lg) {
 }
 template <typename R>
 __device__ __forceinline__ void tail_mono(const TailLevels& tl, int l, int Lg, const int G3[3], cx<R> mono[kNumMono]) {
-  if (tl.nodes[l]) {
-    const NodeConst& nc = tl.nodes[l][node_index(G3, Lg)];
-#pragma unroll
-    for (int q = 0; q < kNumMono; ++q) mono[q] = ldc<R>(nc.mono[q]);
-  } else {
-    cx<R> P[3][7];
-    node_powers(tl.hph[l], Lg, G3, P);
-    node_monomials(P, mono);
-  }
+  node_mono(tl.hph[l], Lg, G3, mono);
 }
 template <typename R>
 __device__ __forceinline__ void tail_A(const TailLevels& tl, int l, int Lg, const int G3[3], cx<R> a4[4][4],
@@ -1938,11 +1927,12 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
   if (s == FCC_OK && p->D > 0) {
     // FP64 node constants for the levels with at most kNodeTableMax nodes
     long long total = 0;
-    // (not for the last level: with one cube per node, the 480 bytes of a
-    // table entry would cost more traffic than forming A from the phases)
+    // (only where a node has at least 64 cubes, n >> L >= 8: with fewer cubes
+    // per node the 400 bytes of a table entry cost more traffic than forming
+    // A from the phases)
     for (int L = 0; L < p->D; ++L) {
       p->node_off[L] = -1;
-      if ((1LL << (3 * L)) <= kNodeTableMax && L < p->D - 1) {
+      if ((1LL << (3 * L)) <= kNodeTableMax && (p->n >> L) >= 8) {
         p->node_off[L] = total;
         total += 1LL << (3 * L);
       }

@@ -33,29 +33,46 @@ SCHEDULES = [
 ]
 
 
-def run(n, prec, flags, t, x):
+def run(n, prec, flags, t, x, X_in=None):
+    """forward of x, and inverse of X_in (default: of the forward output)"""
     plan = fcc.fcc_dct_plan_tuned(n, prec=prec, flags=flags, tuning=t)
-    real = bool(flags & fcc.FCC_REAL_INPUT)
     X = torch.empty(n ** 3, dtype=gu.cdtype(prec), device=gu.DEV)
     y = torch.empty_like(x)
     fcc.fcc_dct_forward(plan, x, X)
-    fcc.fcc_dct_inverse(plan, X, y)
+    fcc.fcc_dct_inverse(plan, X if X_in is None else X_in, y)
     torch.cuda.synchronize()
     out = X.cpu().numpy(), y.cpu().numpy(), fcc.fcc_dct_get_tuning(plan)
     fcc.fcc_dct_destroy(plan)
-    assert real == (not torch.is_complex(x))
     return out
+
+
+def split_key(t, n):
+    """the forward levels that run as two launches and the tail depths: the
+    schedule parts that change which kernels evaluate an expression"""
+    D = n.bit_length() - 1
+    lt = max(0, D - t["tail_levels"][0])
+    return tuple(bool(t["map"][0][L] & SP) for L in range(lt)), tuple(t["tail_levels"])
 
 
 @pytest.mark.parametrize("n,prec", [(4, fcc.FCC_PREC_FP64), (16, fcc.FCC_PREC_FP32), (64, fcc.FCC_PREC_FP32),
                                     (32, fcc.FCC_PREC_FP64)])
 def test_tile_and_map_choices_are_bit_identical(n, prec):
+    """Tiles, block numbering and node groups change no result bit; one-pass
+    against two-pass levels agree to rounding."""
     x = torch.from_numpy(workloads.uniform_fp64(n, 7)).to(gu.DEV, gu.rdtype(prec))
     X0, y0, _ = run(n, prec, fcc.FCC_REAL_INPUT, SCHEDULES[0], x)
-    for t in SCHEDULES[1:]:
-        X1, y1, got = run(n, prec, fcc.FCC_REAL_INPUT, t, x)
-        assert np.array_equal(X0.view(np.uint8), X1.view(np.uint8)), (n, t)
-        assert np.array_equal(y0.view(np.uint8), y1.view(np.uint8)), (n, t)
+    X0_dev = torch.from_numpy(X0).to(gu.DEV)
+    tol = 1e-13 if prec == fcc.FCC_PREC_FP64 else 1e-6
+    ref_by_key = {split_key(SCHEDULES[0], n): X0}
+    for i, t in enumerate(SCHEDULES[1:], 1):
+        X1, y1, got = run(n, prec, fcc.FCC_REAL_INPUT, t, x, X0_dev)
+        key = split_key(t, n)
+        if key in ref_by_key:
+            assert np.array_equal(ref_by_key[key].view(np.uint8), X1.view(np.uint8)), (n, i)
+        ref_by_key.setdefault(key, X1)
+        assert gu.maxrel(X1, X0) <= tol, (n, i)
+        # the inverse never splits differently: same input, same bits
+        assert np.array_equal(y0.view(np.uint8), y1.view(np.uint8)), (n, i)
         lgm0 = max(0, n.bit_length() - 2)  # tile sides clamp to the node's cubes per side
         assert all(v <= lgm0 for v in got["tile"][0][0])
 
