@@ -122,9 +122,9 @@ const char* fcc_status_string(fcc_status s);
 
 /* How a plan schedules the levels of eq. FastAlgorithm on the GPU.  Tiles,
  * block numbering and node groups change no result bit (every output row is
- * summed in the same order).  A different tail depth or FCC_MAP_SPLIT
- * evaluates the same expressions, at the same stage precision, in another
- * kernel and may differ in the last bits.  Index [0] is the forward
+ * summed in the same order).  A different tail depth, FCC_MAP_SPLIT or
+ * FCC_MAP_BALANCE evaluates the same expressions, at the same stage
+ * precision, in another kernel or order and may differ in the last bits.  Index [0] is the forward
  * transform, [1] the inverse.
  *   tail_levels[d] : the last 1..3 levels (node sizes <= 2^tail_levels) run
  *                    fused in one launch with the data resident in LDS (the
@@ -147,13 +147,19 @@ const char* fcc_status_string(fcc_status s);
  *                    DCT_2 (x) I in one launch, the 8 rows of each cube on 8
  *                    adjacent lanes (FCC_MAP_F_INNER is implied there);
  *                    FCC_MAP_SPLIT runs them as two launches instead (gather,
- *                    then DCT_2 on the cubes).  The inverse always uses two. */
+ *                    then DCT_2 on the cubes).  The inverse always uses two.
+ *                    FCC_MAP_BALANCE (two-pass gathers only) sums each long
+ *                    row on 2 or 4 adjacent lanes (by the mean row length of
+ *                    its position in the cube) and adds the parts; it changes
+ *                    the summation order, so results may differ in the last
+ *                    bits.  It takes precedence over FCC_MAP_F_INNER. */
 enum {
   FCC_MAP_XCD = 1u << 0,
   FCC_MAP_F_INNER = 1u << 1,
   FCC_MAP_NODES8 = 1u << 2,
   FCC_MAP_NODES64 = 1u << 3,
-  FCC_MAP_SPLIT = 1u << 4
+  FCC_MAP_SPLIT = 1u << 4,
+  FCC_MAP_BALANCE = 1u << 5
 };
 typedef struct {
   int tail_levels[2];

@@ -264,47 +264,68 @@ __device__ __forceinline__ void load_polys(const DevLevel& lv, double* sp) {
 // Gather sum_e coef(pid_e) in[J + 2^L src_e] over one sliced row, in entry
 // order.  Software pipelined in chunks of 8: the table entries of chunk c+1
 // are loaded while the data of chunk c is in flight, so a row of len entries
-// costs about len/8 dependent memory round trips.
-template <typename R, typename TI>
-__device__ __forceinline__ cx<R> gather_row(const TI* __restrict__ in, int n, int L, const int J[3], const DevSide& sd,
-                                            int S, int r, int j, const double* sp, int nconst,
-                                            const cx<R> mono[kNumMono]) {
-  constexpr int U = 8;
-  const int e0 = sd.start[r] + j, len = sd.len[r];
-  cx<R> acc{R(0), R(0)};
-  if (len <= 0) return acc;
-  uint32_t s8[U];
-  uint16_t p8[U];
+// costs about len/8 dependent memory round trips.  row_begin issues the row's
+// first table loads (kernels call it before the barrier that publishes the
+// polynomials in LDS, so the two overlap); row_finish does the rest.
+constexpr int kChunk = 8;
+struct RowCursor {
+  int e0, len;
+  uint32_t s8[kChunk];
+  uint16_t p8[kChunk];
+};
+__device__ __forceinline__ void row_begin(const DevSide& sd, int S, int r, int j, RowCursor& rc, int k = 0,
+                                          int kf = 0) {
+  const int len = sd.len[r];
+  // part k of 2^kf: a contiguous range of the row's entries
+  const int per = (len + (1 << kf) - 1) >> kf;
+  const int eb = min(len, k * per);
+  rc.e0 = sd.start[r] + j + eb * S;
+  rc.len = min(len, eb + per) - eb;
+  if (rc.len <= 0) return;
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int e = min(u, len - 1);  // past the row's end: repeat its last entry, unused
-    s8[u] = sd.src[e0 + e * S];
-    p8[u] = sd.pid[e0 + e * S];
+  for (int u = 0; u < kChunk; ++u) {
+    const int e = min(u, rc.len - 1);  // past the row's end: repeat its last entry, unused
+    rc.s8[u] = sd.src[rc.e0 + e * S];
+    rc.p8[u] = sd.pid[rc.e0 + e * S];
   }
-  for (int c = 0; c < len; c += U) {
-    cx<R> v8[U];
+}
+// Sum of the parts of a row over its 2^kf adjacent lanes (every lane gets it).
+template <typename R>
+__device__ __forceinline__ cx<R> combine_parts(cx<R> v, int kf) {
+  if (kf >= 1) v = v + cx<R>{__shfl_xor(v.x, 1), __shfl_xor(v.y, 1)};
+  if (kf >= 2) v = v + cx<R>{__shfl_xor(v.x, 2), __shfl_xor(v.y, 2)};
+  return v;
+}
+template <typename R, typename TI>
+__device__ __forceinline__ cx<R> row_finish(const TI* __restrict__ in, int n, int L, const int J[3], const DevSide& sd,
+                                            int S, RowCursor& rc, const double* sp, int nconst,
+                                            const cx<R> mono[kNumMono]) {
+  cx<R> acc{R(0), R(0)};
+  const int len = rc.len, e0 = rc.e0;
+  for (int c = 0; c < len; c += kChunk) {
+    cx<R> v8[kChunk];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      v8[u] = IO<TI, R>::ld(in, gpos(n, L, J, int(s8[u] >> 20), int((s8[u] >> 10) & 1023u), int(s8[u] & 1023u)));
-    uint32_t sn[U];
-    uint16_t pn[U];
-    const bool more = c + U < len;
+    for (int u = 0; u < kChunk; ++u)
+      v8[u] = IO<TI, R>::ld(in, gpos(n, L, J, int(rc.s8[u] >> 20), int((rc.s8[u] >> 10) & 1023u), int(rc.s8[u] & 1023u)));
+    uint32_t sn[kChunk];
+    uint16_t pn[kChunk];
+    const bool more = c + kChunk < len;
     if (more) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = min(c + U + u, len - 1);
+      for (int u = 0; u < kChunk; ++u) {
+        const int e = min(c + kChunk + u, len - 1);
         sn[u] = sd.src[e0 + e * S];
         pn[u] = sd.pid[e0 + e * S];
       }
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (c + u < len) acc = acc + poly_value(sp, nconst, p8[u], mono) * v8[u];
+    for (int u = 0; u < kChunk; ++u)
+      if (c + u < len) acc = acc + poly_value(sp, nconst, rc.p8[u], mono) * v8[u];
     if (more) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        s8[u] = sn[u];
-        p8[u] = pn[u];
+      for (int u = 0; u < kChunk; ++u) {
+        rc.s8[u] = sn[u];
+        rc.p8[u] = pn[u];
       }
     }
   }
@@ -379,6 +400,36 @@ __device__ __forceinline__ RowIdx row_of(long long t, int n, int L, CubeOrder or
   return r;
 }
 
+// Balanced map (GatherMap::balance): thread t of one volume -> (row, lane k
+// of the row's K = 2^kf lanes).
+struct RowPart {
+  RowIdx r;
+  int k, kf;
+};
+__device__ __forceinline__ RowPart row_part_of(long long t, int n, int L, CubeOrder ord, const GatherMap& gm) {
+  const int mask = (1 << L) - 1;
+  const int lgm = __ffs(n) - 2 - L;
+  const long long per = gm.off[8];
+  const long long grp = t / per;
+  const long long r0 = t - grp * per;
+  int i = 0;
+#pragma unroll
+  for (int q = 1; q < 8; ++q) i += r0 >= gm.off[q] ? 1 : 0;
+  RowPart rp;
+  rp.r.f = gm.forder[i];
+  rp.kf = gm.kf[i];
+  const long long v = r0 - gm.off[i];
+  rp.k = int(v & ((1 << rp.kf) - 1));
+  const long long w = v >> rp.kf;  // cube, then node within the group
+  rp.r.cube = int(w >> gm.lg);
+  const int jf = int((grp << gm.lg) | (w & ((1LL << gm.lg) - 1)));
+  rp.r.J[0] = jf >> (2 * L);
+  rp.r.J[1] = (jf >> L) & mask;
+  rp.r.J[2] = jf & mask;
+  cube_abc(rp.r.cube, lgm, ord, rp.r.a);
+  return rp;
+}
+
 // Block index of a gather launch (GatherMap::xcd: blocks i, i+8, i+16, ... run
 // on one XCD and get one contiguous range).
 __device__ __forceinline__ long long gather_block(int xcd) {
@@ -399,19 +450,33 @@ template <typename R, typename TI>
 __global__ __launch_bounds__(256) void k_fwd_gather(VolSet vs, int nvol, int n, int L, DevLevel lv,
                                                     const double2* __restrict__ hph, const NodeConst* nodes, GatherMap gm) {
   __shared__ double sp[kMaxPoly * kNumMono];
-  load_polys(lv, sp);
-  const long long N = (long long)n * n * n;
+  const long long N = gm.balance ? gm.off[8] * ((1LL << (3 * L)) >> gm.lg) : (long long)n * n * n;  // threads per volume
   const long long tg = gather_block(gm.xcd) * blockDim.x + threadIdx.x;
-  if (tg >= N * nvol) return;
-  const long long vol = tg / N, t = tg - vol * N;
+  const bool active = tg < N * nvol;
+  const long long vol = active ? tg / N : 0, t = tg - vol * N;
+  RowIdx ri{};
+  RowCursor rc{};
+  cx<R> mono[kNumMono];
+  int k = 0, kf = 0;
+  if (active) {
+    if (gm.balance) {
+      const RowPart rp = row_part_of(t, n, L, lv.b.order, gm);
+      ri = rp.r, k = rp.k, kf = rp.kf;
+    } else {
+      ri = row_of(t, n, L, lv.b.order, lv.S, gm);
+    }
+    const int slice = ri.cube / lv.S;
+    row_begin(lv.b, lv.S, slice * 8 + ri.f, ri.cube - slice * lv.S, rc, k, kf);
+    load_mono(nodes, hph, L, ri.J, mono);
+  }
+  load_polys(lv, sp);
+  if (!active) return;
   const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, vol));
   cx<R>* __restrict__ out = static_cast<cx<R>*>(vol_ptr(vs.out, vol));
-  const RowIdx ri = row_of(t, n, L, lv.b.order, lv.S, gm);
-  cx<R> mono[kNumMono];
-  load_mono(nodes, hph, L, ri.J, mono);
-  const int slice = ri.cube / lv.S, j = ri.cube - slice * lv.S;
-  const cx<R> y = gather_row<R, TI>(in, n, L, ri.J, lv.b, lv.S, slice * 8 + ri.f, j, sp, lv.nconst, mono);
-  out[gpos(n, L, ri.J, ((ri.f >> 2) & 1) + 2 * ri.a[0], ((ri.f >> 1) & 1) + 2 * ri.a[1], (ri.f & 1) + 2 * ri.a[2])] = y;
+  cx<R> y = row_finish<R, TI>(in, n, L, ri.J, lv.b, lv.S, rc, sp, lv.nconst, mono);
+  if (gm.balance) y = combine_parts(y, kf);
+  if (k == 0)
+    out[gpos(n, L, ri.J, ((ri.f >> 2) & 1) + 2 * ri.a[0], ((ri.f >> 1) & 1) + 2 * ri.a[1], (ri.f & 1) + 2 * ri.a[2])] = y;
 }
 
 // Forward level L in one pass.  Lane f of an aligned group of 8 lanes gathers
@@ -501,19 +566,25 @@ __global__ __launch_bounds__(256) void k_fwd_level(VolSet vs, int nvol, int n, i
                                                    const double2* __restrict__ hph, const NodeConst* nodes,
                                                    GatherMap gm) {
   __shared__ double sp[kMaxPoly * kNumMono];
-  load_polys(lv, sp);
   const long long N = (long long)n * n * n;
   const long long tg = gather_block(gm.xcd) * blockDim.x + threadIdx.x;
-  if (tg >= N * nvol) return;  // whole groups: N is a multiple of 8
-  const long long vol = tg / N, t = tg - vol * N;
+  const bool active = tg < N * nvol;  // whole groups of 8 lanes: N is a multiple of 8
+  const long long vol = active ? tg / N : 0, t = tg - vol * N;
+  const int f = int(t & 7);
+  CubeUnit cu{};
+  RowCursor rc{};
+  cx<R> mono[kNumMono];
+  if (active) {
+    cu = unit_of(t >> 3, n, L, lv.b.order, gm.lg);
+    const int slice = cu.cube / lv.S;
+    row_begin(lv.b, lv.S, slice * 8 + f, cu.cube - slice * lv.S, rc);
+    load_mono(nodes, hph, L, cu.J, mono);
+  }
+  load_polys(lv, sp);
+  if (!active) return;
   const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, vol));
   TO* __restrict__ out = static_cast<TO*>(vol_ptr(vs.out, vol));
-  const int f = int(t & 7);
-  const CubeUnit cu = unit_of(t >> 3, n, L, lv.b.order, gm.lg);
-  cx<R> mono[kNumMono];
-  load_mono(nodes, hph, L, cu.J, mono);
-  const int slice = cu.cube / lv.S, j = cu.cube - slice * lv.S;
-  const cx<R> y = gather_row<R, TI>(in, n, L, cu.J, lv.b, lv.S, slice * 8 + f, j, sp, lv.nconst, mono);
+  const cx<R> y = row_finish<R, TI>(in, n, L, cu.J, lv.b, lv.S, rc, sp, lv.nconst, mono);
   const cx<R> z = hadamard8_lanes(apply_A_lanes<R, kTable>(nodes, hph, L, cu.J, f, y), f);
   IO<TO, R>::st(out, gpos(n, L, cu.J, ((f >> 2) & 1) + 2 * cu.a[0], ((f >> 1) & 1) + 2 * cu.a[1], (f & 1) + 2 * cu.a[2]),
                 z);
@@ -625,19 +696,33 @@ template <typename R, typename TO>
 __global__ __launch_bounds__(256) void k_inv_basis(VolSet vs, int nvol, int n, int L, DevLevel lv,
                                                    const double2* __restrict__ hph, const NodeConst* nodes, GatherMap gm) {
   __shared__ double sp[kMaxPoly * kNumMono];
-  load_polys(lv, sp);
-  const long long N = (long long)n * n * n;
+  const long long N = gm.balance ? gm.off[8] * ((1LL << (3 * L)) >> gm.lg) : (long long)n * n * n;  // threads per volume
   const long long tg = gather_block(gm.xcd) * blockDim.x + threadIdx.x;
-  if (tg >= N * nvol) return;
-  const long long vol = tg / N, t = tg - vol * N;
+  const bool active = tg < N * nvol;
+  const long long vol = active ? tg / N : 0, t = tg - vol * N;
+  RowIdx ri{};
+  RowCursor rc{};
+  cx<R> mono[kNumMono];
+  int k = 0, kf = 0;
+  if (active) {
+    if (gm.balance) {
+      const RowPart rp = row_part_of(t, n, L, lv.c.order, gm);
+      ri = rp.r, k = rp.k, kf = rp.kf;
+    } else {
+      ri = row_of(t, n, L, lv.c.order, lv.S, gm);
+    }
+    const int slice = ri.cube / lv.S;
+    row_begin(lv.c, lv.S, slice * 8 + ri.f, ri.cube - slice * lv.S, rc, k, kf);
+    load_mono(nodes, hph, L, ri.J, mono);
+  }
+  load_polys(lv, sp);
+  if (!active) return;
   const cx<R>* __restrict__ in = static_cast<const cx<R>*>(vol_ptr(vs.in, vol));
   TO* __restrict__ out = static_cast<TO*>(vol_ptr(vs.out, vol));
-  const RowIdx ri = row_of(t, n, L, lv.c.order, lv.S, gm);
-  cx<R> mono[kNumMono];
-  load_mono(nodes, hph, L, ri.J, mono);
-  const int slice = ri.cube / lv.S, j = ri.cube - slice * lv.S;
-  const cx<R> x = gather_row<R, cx<R>>(in, n, L, ri.J, lv.c, lv.S, slice * 8 + ri.f, j, sp, lv.nconst, mono);
-  IO<TO, R>::st(out, gpos(n, L, ri.J, ((ri.f >> 2) & 1) + 2 * ri.a[0], ((ri.f >> 1) & 1) + 2 * ri.a[1], (ri.f & 1) + 2 * ri.a[2]), x);
+  cx<R> x = row_finish<R, cx<R>>(in, n, L, ri.J, lv.c, lv.S, rc, sp, lv.nconst, mono);
+  if (gm.balance) x = combine_parts(x, kf);
+  if (k == 0)
+    IO<TO, R>::st(out, gpos(n, L, ri.J, ((ri.f >> 2) & 1) + 2 * ri.a[0], ((ri.f >> 1) & 1) + 2 * ri.a[1], (ri.f & 1) + 2 * ri.a[2]), x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1288,22 +1373,46 @@ GatherMap gmap(const fcc_plan_s* p, int d, int L) {
   const unsigned m = p->tune.map[d][L];
   const long long half = p->n >> (L + 1), cubes = half * half * half;
   const bool whole = cubes >= p->lv[L].S;
-  GatherMap g{int(m & FCC_MAP_XCD), int(whole && (m & FCC_MAP_F_INNER) != 0), 3 * L};
+  GatherMap g{};
+  g.xcd = int(m & FCC_MAP_XCD);
+  g.f_inner = int(whole && (m & FCC_MAP_F_INNER) != 0);
+  g.lg = 3 * L;
   if (L >= 2 && (m & FCC_MAP_NODES8)) g.lg = std::min(3, 3 * L);
   if (L >= 2 && (m & FCC_MAP_NODES64)) g.lg = std::min(6, 3 * L);
+  if (m & FCC_MAP_BALANCE) {
+    g.balance = 1;
+    g.f_inner = 0;
+    // f by decreasing lanes per row keeps every row's lanes aligned
+    int ord[8] = {0, 1, 2, 3, 4, 5, 6, 7};
+    std::stable_sort(ord, ord + 8, [&](int a, int b) { return p->kf[d][L][a] > p->kf[d][L][b]; });
+    const long long unit = cubes << g.lg;  // threads per lane slot of one f in a group
+    g.off[0] = 0;
+    for (int i = 0; i < 8; ++i) {
+      g.forder[i] = (unsigned char)ord[i];
+      g.kf[i] = p->kf[d][L][ord[i]];
+      g.off[i + 1] = g.off[i] + (unit << g.kf[i]);
+    }
+  }
   return g;
+}
+// threads of a gather launch: one per row, or one per row part (balanced map)
+dim3 grid_gather(const fcc_plan_s* p, const GatherMap& g, int L, int nvol) {
+  if (!g.balance) return grid_points(p->n, nvol);
+  const long long threads = g.off[8] * ((1LL << (3 * L)) >> g.lg) * nvol;
+  return dim3(unsigned((threads + kBlock - 1) / kBlock));
 }
 
 template <typename R>
 void fwd_gather_dispatch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, int nvol, hipStream_t st) {
-  dim3 g = grid_points(p->n, nvol);
+  const GatherMap gm = gmap(p, 0, L);
+  const dim3 g = grid_gather(p, gm, L, nvol);
   const double2* h = phases(p, L);
   const NodeConst* nc = nodes_of(p, L);
   switch (ti) {
-    case DT::F32R: launch((k_fwd_gather<R, float>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 0, L)); break;
-    case DT::F64R: launch((k_fwd_gather<R, double>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 0, L)); break;
-    case DT::F32C: launch((k_fwd_gather<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 0, L)); break;
-    case DT::F64C: launch((k_fwd_gather<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 0, L)); break;
+    case DT::F32R: launch((k_fwd_gather<R, float>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
+    case DT::F64R: launch((k_fwd_gather<R, double>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
+    case DT::F32C: launch((k_fwd_gather<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
+    case DT::F64C: launch((k_fwd_gather<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
   }
 }
 template <typename R, typename TI>
@@ -1366,14 +1475,15 @@ void inv_dct2_dispatch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, int 
 }
 template <typename R>
 void inv_basis_dispatch(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int nvol, hipStream_t st) {
-  dim3 g = grid_points(p->n, nvol);
+  const GatherMap gm = gmap(p, 1, L);
+  const dim3 g = grid_gather(p, gm, L, nvol);
   const double2* h = phases(p, L);
   const NodeConst* nc = nodes_of(p, L);
   switch (to) {
-    case DT::F32R: launch((k_inv_basis<R, float>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 1, L)); break;
-    case DT::F64R: launch((k_inv_basis<R, double>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 1, L)); break;
-    case DT::F32C: launch((k_inv_basis<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 1, L)); break;
-    case DT::F64C: launch((k_inv_basis<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gmap(p, 1, L)); break;
+    case DT::F32R: launch((k_inv_basis<R, float>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
+    case DT::F64R: launch((k_inv_basis<R, double>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
+    case DT::F32C: launch((k_inv_basis<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
+    case DT::F64C: launch((k_inv_basis<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
   }
 }
 
@@ -1791,7 +1901,9 @@ bool valid_tuning(const fcc_tuning& t) {
         if (t.tile[d][L][a] < 0 || t.tile[d][L][a] > 9) return false;
     for (int L = 0; L < 10; ++L) {
       const unsigned m = t.map[d][L];
-      if (m & ~unsigned(FCC_MAP_XCD | FCC_MAP_F_INNER | FCC_MAP_NODES8 | FCC_MAP_NODES64 | FCC_MAP_SPLIT)) return false;
+      if (m & ~unsigned(FCC_MAP_XCD | FCC_MAP_F_INNER | FCC_MAP_NODES8 | FCC_MAP_NODES64 | FCC_MAP_SPLIT |
+                        FCC_MAP_BALANCE))
+        return false;
       if ((m & FCC_MAP_NODES8) && (m & FCC_MAP_NODES64)) return false;
     }
   }
@@ -1903,6 +2015,24 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
       DevLevel lv;
       s = device_level(p->device, n >> L, slice_cubes(L), tile_order(p, 0, L), tile_order(p, 1, L), &lv);
       p->lv.push_back(lv);
+    }
+    // balanced map: lanes per row from the mean row length of each f
+    for (int L = 0; s == FCC_OK && L < p->D; ++L) {
+      const LevelTables* T = level_tables(n >> L);
+      if (!T) {
+        s = FCC_ERR_OOM;
+        break;
+      }
+      for (int d = 0; d < 2; ++d) {
+        const std::vector<int>& rp = d == 0 ? T->b_rowptr : T->c_rowptr;
+        const long long cubes = (long long)(rp.size() - 1) / 8;
+        for (int f = 0; f < 8; ++f) {
+          long long tot = 0;
+          for (long long c = 0; c < cubes; ++c) tot += rp[c * 8 + f + 1] - rp[c * 8 + f];
+          const double mean = cubes ? double(tot) / double(cubes) : 0.0;
+          p->kf[d][L][f] = mean > 20.0 ? 2 : (mean > 10.0 ? 1 : 0);
+        }
+      }
     }
     // plain-order tables with one cube per slice for every level a fused
     // tail may cover (node sizes <= 8); levels >= 2 have them already
@@ -2147,9 +2277,16 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
       };
       static const int tiles0[][3] = {{0, 0, 0}, {2, 2, 2}, {1, 2, 3}, {0, 3, 3}, {3, 3, 3}, {2, 2, 4}};
       static const int tiles1[][3] = {{0, 0, 0}, {1, 1, 1}, {0, 1, 2}, {2, 2, 2}};
-      static const unsigned top_fwd[] = {0u, FCC_MAP_XCD, FCC_MAP_SPLIT, FCC_MAP_SPLIT | FCC_MAP_XCD,
-                                         FCC_MAP_SPLIT | FCC_MAP_F_INNER, FCC_MAP_SPLIT | FCC_MAP_F_INNER | FCC_MAP_XCD};
-      static const unsigned top_inv[] = {0u, FCC_MAP_XCD, FCC_MAP_F_INNER, FCC_MAP_F_INNER | FCC_MAP_XCD};
+      static const unsigned top_fwd[] = {0u,
+                                         FCC_MAP_XCD,
+                                         FCC_MAP_SPLIT,
+                                         FCC_MAP_SPLIT | FCC_MAP_XCD,
+                                         FCC_MAP_SPLIT | FCC_MAP_F_INNER,
+                                         FCC_MAP_SPLIT | FCC_MAP_F_INNER | FCC_MAP_XCD,
+                                         FCC_MAP_SPLIT | FCC_MAP_BALANCE,
+                                         FCC_MAP_SPLIT | FCC_MAP_BALANCE | FCC_MAP_XCD};
+      static const unsigned top_inv[] = {0u, FCC_MAP_XCD, FCC_MAP_F_INNER, FCC_MAP_F_INNER | FCC_MAP_XCD, FCC_MAP_BALANCE,
+                                         FCC_MAP_BALANCE | FCC_MAP_XCD};
       for (int L = 0; L < 2 && L < p->tail_Lt[d] && s == FCC_OK; ++L) {
         const int lgm = p->D - L - 1;
         const int ntiles = L == 0 ? 6 : 4;
@@ -2180,7 +2317,7 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
           }
           bool won = false;
           const unsigned* maps = d == 0 ? top_fwd : top_inv;
-          const int nmaps = d == 0 ? 6 : 4;
+          const int nmaps = d == 0 ? 8 : 6;
           for (int mi = 0; mi < nmaps && s == FCC_OK; ++mi) {
             cur = cand;
             p->tune.tile[d][L][0] = o.la;
@@ -2229,19 +2366,23 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
                                           FCC_MAP_NODES64 | FCC_MAP_XCD,
                                           FCC_MAP_SPLIT,
                                           FCC_MAP_SPLIT | FCC_MAP_NODES8 | FCC_MAP_XCD,
-                                          FCC_MAP_SPLIT | FCC_MAP_NODES64};
+                                          FCC_MAP_SPLIT | FCC_MAP_NODES64,
+                                          FCC_MAP_SPLIT | FCC_MAP_BALANCE | FCC_MAP_NODES64,
+                                          FCC_MAP_SPLIT | FCC_MAP_BALANCE | FCC_MAP_NODES64 | FCC_MAP_XCD};
       static const unsigned deep_inv[] = {0u,
                                           FCC_MAP_XCD,
                                           FCC_MAP_NODES8,
                                           FCC_MAP_NODES8 | FCC_MAP_XCD,
                                           FCC_MAP_NODES64,
                                           FCC_MAP_NODES64 | FCC_MAP_XCD,
-                                          FCC_MAP_NODES8 | FCC_MAP_F_INNER | FCC_MAP_XCD};
+                                          FCC_MAP_NODES8 | FCC_MAP_F_INNER | FCC_MAP_XCD,
+                                          FCC_MAP_BALANCE | FCC_MAP_NODES64 | FCC_MAP_XCD,
+                                          FCC_MAP_BALANCE | FCC_MAP_XCD};
       for (int L = 2; L < p->tail_Lt[d] && s == FCC_OK; ++L) {
         unsigned best_m = p->tune.map[d][L];
         double best_ms = 1e30;
         const unsigned* maps = d == 0 ? deep_fwd : deep_inv;
-        const int nmaps = d == 0 ? 9 : 7;
+        const int nmaps = d == 0 ? 11 : 9;
         for (int mi = 0; mi < nmaps; ++mi) {
           p->tune.map[d][L] = maps[mi];
           s = d == 0 ? time_slots(p, a, b, 1, reps, st, &ms) : time_slots(p, b, a, -1, reps, st, &ms);

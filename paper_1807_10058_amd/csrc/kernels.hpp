@@ -136,8 +136,17 @@ struct DevLevel {
 // consecutive (otherwise f is the slowest index).  lg: log2 of the node group
 // (levels >= 2): all rows of 2^lg consecutive nodes run before the next group;
 // 3L means one group of all 8^L nodes.
+// balance (levels with long rows): row f is summed by K_f = 2^kf adjacent
+// lanes, each over a contiguous part of the row, then combined with lane
+// shuffles.  Within a node group the threads run f by f in the order forder
+// (decreasing K_f, which keeps every row's lanes aligned), lane k fastest,
+// then cube, then node; off[i] is the first thread of the i-th f in the
+// group and off[8] the group's thread count.
 struct GatherMap {
   int xcd, f_inner, lg;
+  int balance;
+  unsigned char kf[8], forder[8];
+  long long off[9];
 };
 
 // Where the volumes of one launch live: one volume at `one` (arr == nullptr)

@@ -38,6 +38,7 @@ struct fcc_plan_s {
   fcc_tuning tune{};                    // the schedule, sizes clamped to this n
   int tail_Lt[2] = {0, 0};              // first level of the fused LDS tail: [0] forward, [1] inverse
   std::vector<fcc::DevLevel> tlv;       // per level from min(tail_Lt) on: plain-order tables, S = 1
+  unsigned char kf[2][16][8] = {};      // balanced map: log2 lanes per row, per side, level and f
 };
 
 namespace fcc {
