@@ -114,14 +114,80 @@ struct Vec8<_Float16> {
   }
 };
 
-constexpr int BM = 64, BN = 128, BK = 32, LDSK = BK + 8;
+constexpr int BM = 64, BN = 128, BK = 64, LDSK = BK + 8;
+
+// One K tile of the split GEMM's operands in registers: 16 floats of an A row
+// (from k0 + akc) and 32 entries of a W row, hi and lo (from k0).  Named
+// members, no arrays, so that nothing is addressed through scratch.
+struct GemmTile {
+  float4 a0, a1, a2, a3;
+  uint4 h0, h1, h2, h3, l0, l1, l2, l3;
+};
+template <bool kVec>
+__device__ __forceinline__ float4 gemm_a4(const float* arp, int K, int kk) {
+  if constexpr (kVec) {
+    // K % 4 == 0: a float4 is wholly in range or wholly out
+    return (arp && kk < K) ? *reinterpret_cast<const float4*>(arp + kk) : make_float4(0.f, 0.f, 0.f, 0.f);
+  } else {
+    float4 v;
+    v.x = (arp && kk < K) ? arp[kk] : 0.f;
+    v.y = (arp && kk + 1 < K) ? arp[kk + 1] : 0.f;
+    v.z = (arp && kk + 2 < K) ? arp[kk + 2] : 0.f;
+    v.w = (arp && kk + 3 < K) ? arp[kk + 3] : 0.f;
+    return v;
+  }
+}
+template <bool kVec, typename T16>
+__device__ __forceinline__ void gemm_load(const float* arp, int K, int k0, int akc, const T16* bhp, const T16* blp,
+                                          GemmTile& t) {
+  const int kk = k0 + akc;
+  t.a0 = gemm_a4<kVec>(arp, K, kk);
+  t.a1 = gemm_a4<kVec>(arp, K, kk + 4);
+  t.a2 = gemm_a4<kVec>(arp, K, kk + 8);
+  t.a3 = gemm_a4<kVec>(arp, K, kk + 12);
+  const uint4* hp = reinterpret_cast<const uint4*>(bhp + k0);
+  const uint4* lp = reinterpret_cast<const uint4*>(blp + k0);
+  t.h0 = hp[0], t.h1 = hp[1], t.h2 = hp[2], t.h3 = hp[3];
+  t.l0 = lp[0], t.l1 = lp[1], t.l2 = lp[2], t.l3 = lp[3];
+}
+// 8 floats, scaled, as hi and lo 16-bit vectors
+template <typename T16>
+__device__ __forceinline__ void gemm_split8(float4 x, float4 y, float s, typename Vec8<T16>::type& hi,
+                                            typename Vec8<T16>::type& lo) {
+  const float v[8] = {x.x * s, x.y * s, x.z * s, x.w * s, y.x * s, y.y * s, y.z * s, y.w * s};
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const T16 t = T16(v[i]);
+    hi[i] = t;
+    lo[i] = T16(v[i] - float(t));
+  }
+}
+template <typename T16>
+__device__ __forceinline__ void gemm_store(const GemmTile& t, float as, T16* ahi, T16* alo, T16* bhi, T16* blo) {
+  typedef typename Vec8<T16>::type V8;
+  V8 hi, lo;
+  gemm_split8<T16>(t.a0, t.a1, as, hi, lo);
+  *reinterpret_cast<V8*>(ahi) = hi;
+  *reinterpret_cast<V8*>(alo) = lo;
+  gemm_split8<T16>(t.a2, t.a3, as, hi, lo);
+  *reinterpret_cast<V8*>(ahi + 8) = hi;
+  *reinterpret_cast<V8*>(alo + 8) = lo;
+  uint4* bh = reinterpret_cast<uint4*>(bhi);
+  uint4* bl = reinterpret_cast<uint4*>(blo);
+  bh[0] = t.h0, bh[1] = t.h1, bh[2] = t.h2, bh[3] = t.h3;
+  bl[0] = t.l0, bl[1] = t.l1, bl[2] = t.l2, bl[3] = t.l3;
+}
 
 // out[r, c] = (sum_k in[r, k] W[c, k]) * w_unscale  for r < M, c < Nc.
 // Block 256 threads = 4 waves as 2 (rows) x 2 (cols); each wave owns a 32 x 64
-// tile = 2 x 4 MFMA 16x16 tiles.  Operand layout of v_mfma_f32_16x16x32:
-// A lane l holds A[l % 16][8 (l / 16) + i], B lane l holds B[8 (l / 16) + i][l % 16],
-// D lane l holds D[4 (l / 16) + v][l % 16].
-template <typename T16>
+// tile = 2 x 4 MFMA 16x16 tiles, two 32-deep MFMA steps per K tile of 64.
+// Operand layout of v_mfma_f32_16x16x32: A lane l holds A[l % 16][8 (l / 16) + i],
+// B lane l holds B[8 (l / 16) + i][l % 16], D lane l holds D[4 (l / 16) + v][l % 16].
+// The next K tile of A (16 floats per thread) and W (hi and lo, 64 bytes each
+// per thread) is loaded into registers while the current one is multiplied
+// from LDS; A is split into hi + lo when it is stored to LDS.  kVec: rows are
+// read as float4 (K a multiple of 4).
+template <typename T16, bool kVec>
 __global__ __launch_bounds__(256) void k_split_gemm(const float* const* a_rows, const float* a_base, long long lda,
                                                     float* const* c_rows, float* c_base, long long ldc,
                                                     const T16* __restrict__ w_hi, const T16* __restrict__ w_lo,
@@ -141,49 +207,45 @@ __global__ __launch_bounds__(256) void k_split_gemm(const float* const* a_rows, 
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  const int arow = tid >> 2, akc = (tid & 3) * 8;
+  // A: thread -> row arow, 16 consecutive k from akc; W: row brow, 32 k from bkc
+  const int arow = tid >> 2, akc = (tid & 3) * 16;
   const float* arp = nullptr;
   float as = 1.0f;
   if (m0 + arow < M) {
     arp = a_rows ? a_rows[m0 + arow] : a_base + (long long)(m0 + arow) * lda;
     if (rowscale) as = rowscale[m0 + arow];
   }
-  const int brow = tid >> 1, bkc = (tid & 1) * 16;
+  const int brow = tid >> 1, bkc = (tid & 1) * 32;
   const T16* bhp = w_hi + (long long)(n0 + brow) * Kp + bkc;
   const T16* blp = w_lo + (long long)(n0 + brow) * Kp + bkc;
 
+  GemmTile tile;
+  gemm_load<kVec>(arp, K, 0, akc, bhp, blp, tile);
   for (int k0 = 0; k0 < K; k0 += BK) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int kk = k0 + akc + i;
-      const float v = (arp && kk < K) ? arp[kk] * as : 0.0f;
-      const T16 h = T16(v);
-      sa_hi[arow][akc + i] = h;
-      sa_lo[arow][akc + i] = T16(v - float(h));
-    }
-    *reinterpret_cast<uint4*>(&sb_hi[brow][bkc]) = *reinterpret_cast<const uint4*>(bhp + k0);
-    *reinterpret_cast<uint4*>(&sb_hi[brow][bkc + 8]) = *reinterpret_cast<const uint4*>(bhp + k0 + 8);
-    *reinterpret_cast<uint4*>(&sb_lo[brow][bkc]) = *reinterpret_cast<const uint4*>(blp + k0);
-    *reinterpret_cast<uint4*>(&sb_lo[brow][bkc + 8]) = *reinterpret_cast<const uint4*>(blp + k0 + 8);
+    gemm_store<T16>(tile, as, &sa_hi[arow][akc], &sa_lo[arow][akc], &sb_hi[brow][bkc], &sb_lo[brow][bkc]);
     __syncthreads();
-    const int kq = (lane >> 4) * 8;
-    V8 ah[2], al[2];
+    if (k0 + BK < K) gemm_load<kVec>(arp, K, k0 + BK, akc, bhp, blp, tile);  // in flight during the MFMAs below
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-      const int r = wm * 32 + mt * 16 + (lane & 15);
-      ah[mt] = *reinterpret_cast<const V8*>(&sa_hi[r][kq]);
-      al[mt] = *reinterpret_cast<const V8*>(&sa_lo[r][kq]);
-    }
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      const int c = wn * 64 + nt * 16 + (lane & 15);
-      const V8 bh = *reinterpret_cast<const V8*>(&sb_hi[c][kq]);
-      const V8 bl = *reinterpret_cast<const V8*>(&sb_lo[c][kq]);
+    for (int ks = 0; ks < BK; ks += 32) {
+      const int kq = ks + (lane >> 4) * 8;
+      V8 ah[2], al[2];
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt) {
-        acc[mt][nt] = Vec8<T16>::mfma(ah[mt], bh, acc[mt][nt]);
-        acc[mt][nt] = Vec8<T16>::mfma(ah[mt], bl, acc[mt][nt]);
-        acc[mt][nt] = Vec8<T16>::mfma(al[mt], bh, acc[mt][nt]);
+        const int r = wm * 32 + mt * 16 + (lane & 15);
+        ah[mt] = *reinterpret_cast<const V8*>(&sa_hi[r][kq]);
+        al[mt] = *reinterpret_cast<const V8*>(&sa_lo[r][kq]);
+      }
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        const int c = wn * 64 + nt * 16 + (lane & 15);
+        const V8 wh = *reinterpret_cast<const V8*>(&sb_hi[c][kq]);
+        const V8 wl = *reinterpret_cast<const V8*>(&sb_lo[c][kq]);
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+          acc[mt][nt] = Vec8<T16>::mfma(ah[mt], wh, acc[mt][nt]);
+          acc[mt][nt] = Vec8<T16>::mfma(ah[mt], wl, acc[mt][nt]);
+          acc[mt][nt] = Vec8<T16>::mfma(al[mt], wh, acc[mt][nt]);
+        }
       }
     }
     __syncthreads();
@@ -392,14 +454,23 @@ fcc_status dense_run(const fcc_plan_s* p, const DenseOp& op, int M, const void* 
     rowscale = nullptr;
   }
   dim3 grid(op.Ncp / BN, (M + BM - 1) / BM);
-  if (fp16)
-    hipLaunchKernelGGL(k_split_gemm<_Float16>, grid, dim3(256), 0, st, ar, ab, (long long)op.K, cr, cb,
-                       (long long)op.Nc, static_cast<const _Float16*>(op.w_hi), static_cast<const _Float16*>(op.w_lo),
-                       M, op.K, op.Nc, op.Kp, rowscale, op.w_unscale);
-  else
-    hipLaunchKernelGGL(k_split_gemm<__bf16>, grid, dim3(256), 0, st, ar, ab, (long long)op.K, cr, cb,
-                       (long long)op.Nc, static_cast<const __bf16*>(op.w_hi), static_cast<const __bf16*>(op.w_lo), M,
-                       op.K, op.Nc, op.Kp, rowscale, op.w_unscale);
+  const bool vec = (op.K & 3) == 0;
+#define FCC_GEMM(T, V)                                                                                           \
+  hipLaunchKernelGGL((k_split_gemm<T, V>), grid, dim3(256), 0, st, ar, ab, (long long)op.K, cr, cb,              \
+                     (long long)op.Nc, static_cast<const T*>(op.w_hi), static_cast<const T*>(op.w_lo), M, op.K, \
+                     op.Nc, op.Kp, rowscale, op.w_unscale)
+  if (fp16) {
+    if (vec)
+      FCC_GEMM(_Float16, true);
+    else
+      FCC_GEMM(_Float16, false);
+  } else {
+    if (vec)
+      FCC_GEMM(__bf16, true);
+    else
+      FCC_GEMM(__bf16, false);
+  }
+#undef FCC_GEMM
   return hipGetLastError() == hipSuccess ? FCC_OK : FCC_ERR_HIP;
 }
 
