@@ -332,6 +332,40 @@ __device__ __forceinline__ cx<R> row_finish(const TI* __restrict__ in, int n, in
   return acc;
 }
 
+// Gather of a row that is the same on every lane of the wavefront (levels >= 2
+// with one cube per slice and at least 64 consecutive nodes per group: lanes
+// differ only in the node).  The row index is made provably uniform, so the
+// table entries and the polynomial coefficients are read through the scalar
+// cache and no LDS copy of the polynomials is needed.  Same entry order as
+// row_finish.
+template <typename R, typename TI>
+__device__ __forceinline__ cx<R> row_uniform(const TI* __restrict__ in, int n, int L, const int J[3],
+                                             const DevSide& sd, int r, const double* __restrict__ poly, int nconst,
+                                             const cx<R> mono[kNumMono]) {
+  r = __builtin_amdgcn_readfirstlane(r);
+  const int e0 = __builtin_amdgcn_readfirstlane(sd.start[r]);
+  const int len = __builtin_amdgcn_readfirstlane(sd.len[r]);
+  cx<R> acc{R(0), R(0)};
+  for (int c = 0; c < len; c += kChunk) {
+    uint32_t s8[kChunk];
+    int p8[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const int e = min(c + u, len - 1);
+      s8[u] = __builtin_amdgcn_readfirstlane(sd.src[e0 + e]);
+      p8[u] = __builtin_amdgcn_readfirstlane(int(sd.pid[e0 + e]));
+    }
+    cx<R> v8[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u)
+      v8[u] = IO<TI, R>::ld(in, gpos(n, L, J, int(s8[u] >> 20), int((s8[u] >> 10) & 1023u), int(s8[u] & 1023u)));
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u)
+      if (c + u < len) acc = acc + poly_value(poly, nconst, p8[u], mono) * v8[u];
+  }
+  return acc;
+}
+
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
@@ -446,9 +480,24 @@ __device__ __forceinline__ void load_mono(const NodeConst*, const double2* __res
 
 // Forward level L, first pass: y(def, abc) = row (def,abc) of B_nl(c) applied to
 // the node, one thread per row, stored at node-local position def + 2 abc.
-template <typename R, typename TI>
+template <typename R, typename TI, bool kUni>
 __global__ __launch_bounds__(256) void k_fwd_gather(VolSet vs, int nvol, int n, int L, DevLevel lv,
                                                     const double2* __restrict__ hph, const NodeConst* nodes, GatherMap gm) {
+  if constexpr (kUni) {
+    // wave-uniform rows (see row_uniform): no LDS, no barrier
+    const long long N = (long long)n * n * n;
+    const long long tg = gather_block(gm.xcd) * blockDim.x + threadIdx.x;
+    if (tg >= N * nvol) return;
+    const long long vol = tg / N, t = tg - vol * N;
+    const RowIdx ri = row_of(t, n, L, lv.b.order, 1, gm);
+    cx<R> mono[kNumMono];
+    load_mono(nodes, hph, L, ri.J, mono);
+    const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, vol));
+    cx<R>* __restrict__ out = static_cast<cx<R>*>(vol_ptr(vs.out, vol));
+    const cx<R> y = row_uniform<R, TI>(in, n, L, ri.J, lv.b, ri.cube * 8 + ri.f, lv.poly, lv.nconst, mono);
+    out[gpos(n, L, ri.J, ((ri.f >> 2) & 1) + 2 * ri.a[0], ((ri.f >> 1) & 1) + 2 * ri.a[1], (ri.f & 1) + 2 * ri.a[2])] = y;
+    return;
+  }
   __shared__ double sp[kMaxPoly * kNumMono];
   const long long N = gm.balance ? gm.off[8] * ((1LL << (3 * L)) >> gm.lg) : (long long)n * n * n;  // threads per volume
   const long long tg = gather_block(gm.xcd) * blockDim.x + threadIdx.x;
@@ -692,9 +741,24 @@ __global__ __launch_bounds__(256) void k_inv_dct2(VolSet vs, int nvol, int n, in
 
 // Inverse level L, second pass: x(kappa) = sum C_nl(phi)[kappa, (def,abc)] y(def + 2 abc),
 // one thread per output kappa = i + 2 abc.
-template <typename R, typename TO>
+template <typename R, typename TO, bool kUni>
 __global__ __launch_bounds__(256) void k_inv_basis(VolSet vs, int nvol, int n, int L, DevLevel lv,
                                                    const double2* __restrict__ hph, const NodeConst* nodes, GatherMap gm) {
+  if constexpr (kUni) {
+    // wave-uniform rows (see row_uniform): no LDS, no barrier
+    const long long N = (long long)n * n * n;
+    const long long tg = gather_block(gm.xcd) * blockDim.x + threadIdx.x;
+    if (tg >= N * nvol) return;
+    const long long vol = tg / N, t = tg - vol * N;
+    const RowIdx ri = row_of(t, n, L, lv.c.order, 1, gm);
+    cx<R> mono[kNumMono];
+    load_mono(nodes, hph, L, ri.J, mono);
+    const cx<R>* __restrict__ in = static_cast<const cx<R>*>(vol_ptr(vs.in, vol));
+    TO* __restrict__ out = static_cast<TO*>(vol_ptr(vs.out, vol));
+    const cx<R> x = row_uniform<R, cx<R>>(in, n, L, ri.J, lv.c, ri.cube * 8 + ri.f, lv.poly, lv.nconst, mono);
+    IO<TO, R>::st(out, gpos(n, L, ri.J, ((ri.f >> 2) & 1) + 2 * ri.a[0], ((ri.f >> 1) & 1) + 2 * ri.a[1], (ri.f & 1) + 2 * ri.a[2]), x);
+    return;
+  }
   __shared__ double sp[kMaxPoly * kNumMono];
   const long long N = gm.balance ? gm.off[8] * ((1LL << (3 * L)) >> gm.lg) : (long long)n * n * n;  // threads per volume
   const long long tg = gather_block(gm.xcd) * blockDim.x + threadIdx.x;
@@ -1402,18 +1466,30 @@ dim3 grid_gather(const fcc_plan_s* p, const GatherMap& g, int L, int nvol) {
   return dim3(unsigned((threads + kBlock - 1) / kBlock));
 }
 
+// rows are wave-uniform: one cube per slice, 64 lanes in one node group, no parts
+bool uniform_rows(const fcc_plan_s* p, const GatherMap& gm, int L) {
+  return p->lv[L].S == 1 && gm.lg >= 6 && !gm.balance;
+}
+template <typename R, bool U>
+void fwd_gather_launch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, int nvol, hipStream_t st,
+                       const GatherMap& gm, dim3 g) {
+  const double2* h = phases(p, L);
+  const NodeConst* nc = nodes_of(p, L);
+  switch (ti) {
+    case DT::F32R: launch((k_fwd_gather<R, float, U>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
+    case DT::F64R: launch((k_fwd_gather<R, double, U>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
+    case DT::F32C: launch((k_fwd_gather<R, float2, U>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
+    case DT::F64C: launch((k_fwd_gather<R, double2, U>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
+  }
+}
 template <typename R>
 void fwd_gather_dispatch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, int nvol, hipStream_t st) {
   const GatherMap gm = gmap(p, 0, L);
   const dim3 g = grid_gather(p, gm, L, nvol);
-  const double2* h = phases(p, L);
-  const NodeConst* nc = nodes_of(p, L);
-  switch (ti) {
-    case DT::F32R: launch((k_fwd_gather<R, float>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
-    case DT::F64R: launch((k_fwd_gather<R, double>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
-    case DT::F32C: launch((k_fwd_gather<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
-    case DT::F64C: launch((k_fwd_gather<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
-  }
+  if (uniform_rows(p, gm, L))
+    fwd_gather_launch<R, true>(p, L, ti, vs, nvol, st, gm, g);
+  else
+    fwd_gather_launch<R, false>(p, L, ti, vs, nvol, st, gm, g);
 }
 template <typename R, typename TI>
 void fwd_level_out(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int nvol, hipStream_t st) {
@@ -1473,18 +1549,26 @@ void inv_dct2_dispatch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, int 
   else
     launch((k_inv_dct2<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, h, nc);
 }
+template <typename R, bool U>
+void inv_basis_launch(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int nvol, hipStream_t st,
+                      const GatherMap& gm, dim3 g) {
+  const double2* h = phases(p, L);
+  const NodeConst* nc = nodes_of(p, L);
+  switch (to) {
+    case DT::F32R: launch((k_inv_basis<R, float, U>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
+    case DT::F64R: launch((k_inv_basis<R, double, U>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
+    case DT::F32C: launch((k_inv_basis<R, float2, U>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
+    case DT::F64C: launch((k_inv_basis<R, double2, U>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
+  }
+}
 template <typename R>
 void inv_basis_dispatch(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int nvol, hipStream_t st) {
   const GatherMap gm = gmap(p, 1, L);
   const dim3 g = grid_gather(p, gm, L, nvol);
-  const double2* h = phases(p, L);
-  const NodeConst* nc = nodes_of(p, L);
-  switch (to) {
-    case DT::F32R: launch((k_inv_basis<R, float>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
-    case DT::F64R: launch((k_inv_basis<R, double>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
-    case DT::F32C: launch((k_inv_basis<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
-    case DT::F64C: launch((k_inv_basis<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, p->lv[L], h, nc, gm); break;
-  }
+  if (uniform_rows(p, gm, L))
+    inv_basis_launch<R, true>(p, L, to, vs, nvol, st, gm, g);
+  else
+    inv_basis_launch<R, false>(p, L, to, vs, nvol, st, gm, g);
 }
 
 TailLevels tail_levels(const fcc_plan_s* p, int Lt) {
