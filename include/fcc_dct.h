@@ -126,7 +126,7 @@ const char* fcc_status_string(fcc_status s);
  * FCC_MAP_BALANCE evaluates the same expressions, at the same stage
  * precision, in another kernel or order and may differ in the last bits.  Index [0] is the forward
  * transform, [1] the inverse.
- *   tail_levels[d] : the last 1..3 levels (node sizes <= 2^tail_levels) run
+ *   tail_levels[d] : the last 1..4 levels (node sizes <= 2^tail_levels) run
  *                    fused in one launch with the data resident in LDS (the
  *                    last level alone, where B_2 = C_2 = I, is a per-cube
  *                    DCT_2 pass).
@@ -169,7 +169,7 @@ typedef struct {
 
 /* fcc_dct_plan with an explicit schedule.  tuning == NULL takes the schedule
  * fcc_dct_plan would take (see fcc_dct_autotune).  Errors: those of
- * fcc_dct_plan, and FCC_ERR_INVALID_ARG for tail_levels outside 1..3, a tile
+ * fcc_dct_plan, and FCC_ERR_INVALID_ARG for tail_levels outside 1..4, a tile
  * size outside 0..9, unknown map bits or both node-group bits. */
 fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_precision prec,
                               unsigned flags, const fcc_tuning* tuning, void* hip_stream);

@@ -790,16 +790,17 @@ __global__ __launch_bounds__(256) void k_inv_basis(VolSet vs, int nvol, int n, i
 }
 
 // ---------------------------------------------------------------------------
-// Fused tail: the last levels (node size nl0 <= kTailNl) of a group of G <= kTailG
+// Fused tail: the last levels (node size nl0 <= 16) of a group of G sibling nodes
 // sibling nodes (consecutive J_z) run in LDS, one thread per 2x2x2 cube of
 // every sub-level.  Sub-level l of the tail is global level Lt + l; its
 // sub-nodes j' in [0, 2^l)^3 own the node-local positions j' + 2^l b, exactly
 // as the global layout nests.
 // ---------------------------------------------------------------------------
-constexpr int kTailNl = 8;
-constexpr int kTailG = 2;
-constexpr int kTailPts = kTailNl * kTailNl * kTailNl;
-constexpr int kTailCubes = kTailPts / 8;  // cubes of one node at every sub-level
+// LDS capacity in points of the two tail forms: node sizes up to 8 (two
+// nodes of 8^3) and 16 (one node of 16^3, 64 KB in FP64).  A block has one
+// thread per cube of its nodes: capacity / 8.
+constexpr int kTailCapSmall = 1024;
+constexpr int kTailCapBig = 4096;
 
 struct TailLevels {
   DevLevel lv[4];             // CSR tables (S = 1) of node sizes nl0, nl0/2, ...
@@ -811,16 +812,47 @@ __device__ __forceinline__ int lpos(int nl0, int l, const int jp[3], int x, int 
   return (((jp[0] + (x << l)) * nl0) + (jp[1] + (y << l))) * nl0 + (jp[2] + (z << l));
 }
 
-// One CSR row gathered from an LDS node buffer.
+// One table row gathered from an LDS node buffer, in entry order.  The table
+// lives in global memory: the row's entries are read in chunks of 8 with the
+// next chunk in flight while the current one is summed (e0, len: the row's
+// start and length, loaded by the caller for all 8 rows of a cube at once).
 template <typename R>
-__device__ __forceinline__ cx<R> lds_row(const cx<R>* buf, int nl0, int l, const int jp[3], const DevSide& sd, int r,
-                                         const double* sp, int nconst, const cx<R> mono[kNumMono]) {
-  const int e0 = sd.start[r], len = sd.len[r];
+__device__ __forceinline__ cx<R> lds_row(const cx<R>* buf, int nl0, int l, const int jp[3], const DevSide& sd, int e0,
+                                         int len, const double* sp, int nconst, const cx<R> mono[kNumMono]) {
   cx<R> acc{R(0), R(0)};
-  for (int e = 0; e < len; ++e) {
-    const uint32_t s = sd.src[e0 + e];
-    acc = acc + poly_value(sp, nconst, sd.pid[e0 + e], mono) *
-                    buf[lpos(nl0, l, jp, int(s >> 20), int((s >> 10) & 1023u), int(s & 1023u))];
+  if (len <= 0) return acc;
+  uint32_t s8[kChunk];
+  uint16_t p8[kChunk];
+#pragma unroll
+  for (int u = 0; u < kChunk; ++u) {
+    const int e = min(u, len - 1);
+    s8[u] = sd.src[e0 + e];
+    p8[u] = sd.pid[e0 + e];
+  }
+  for (int c = 0; c < len; c += kChunk) {
+    uint32_t sn[kChunk];
+    uint16_t pn[kChunk];
+    const bool more = c + kChunk < len;
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) {
+        const int e = min(c + kChunk + u, len - 1);
+        sn[u] = sd.src[e0 + e];
+        pn[u] = sd.pid[e0 + e];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u)
+      if (c + u < len)
+        acc = acc + poly_value(sp, nconst, p8[u], mono) *
+                        buf[lpos(nl0, l, jp, int(s8[u] >> 20), int((s8[u] >> 10) & 1023u), int(s8[u] & 1023u))];
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) {
+        s8[u] = sn[u];
+        p8[u] = pn[u];
+      }
+    }
   }
   return acc;
 }
@@ -909,9 +941,9 @@ __device__ __forceinline__ void tail_store(const TailGeom& tg, const int J[3], c
 // Every thread owns at most one cube per sub-level (the block has at least
 // G * nl0^3 / 8 threads), so each sub-level reads its cube into registers,
 // waits, and writes back into the same LDS buffer.
-template <typename R, typename TI, typename TO>
-__global__ __launch_bounds__(kTailG * kTailCubes) void k_fwd_tail(VolSet vs, TailGeom tg, TailLevels tl) {
-  __shared__ cx<R> buf[kTailG * kTailPts];
+template <typename R, typename TI, typename TO, int kCap>
+__global__ __launch_bounds__(kCap / 8) void k_fwd_tail(VolSet vs, TailGeom tg, TailLevels tl) {
+  __shared__ cx<R> buf[kCap];
   __shared__ double sp[kMaxPoly * kNumMono];
   long long vol;
   int J[3];
@@ -934,9 +966,12 @@ __global__ __launch_bounds__(kTailG * kTailCubes) void k_fwd_tail(VolSet vs, Tai
       const cx<R>* src = buf + c.g * npts;
       cx<R> mono[kNumMono];
       tail_mono<R>(tl, l, Lg, c.G3, mono);
+      int rs[8], rl[8];
+#pragma unroll
+      for (int f = 0; f < 8; ++f) rs[f] = lv.b.start[cube * 8 + f], rl[f] = lv.b.len[cube * 8 + f];
       cx<R> y[8];
 #pragma unroll
-      for (int f = 0; f < 8; ++f) y[f] = lds_row(src, tg.nl0, l, c.jp, lv.b, cube * 8 + f, sp, lv.nconst, mono);
+      for (int f = 0; f < 8; ++f) y[f] = lds_row(src, tg.nl0, l, c.jp, lv.b, rs[f], rl[f], sp, lv.nconst, mono);
       if (tl.nodes[l]) {
         const NodeConst& nc = tl.nodes[l][node_index(c.G3, Lg)];
         const int c4[4] = {1, 3, 4, 6}, c3[3] = {2, 5, 7};
@@ -974,9 +1009,9 @@ __global__ __launch_bounds__(kTailG * kTailCubes) void k_fwd_tail(VolSet vs, Tai
   tail_store<R>(tg, J, buf, static_cast<TO*>(vol_ptr(vs.out, vol)));
 }
 
-template <typename R, typename TI, typename TO>
-__global__ __launch_bounds__(kTailG * kTailCubes) void k_inv_tail(VolSet vs, TailGeom tg, TailLevels tl) {
-  __shared__ cx<R> buf[kTailG * kTailPts];
+template <typename R, typename TI, typename TO, int kCap>
+__global__ __launch_bounds__(kCap / 8) void k_inv_tail(VolSet vs, TailGeom tg, TailLevels tl) {
+  __shared__ cx<R> buf[kCap];
   __shared__ double sp[kMaxPoly * kNumMono];
   long long vol;
   int J[3];
@@ -1028,8 +1063,11 @@ __global__ __launch_bounds__(kTailG * kTailCubes) void k_inv_tail(VolSet vs, Tai
       const cx<R>* src = buf + c.g * npts;
       cx<R> mono[kNumMono];
       tail_mono<R>(tl, l, Lg, c.G3, mono);
+      int rs[8], rl[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) x[i] = lds_row(src, tg.nl0, l, c.jp, lv.c, cube * 8 + i, sp, lv.nconst, mono);
+      for (int i = 0; i < 8; ++i) rs[i] = lv.c.start[cube * 8 + i], rl[i] = lv.c.len[cube * 8 + i];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) x[i] = lds_row(src, tg.nl0, l, c.jp, lv.c, rs[i], rl[i], sp, lv.nconst, mono);
     }
     __syncthreads();
     if (t < ncubes) {
@@ -1580,6 +1618,7 @@ TailLevels tail_levels(const fcc_plan_s* p, int Lt) {
   }
   return tl;
 }
+int tail_cap(int nl0) { return nl0 <= 8 ? kTailCapSmall : kTailCapBig; }
 // As many sibling nodes per block as the LDS buffer holds (within one row of
 // J_z), fewer while the launch would have under 2048 blocks.
 TailGeom tail_geom(const fcc_plan_s* p, int Lt, int nvol) {
@@ -1588,7 +1627,7 @@ TailGeom tail_geom(const fcc_plan_s* p, int Lt, int nvol) {
   g.Lt = Lt;
   g.nl0 = p->n >> Lt;
   g.k = p->D - Lt;
-  g.G = std::min(kTailG * kTailPts / (g.nl0 * g.nl0 * g.nl0), 1 << Lt);
+  g.G = std::min(tail_cap(g.nl0) / (g.nl0 * g.nl0 * g.nl0), 1 << Lt);
   while (g.G > 1 && (1LL << (3 * g.Lt)) / g.G * nvol < 2048) g.G >>= 1;
   return g;
 }
@@ -1598,10 +1637,19 @@ template <typename R, typename TI>
 void fwd_tail_out(const fcc_plan_s* p, DT to, const VolSet& vs, int nvol, hipStream_t st) {
   const TailGeom g = tail_geom(p, p->tail_Lt[0], nvol);
   const TailLevels tl = tail_levels(p, p->tail_Lt[0]);
-  if (to == DT::F32C)
-    launch((k_fwd_tail<R, TI, float2>), tail_grid(g, nvol), tail_block_dim(g), 0, st, vs, g, tl);
-  else
-    launch((k_fwd_tail<R, TI, double2>), tail_grid(g, nvol), tail_block_dim(g), 0, st, vs, g, tl);
+  const dim3 gr = tail_grid(g, nvol), bd = tail_block_dim(g);
+  const bool big = tail_cap(g.nl0) == kTailCapBig;
+  if (to == DT::F32C) {
+    if (big)
+      launch((k_fwd_tail<R, TI, float2, kTailCapBig>), gr, bd, 0, st, vs, g, tl);
+    else
+      launch((k_fwd_tail<R, TI, float2, kTailCapSmall>), gr, bd, 0, st, vs, g, tl);
+  } else {
+    if (big)
+      launch((k_fwd_tail<R, TI, double2, kTailCapBig>), gr, bd, 0, st, vs, g, tl);
+    else
+      launch((k_fwd_tail<R, TI, double2, kTailCapSmall>), gr, bd, 0, st, vs, g, tl);
+  }
 }
 template <typename R>
 void fwd_tail_dispatch(const fcc_plan_s* p, DT ti, DT to, const VolSet& vs, int nvol, hipStream_t st) {
@@ -1617,11 +1665,20 @@ void inv_tail_out(const fcc_plan_s* p, DT to, const VolSet& vs, int nvol, hipStr
   const TailGeom g = tail_geom(p, p->tail_Lt[1], nvol);
   const TailLevels tl = tail_levels(p, p->tail_Lt[1]);
   const dim3 gr = tail_grid(g, nvol), bd = tail_block_dim(g);
-  switch (to) {
-    case DT::F32R: launch((k_inv_tail<R, TI, float>), gr, bd, 0, st, vs, g, tl); break;
-    case DT::F64R: launch((k_inv_tail<R, TI, double>), gr, bd, 0, st, vs, g, tl); break;
-    case DT::F32C: launch((k_inv_tail<R, TI, float2>), gr, bd, 0, st, vs, g, tl); break;
-    case DT::F64C: launch((k_inv_tail<R, TI, double2>), gr, bd, 0, st, vs, g, tl); break;
+  if (tail_cap(g.nl0) == kTailCapBig) {
+    switch (to) {
+      case DT::F32R: launch((k_inv_tail<R, TI, float, kTailCapBig>), gr, bd, 0, st, vs, g, tl); break;
+      case DT::F64R: launch((k_inv_tail<R, TI, double, kTailCapBig>), gr, bd, 0, st, vs, g, tl); break;
+      case DT::F32C: launch((k_inv_tail<R, TI, float2, kTailCapBig>), gr, bd, 0, st, vs, g, tl); break;
+      case DT::F64C: launch((k_inv_tail<R, TI, double2, kTailCapBig>), gr, bd, 0, st, vs, g, tl); break;
+    }
+  } else {
+    switch (to) {
+      case DT::F32R: launch((k_inv_tail<R, TI, float, kTailCapSmall>), gr, bd, 0, st, vs, g, tl); break;
+      case DT::F64R: launch((k_inv_tail<R, TI, double, kTailCapSmall>), gr, bd, 0, st, vs, g, tl); break;
+      case DT::F32C: launch((k_inv_tail<R, TI, float2, kTailCapSmall>), gr, bd, 0, st, vs, g, tl); break;
+      case DT::F64C: launch((k_inv_tail<R, TI, double2, kTailCapSmall>), gr, bd, 0, st, vs, g, tl); break;
+    }
   }
 }
 template <typename R>
@@ -1697,7 +1754,7 @@ fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
       fwd_dct2_dispatch<float>(p, p->D - 1, cplx_type(p), VolSet{src, out}, nvol, st);
     return launch_status("forward level launch");
   }
-  // the last levels (node size <= kTailNl) in one LDS-resident launch
+  // the last levels (node size <= 16) in one LDS-resident launch
   if (p->stages64)
     fwd_tail_dispatch<double>(p, src_t, cplx_type(p), VolSet{src, out}, nvol, st);
   else
@@ -1979,7 +2036,7 @@ fcc_tuning default_tuning(int n) {
 }
 bool valid_tuning(const fcc_tuning& t) {
   for (int d = 0; d < 2; ++d) {
-    if (t.tail_levels[d] < 1 || t.tail_levels[d] > 3) return false;
+    if (t.tail_levels[d] < 1 || t.tail_levels[d] > 4) return false;
     for (int L = 0; L < 2; ++L)
       for (int a = 0; a < 3; ++a)
         if (t.tile[d][L][a] < 0 || t.tile[d][L][a] > 9) return false;
@@ -2119,9 +2176,9 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
       }
     }
     // plain-order tables with one cube per slice for every level a fused
-    // tail may cover (node sizes <= 8); levels >= 2 have them already
+    // tail may cover (node sizes <= 16); levels >= 2 have them already
     p->tlv.resize(p->D);
-    for (int L = std::max(0, p->D - 3); s == FCC_OK && L < p->D; ++L) {
+    for (int L = std::max(0, p->D - 4); s == FCC_OK && L < p->D; ++L) {
       if (L >= 2)
         p->tlv[L] = p->lv[L];
       else
@@ -2341,7 +2398,7 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
       // 1. fused tail depth, by whole-direction time
       int best_k = p->tune.tail_levels[d];
       double best_t = 1e30;
-      for (int k = 1; k <= std::min(3, p->D) && s == FCC_OK; ++k) {
+      for (int k = 1; k <= std::min(4, p->D) && s == FCC_OK; ++k) {
         p->tune.tail_levels[d] = k;
         p->tail_Lt[d] = std::max(0, p->D - k);
         double t = 0.0;

@@ -75,7 +75,7 @@ def _tuning(**kw):
 
 
 @pytest.mark.parametrize("bad", [
-    {"tail_levels": [0, 1]}, {"tail_levels": [1, 4]},
+    {"tail_levels": [0, 1]}, {"tail_levels": [1, 5]},
     {"tile": [[[0, 0, -1], [0, 0, 0]], [[0, 0, 0], [0, 0, 0]]]},
     {"tile": [[[0, 0, 0], [0, 0, 0]], [[0, 10, 0], [0, 0, 0]]]},
     {"map": [[64, 0], [0, 0]]},

@@ -87,7 +87,7 @@ def test_tile_and_map_choices_are_bit_identical(n, prec):
         assert all(v <= lgm0 for v in got["tile"][0][0])
 
 
-@pytest.mark.parametrize("tail", [(1, 1), (2, 3), (3, 2)])
+@pytest.mark.parametrize("tail", [(1, 1), (2, 3), (3, 2), (4, 4)])
 def test_every_tail_depth_matches_the_oracle(tail):
     n = 16
     x = workloads.uniform_fp64(n, 11)
@@ -99,7 +99,7 @@ def test_every_tail_depth_matches_the_oracle(tail):
     assert gu.maxrel(y, x) <= 1e-10
 
 
-@pytest.mark.parametrize("tail", [(1, 1), (3, 3)])
+@pytest.mark.parametrize("tail", [(1, 1), (3, 3), (4, 4)])
 def test_tail_depth_at_n64_fp32_sampled(tail):
     n = 64
     x = workloads.gaussian_field(n, 1)
