@@ -136,7 +136,9 @@ const char* fcc_status_string(fcc_status s);
  *                    Each side is clamped to the node's n / 2^(L+1) cubes.
  *   map[d][L]      : thread map of the gather pass at level L = 0..9.
  *                    FCC_MAP_XCD numbers the blocks so that each XCD takes one
- *                    contiguous range of rows.  FCC_MAP_F_INNER puts the 8 rows
+ *                    contiguous range of rows; FCC_MAP_XCD16 gives each XCD
+ *                    runs of 16 consecutive blocks instead (it takes precedence over
+ *                    FCC_MAP_XCD).  FCC_MAP_F_INNER puts the 8 rows
  *                    of a cube next to each other (otherwise the row's position
  *                    in its cube is the slowest index).  From level 2 on,
  *                    FCC_MAP_NODES8 / FCC_MAP_NODES64 run all rows of an
@@ -159,7 +161,8 @@ enum {
   FCC_MAP_NODES8 = 1u << 2,
   FCC_MAP_NODES64 = 1u << 3,
   FCC_MAP_SPLIT = 1u << 4,
-  FCC_MAP_BALANCE = 1u << 5
+  FCC_MAP_BALANCE = 1u << 5,
+  FCC_MAP_XCD16 = 1u << 6
 };
 typedef struct {
   int tail_levels[2];

@@ -466,9 +466,17 @@ __device__ __forceinline__ RowPart row_part_of(long long t, int n, int L, CubeOr
 
 // Block index of a gather launch (GatherMap::xcd: blocks i, i+8, i+16, ... run
 // on one XCD and get one contiguous range).
+// xcd = 2: runs of 16 consecutive blocks per XCD instead (blocks past the last
+// whole group of 8 x 16 keep their number).
 __device__ __forceinline__ long long gather_block(int xcd) {
   if (!xcd) return blockIdx.x;
-  const unsigned nb = gridDim.x, i = blockIdx.x, x = i & 7u, l = i >> 3, per = nb >> 3, rem = nb & 7u;
+  const unsigned nb = gridDim.x, i = blockIdx.x, x = i & 7u, l = i >> 3;
+  if (xcd == 2) {
+    const unsigned whole = nb / 128u * 128u;
+    if (i >= whole) return i;
+    return (long long)(l >> 4) * 128 + x * 16 + (l & 15u);
+  }
+  const unsigned per = nb >> 3, rem = nb & 7u;
   return (long long)x * per + min(x, rem) + l;
 }
 
@@ -1476,7 +1484,7 @@ GatherMap gmap(const fcc_plan_s* p, int d, int L) {
   const long long half = p->n >> (L + 1), cubes = half * half * half;
   const bool whole = cubes >= p->lv[L].S;
   GatherMap g{};
-  g.xcd = int(m & FCC_MAP_XCD);
+  g.xcd = (m & FCC_MAP_XCD16) ? 2 : int(m & FCC_MAP_XCD);
   g.f_inner = int(whole && (m & FCC_MAP_F_INNER) != 0);
   g.lg = 3 * L;
   if (L >= 2 && (m & FCC_MAP_NODES8)) g.lg = std::min(3, 3 * L);
@@ -2043,7 +2051,7 @@ bool valid_tuning(const fcc_tuning& t) {
     for (int L = 0; L < 10; ++L) {
       const unsigned m = t.map[d][L];
       if (m & ~unsigned(FCC_MAP_XCD | FCC_MAP_F_INNER | FCC_MAP_NODES8 | FCC_MAP_NODES64 | FCC_MAP_SPLIT |
-                        FCC_MAP_BALANCE))
+                        FCC_MAP_BALANCE | FCC_MAP_XCD16))
         return false;
       if ((m & FCC_MAP_NODES8) && (m & FCC_MAP_NODES64)) return false;
     }
@@ -2425,9 +2433,17 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
                                          FCC_MAP_SPLIT | FCC_MAP_F_INNER,
                                          FCC_MAP_SPLIT | FCC_MAP_F_INNER | FCC_MAP_XCD,
                                          FCC_MAP_SPLIT | FCC_MAP_BALANCE,
-                                         FCC_MAP_SPLIT | FCC_MAP_BALANCE | FCC_MAP_XCD};
-      static const unsigned top_inv[] = {0u, FCC_MAP_XCD, FCC_MAP_F_INNER, FCC_MAP_F_INNER | FCC_MAP_XCD, FCC_MAP_BALANCE,
-                                         FCC_MAP_BALANCE | FCC_MAP_XCD};
+                                         FCC_MAP_SPLIT | FCC_MAP_BALANCE | FCC_MAP_XCD,
+                                         FCC_MAP_SPLIT | FCC_MAP_XCD16,
+                                         FCC_MAP_SPLIT | FCC_MAP_F_INNER | FCC_MAP_XCD16};
+      static const unsigned top_inv[] = {0u,
+                                         FCC_MAP_XCD,
+                                         FCC_MAP_F_INNER,
+                                         FCC_MAP_F_INNER | FCC_MAP_XCD,
+                                         FCC_MAP_BALANCE,
+                                         FCC_MAP_BALANCE | FCC_MAP_XCD,
+                                         FCC_MAP_XCD16,
+                                         FCC_MAP_F_INNER | FCC_MAP_XCD16};
       for (int L = 0; L < 2 && L < p->tail_Lt[d] && s == FCC_OK; ++L) {
         const int lgm = p->D - L - 1;
         const int ntiles = L == 0 ? 6 : 4;
@@ -2458,7 +2474,7 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
           }
           bool won = false;
           const unsigned* maps = d == 0 ? top_fwd : top_inv;
-          const int nmaps = d == 0 ? 8 : 6;
+          const int nmaps = d == 0 ? 10 : 8;
           for (int mi = 0; mi < nmaps && s == FCC_OK; ++mi) {
             cur = cand;
             p->tune.tile[d][L][0] = o.la;
@@ -2509,7 +2525,8 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
                                           FCC_MAP_SPLIT | FCC_MAP_NODES8 | FCC_MAP_XCD,
                                           FCC_MAP_SPLIT | FCC_MAP_NODES64,
                                           FCC_MAP_SPLIT | FCC_MAP_BALANCE | FCC_MAP_NODES64,
-                                          FCC_MAP_SPLIT | FCC_MAP_BALANCE | FCC_MAP_NODES64 | FCC_MAP_XCD};
+                                          FCC_MAP_SPLIT | FCC_MAP_BALANCE | FCC_MAP_NODES64 | FCC_MAP_XCD,
+                                          FCC_MAP_SPLIT | FCC_MAP_NODES64 | FCC_MAP_XCD16};
       static const unsigned deep_inv[] = {0u,
                                           FCC_MAP_XCD,
                                           FCC_MAP_NODES8,
@@ -2518,12 +2535,13 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
                                           FCC_MAP_NODES64 | FCC_MAP_XCD,
                                           FCC_MAP_NODES8 | FCC_MAP_F_INNER | FCC_MAP_XCD,
                                           FCC_MAP_BALANCE | FCC_MAP_NODES64 | FCC_MAP_XCD,
-                                          FCC_MAP_BALANCE | FCC_MAP_XCD};
+                                          FCC_MAP_BALANCE | FCC_MAP_XCD,
+                                          FCC_MAP_NODES64 | FCC_MAP_XCD16};
       for (int L = 2; L < p->tail_Lt[d] && s == FCC_OK; ++L) {
         unsigned best_m = p->tune.map[d][L];
         double best_ms = 1e30;
         const unsigned* maps = d == 0 ? deep_fwd : deep_inv;
-        const int nmaps = d == 0 ? 11 : 9;
+        const int nmaps = d == 0 ? 12 : 10;
         for (int mi = 0; mi < nmaps; ++mi) {
           p->tune.map[d][L] = maps[mi];
           s = d == 0 ? time_slots(p, a, b, 1, reps, st, &ms) : time_slots(p, b, a, -1, reps, st, &ms);

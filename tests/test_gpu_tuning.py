@@ -23,7 +23,8 @@ def tuning(tail=(1, 1), tiles=((0, 0, 0), (0, 0, 0), (0, 0, 0), (0, 0, 0)), maps
             "map": [[maps[0], maps[1]] + [deep[0]] * 8, [maps[2], maps[3]] + [deep[1]] * 8]}
 
 
-N8, N64, SP, BAL = fcc.FCC_MAP_NODES8, fcc.FCC_MAP_NODES64, fcc.FCC_MAP_SPLIT, fcc.FCC_MAP_BALANCE
+N8, N64, SP, BAL, X16 = (fcc.FCC_MAP_NODES8, fcc.FCC_MAP_NODES64, fcc.FCC_MAP_SPLIT, fcc.FCC_MAP_BALANCE,
+                         fcc.FCC_MAP_XCD16)
 SCHEDULES = [
     tuning(),
     tuning(tiles=((2, 2, 2), (1, 1, 1), (2, 2, 2), (2, 2, 2)), maps=(0, 0, 2, 2), deep=(N8, N8 | 1)),
@@ -33,6 +34,8 @@ SCHEDULES = [
     tuning(tiles=((2, 2, 2), (1, 1, 1), (2, 2, 2), (2, 2, 2)), maps=(SP | BAL, SP | BAL | 1, BAL, BAL | 1),
            deep=(SP | BAL | N64, BAL | N64 | 1)),
     tuning(maps=(SP | BAL | 1, SP, BAL | 2, 0), deep=(SP | BAL, BAL)),
+    tuning(tiles=((2, 2, 2), (1, 1, 1), (2, 2, 2), (2, 2, 2)), maps=(SP | X16, SP | X16, 2 | X16, X16),
+           deep=(SP | N64 | X16, N64 | X16)),
 ]
 
 
