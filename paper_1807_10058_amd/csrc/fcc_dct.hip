@@ -2107,6 +2107,7 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
     return FCC_ERR_INVALID_ARG;
   if (tuning && !valid_tuning(*tuning)) return FCC_ERR_INVALID_ARG;
   if ((prec == FCC_PREC_SPLIT_BF16 || prec == FCC_PREC_SPLIT_FP16) && n > 8) return FCC_ERR_UNSUPPORTED;
+  if (n > 512) return FCC_ERR_UNSUPPORTED;  // level-0 tables of ~80 GB, derived on the host
   double r[3] = {0.125, 0.0, 0.375};
   if (rst)
     for (int d = 0; d < 3; ++d) {

@@ -50,6 +50,12 @@ def test_plan_rejects_singular_skew_like_the_oracle():
     assert np.linalg.cond(oracle.matrix(2, (0.31, 0.07, 0.23))) < 1e6
 
 
+def test_plan_rejects_n_1024_as_unsupported():
+    with pytest.raises(fcc.FccError) as e:
+        fcc.fcc_dct_plan(1024, stream=0)
+    assert e.value.status == 6
+
+
 def test_plan_rejects_bad_flags_and_precision():
     with pytest.raises(fcc.FccError) as e:
         fcc.fcc_dct_plan(4, prec=9)
