@@ -2017,6 +2017,8 @@ fcc_status fcc_asp_tables(int nl, fcc_level_tables* out) {
   return FCC_OK;
 }
 
+}  // extern "C"
+
 namespace {
 // Built-in schedule: the autotuner's choices on MI355X at n = 64, 128, 256.
 fcc_tuning default_tuning(int n) {
@@ -2084,6 +2086,8 @@ std::map<std::array<int, 4>, fcc_tuning>& tuned() {
   return t;
 }
 }  // namespace
+
+extern "C" {
 
 fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precision prec, unsigned flags,
                         void* hip_stream) {
@@ -2298,6 +2302,8 @@ fcc_status fcc_dct_inverse(fcc_plan_t p, const void* X, void* x, void* hip_strea
                          static_cast<hipStream_t>(hip_stream));
 }
 
+}  // extern "C"
+
 namespace {
 // Average duration (ms) of each launch slot of `reps` transforms in direction
 // +1 (forward) or -1 (inverse), timed with events around every launch.
@@ -2352,6 +2358,8 @@ fcc_status time_slots(const fcc_plan_s* p, const void* in, void* out, int direct
   return s;
 }
 }  // namespace
+
+extern "C" {
 
 fcc_status fcc_dct_time_launches(fcc_plan_t p, const void* in, void* out, int direction, int reps, float* ms,
                                  int cap, int* count, void* hip_stream) {
