@@ -158,7 +158,17 @@ const char* fcc_status_string(fcc_status s);
  *                    row on 2 or 4 adjacent lanes (by the mean row length of
  *                    its position in the cube) and adds the parts; it changes
  *                    the summation order, so results may differ in the last
- *                    bits.  It takes precedence over FCC_MAP_F_INNER. */
+ *                    bits.  It takes precedence over FCC_MAP_F_INNER.
+ *                    FCC_MAP_CLUSTER (gather passes at levels 0 and 1 where
+ *                    the node has a multiple of 4 slices of cubes) runs the
+ *                    slices in blocks of 4, the 8 f of a block one after the
+ *                    other, and orders the slices so that the cubes of one
+ *                    block of B_nl (C_nl) run together: a block is an orbit
+ *                    of (generically) 24 cubes whose rows read the same
+ *                    sources and no others, so with FCC_MAP_XCD or
+ *                    FCC_MAP_XCD16 those sources are fetched into one XCD's
+ *                    L2 once.  It takes precedence over FCC_MAP_F_INNER and
+ *                    FCC_MAP_BALANCE and changes no result bit. */
 enum {
   FCC_MAP_XCD = 1u << 0,
   FCC_MAP_F_INNER = 1u << 1,
@@ -166,7 +176,8 @@ enum {
   FCC_MAP_NODES64 = 1u << 3,
   FCC_MAP_SPLIT = 1u << 4,
   FCC_MAP_BALANCE = 1u << 5,
-  FCC_MAP_XCD16 = 1u << 6
+  FCC_MAP_XCD16 = 1u << 6,
+  FCC_MAP_CLUSTER = 1u << 7
 };
 typedef struct {
   int tail_levels[2];
@@ -236,6 +247,11 @@ fcc_status fcc_dct_roundtrip_residual(fcc_plan_t plan, const void* x, const void
  *     name the source position def + 2*abc (packed the same way).
  *   Polynomial p has coefficients poly[p*nmono + q] of the monomial
  *     c1^e1 c2^e2 c3^e3 with (e1,e2,e3) = mono[3q..3q+2], c = (sigma,tau,rho)(node).
+ *   Blocks of B: cubes whose B rows read a common source are in one block,
+ *     and the rows of a block read no source of another block (a generic
+ *     block is an orbit of 24 cubes).  Block ids are the smallest cube index
+ *     of the block.  C = B^{-1} is block diagonal the other way round: row
+ *     kappa of C reads only positions of cubes in block kappa_block[kappa].
  * Pointers stay valid until the process ends.  Returns FCC_ERR_NOT_POW2 for a
  * bad nl, FCC_ERR_OOM if the derivation cannot allocate. */
 typedef struct {
@@ -248,6 +264,8 @@ typedef struct {
   const int* c_rowptr;   /* 8*m^3 + 1                              */
   const unsigned* c_src;
   const unsigned short* c_pid;
+  const int* cube_block;  /* m^3: per cube, the smallest cube of its block of B   */
+  const int* kappa_block; /* nl^3: per source kappa, the block that reads it in B */
 } fcc_level_tables;
 
 fcc_status fcc_asp_tables(int nl, fcc_level_tables* out);

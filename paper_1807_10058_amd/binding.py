@@ -12,8 +12,8 @@ _LIB_PATH = os.path.join(_HERE, "libfccdct.so")
 FCC_OK = 0
 FCC_PREC_FP64, FCC_PREC_FP32, FCC_PREC_SPLIT_BF16, FCC_PREC_SPLIT_FP16 = 0, 1, 2, 3
 FCC_REAL_INPUT, FCC_STAGES_FP32, FCC_STAGES_FP64, FCC_LEVEL0_FP32 = 1, 2, 4, 8
-FCC_MAP_XCD, FCC_MAP_F_INNER, FCC_MAP_NODES8, FCC_MAP_NODES64, FCC_MAP_SPLIT, FCC_MAP_BALANCE, FCC_MAP_XCD16 = \
-    1, 2, 4, 8, 16, 32, 64
+(FCC_MAP_XCD, FCC_MAP_F_INNER, FCC_MAP_NODES8, FCC_MAP_NODES64, FCC_MAP_SPLIT, FCC_MAP_BALANCE, FCC_MAP_XCD16,
+ FCC_MAP_CLUSTER) = 1, 2, 4, 8, 16, 32, 64, 128
 _MAX_LEVELS = 10
 
 # torch is loaded first so that libfccdct.so binds to the HIP runtime torch
@@ -32,7 +32,8 @@ class _LevelTables(ctypes.Structure):
                 ("b_rowptr", ctypes.POINTER(ctypes.c_int)), ("b_src", ctypes.POINTER(ctypes.c_uint)),
                 ("b_pid", ctypes.POINTER(ctypes.c_ushort)),
                 ("c_rowptr", ctypes.POINTER(ctypes.c_int)), ("c_src", ctypes.POINTER(ctypes.c_uint)),
-                ("c_pid", ctypes.POINTER(ctypes.c_ushort))]
+                ("c_pid", ctypes.POINTER(ctypes.c_ushort)),
+                ("cube_block", ctypes.POINTER(ctypes.c_int)), ("kappa_block", ctypes.POINTER(ctypes.c_int))]
 
 
 class _Tuning(ctypes.Structure):
@@ -247,4 +248,6 @@ def fcc_asp_tables(nl):
         out[side + "_rowptr"] = rp
         out[side + "_src"] = arr(getattr(t, side + "_src"), int(rp[-1]), np.int64)
         out[side + "_pid"] = arr(getattr(t, side + "_pid"), int(rp[-1]), np.int64)
+    out["cube_block"] = arr(t.cube_block, t.m ** 3, np.int64)
+    out["kappa_block"] = arr(t.kappa_block, t.nl ** 3, np.int64)
     return out

@@ -588,4 +588,50 @@ const LevelTables* level_tables(int nl) {
   }
 }
 
+const GatherBlocks* gather_blocks(int nl) {
+  static std::mutex mu;
+  static std::map<int, std::unique_ptr<GatherBlocks>> cache;
+  const LevelTables* T = level_tables(nl);
+  if (!T) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(nl);
+  if (it != cache.end()) return it->second.get();
+  try {
+    const int m = T->m, cubes = m * m * m;
+    const auto& rp = T->b_rowptr;
+    const auto& src = T->b_src;
+    auto flat = [&](uint32_t s) { return (size_t(s >> 20) * nl + ((s >> 10) & 1023u)) * nl + (s & 1023u); };
+    // union-find over cubes; the root of a set is its smallest cube
+    std::vector<int> par(cubes);
+    for (int c = 0; c < cubes; ++c) par[c] = c;
+    auto find = [&](int x) {
+      while (par[x] != x) {
+        par[x] = par[par[x]];
+        x = par[x];
+      }
+      return x;
+    };
+    auto out = std::make_unique<GatherBlocks>();
+    std::vector<int>& owner = out->kappa;  // first cube that reads a source, then its block
+    owner.assign(size_t(nl) * nl * nl, -1);
+    for (int c = 0; c < cubes; ++c)
+      for (int e = rp[size_t(c) * 8]; e < rp[size_t(c) * 8 + 8]; ++e) {
+        const size_t k = flat(src[e]);
+        if (owner[k] < 0) {
+          owner[k] = c;
+        } else {
+          const int a = find(owner[k]), b = find(c);
+          if (a != b) par[std::max(a, b)] = std::min(a, b);
+        }
+      }
+    out->cube.resize(cubes);
+    for (int c = 0; c < cubes; ++c) out->cube[c] = find(c);
+    for (int& o : owner)
+      if (o >= 0) o = out->cube[o];
+    return cache.emplace(nl, std::move(out)).first->second.get();
+  } catch (const std::bad_alloc&) {
+    return nullptr;
+  }
+}
+
 }  // namespace fcc

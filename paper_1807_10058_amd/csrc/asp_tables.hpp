@@ -42,6 +42,19 @@ struct LevelTables {
 // Returns nullptr if nl is invalid or memory runs out.  Thread safe.
 const LevelTables* level_tables(int nl);
 
+// Blocks of B_nl: the cubes abc whose gather rows (def, abc) read a common
+// source form one block, and no source is read from two blocks, so B_nl is
+// block diagonal after permuting rows and sources (for generic abc a block is
+// an orbit of 24 cubes under an affine action of W).  C_nl = B_nl^{-1} has the
+// transposed structure: row kappa of C reads only the positions def + 2 abc
+// of the cubes of the block that reads kappa in B.
+struct GatherBlocks {
+  std::vector<int> cube;   // m^3: per natural cube (a*m + b)*m + c, the smallest cube of its block
+  std::vector<int> kappa;  // nl^3: per node-local source kappa, the block of the B rows that read it
+};
+// Derived from level_tables(nl) (cached; nullptr on failure).
+const GatherBlocks* gather_blocks(int nl);
+
 // W = S_4 as 24 integer 3x3 matrices (row-major), closure of the generators of
 // eq. GeneratorMatricesS4.
 const std::vector<std::array<int, 9>>& weyl_group();

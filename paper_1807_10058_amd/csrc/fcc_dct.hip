@@ -409,7 +409,8 @@ __device__ __forceinline__ cx<R> ldc(const double2& v) {
 struct RowIdx {
   int J[3], a[3], cube, f;
 };
-__device__ __forceinline__ RowIdx row_of(long long t, int n, int L, CubeOrder ord, int S, GatherMap gm) {
+__device__ __forceinline__ RowIdx row_of(long long t, int n, int L, CubeOrder ord, int S, GatherMap gm,
+                                         const int* perm = nullptr) {
   const int mask = (1 << L) - 1;
   const int lgm = __ffs(n) - 2 - L;  // log2 of m = n / 2^(L+1)
   // node within its group fastest, then the row, then the group
@@ -419,7 +420,12 @@ __device__ __forceinline__ RowIdx row_of(long long t, int n, int L, CubeOrder or
   const long long grp = hi / rows, rest = hi - grp * rows;
   const int jf = int((grp << lg) | (t & ((1LL << lg) - 1)));
   RowIdx r;
-  if (gm.f_inner) {
+  if (gm.cluster) {
+    // unit q = (block of 4 slices, f, slice within the block); 64 lanes each
+    const long long q = rest / S;
+    r.f = int((q >> 2) & 7);
+    r.cube = (perm[q >> 5] * 4 + int(q & 3)) * S + int(rest - q * S);
+  } else if (gm.f_inner) {
     const long long sf = rest / S;  // slice * 8 + f
     r.f = int(sf & 7);
     r.cube = int((sf >> 3) * S + (rest - sf * S));
@@ -520,7 +526,7 @@ __global__ __launch_bounds__(256) void k_fwd_gather(VolSet vs, int nvol, int n, 
       const RowPart rp = row_part_of(t, n, L, lv.b.order, gm);
       ri = rp.r, k = rp.k, kf = rp.kf;
     } else {
-      ri = row_of(t, n, L, lv.b.order, lv.S, gm);
+      ri = row_of(t, n, L, lv.b.order, lv.S, gm, lv.b.perm);
     }
     const int slice = ri.cube / lv.S;
     row_begin(lv.b, lv.S, slice * 8 + ri.f, ri.cube - slice * lv.S, rc, k, kf);
@@ -781,7 +787,7 @@ __global__ __launch_bounds__(256) void k_inv_basis(VolSet vs, int nvol, int n, i
       const RowPart rp = row_part_of(t, n, L, lv.c.order, gm);
       ri = rp.r, k = rp.k, kf = rp.kf;
     } else {
-      ri = row_of(t, n, L, lv.c.order, lv.S, gm);
+      ri = row_of(t, n, L, lv.c.order, lv.S, gm, lv.c.perm);
     }
     const int slice = ri.cube / lv.S;
     row_begin(lv.c, lv.S, slice * 8 + ri.f, ri.cube - slice * lv.S, rc, k, kf);
@@ -1238,8 +1244,8 @@ fcc_status upload(const std::vector<T>& v, const T** out, std::vector<void*>* ow
 // rows cube * 8 + f; zero_pid names a polynomial equal to zero.
 // Sliced device copy of one side (B or C) of the tables, cube order `ord`.
 fcc_status upload_side(const std::vector<int>& rowptr, const std::vector<uint32_t>& src,
-                       const std::vector<uint16_t>& pid, const DevPolys& dp, int S, CubeOrder ord, DevSide* out,
-                       std::vector<void*>* own) {
+                       const std::vector<uint16_t>& pid, const DevPolys& dp, int S, CubeOrder ord,
+                       const GatherBlocks* blocks, bool cside, DevSide* out, std::vector<void*>* own) {
   const int rows = int(rowptr.size()) - 1, cubes = rows / 8, slices = (cubes + S - 1) / S;
   int m = 1, lgm = 0;
   while (m * m * m < cubes) m *= 2, ++lgm;
@@ -1281,6 +1287,38 @@ fcc_status upload_side(const std::vector<int>& rowptr, const std::vector<uint32_
   if ((s = upload(len, &out->len, own)) != FCC_OK) return s;
   if ((s = upload(ssrc, &out->src, own)) != FCC_OK) return s;
   out->order = ord;
+  out->perm = nullptr;
+  if (S > 1 && blocks && slices % 4 == 0) {
+    // Groups of 4 consecutive slices (one block of threads: neighbouring
+    // tiles, which share cache lines in the CU) sorted by the first (in slice
+    // order) block of B they touch, so that the groups holding one block
+    // become neighbours.  A B row belongs to its cube's block; a C row kappa
+    // to the block that reads kappa in B.
+    std::vector<int> qof(cubes);
+    for (int q = 0; q < cubes; ++q) qof[nat[q]] = q;
+    const int groups = slices / 4;
+    std::vector<std::pair<int, int>> key(groups);
+    for (int gi = 0; gi < groups; ++gi) {
+      int k = cubes;
+      for (int j = 0; j < 4 * S; ++j) {
+        const int c = nat[gi * 4 * S + j];
+        if (!cside) {
+          k = std::min(k, qof[blocks->cube[c]]);
+          continue;
+        }
+        const int a = c / (m * m), b = (c / m) % m, cc = c % m, nl = 2 * m;
+        for (int i = 0; i < 8; ++i) {
+          const size_t kap = (size_t(2 * a + (i >> 2)) * nl + (2 * b + ((i >> 1) & 1))) * nl + (2 * cc + (i & 1));
+          k = std::min(k, qof[blocks->kappa[kap]]);
+        }
+      }
+      key[gi] = {k, gi};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int> perm(groups);
+    for (int i = 0; i < groups; ++i) perm[i] = key[i].second;
+    if ((s = upload(perm, &out->perm, own)) != FCC_OK) return s;
+  }
   return upload(spid, &out->pid, own);
 }
 
@@ -1362,8 +1400,10 @@ fcc_status device_side(int dev, int nl, int S, int side, CubeOrder ord, DevSide*
   const DevPolys* dp = nullptr;
   fcc_status s = device_polys(dev, nl, &dp);
   if (s != FCC_OK) return s;
-  s = side == 0 ? upload_side(T->b_rowptr, T->b_src, T->b_pid, *dp, S, ord, out, own)
-                : upload_side(T->c_rowptr, T->c_src, T->c_pid, *dp, S, ord, out, own);
+  const GatherBlocks* blocks = nullptr;
+  if (S > 1 && !(blocks = gather_blocks(nl))) return FCC_ERR_OOM;
+  s = side == 0 ? upload_side(T->b_rowptr, T->b_src, T->b_pid, *dp, S, ord, blocks, false, out, own)
+                : upload_side(T->c_rowptr, T->c_src, T->c_pid, *dp, S, ord, blocks, true, out, own);
   if (s == FCC_OK && !own) C.sides.emplace(key, *out);
   return s;
 }
@@ -1487,9 +1527,13 @@ GatherMap gmap(const fcc_plan_s* p, int d, int L) {
   g.xcd = (m & FCC_MAP_XCD16) ? 2 : int(m & FCC_MAP_XCD);
   g.f_inner = int(whole && (m & FCC_MAP_F_INNER) != 0);
   g.lg = 3 * L;
+  // the clustered map runs blocks of 4 whole slices (levels 0 and 1 only)
+  const long long S = p->lv[L].S;
+  g.cluster = int((m & FCC_MAP_CLUSTER) && L <= 1 && S > 1 && cubes % (4 * S) == 0);
+  if (g.cluster) g.f_inner = 0;
   if (L >= 2 && (m & FCC_MAP_NODES8)) g.lg = std::min(3, 3 * L);
   if (L >= 2 && (m & FCC_MAP_NODES64)) g.lg = std::min(6, 3 * L);
-  if (m & FCC_MAP_BALANCE) {
+  if ((m & FCC_MAP_BALANCE) && !g.cluster) {
     g.balance = 1;
     g.f_inner = 0;
     // f by decreasing lanes per row keeps every row's lanes aligned
@@ -2014,6 +2058,10 @@ fcc_status fcc_asp_tables(int nl, fcc_level_tables* out) {
   out->c_rowptr = T->c_rowptr.data();
   out->c_src = T->c_src.data();
   out->c_pid = T->c_pid.data();
+  const GatherBlocks* gb = gather_blocks(nl);
+  if (!gb) return FCC_ERR_OOM;
+  out->cube_block = gb->cube.data();
+  out->kappa_block = gb->kappa.data();
   return FCC_OK;
 }
 
@@ -2034,12 +2082,13 @@ fcc_tuning default_tuning(int n) {
   // forward: gather and DCT_2 as two passes, groups of 64 nodes from level 2 on
   for (int L = 0; L < 10; ++L) t.map[0][L] = L < 2 ? FCC_MAP_SPLIT : (FCC_MAP_SPLIT | FCC_MAP_NODES64);
   // inverse: small n XCD-contiguous (groups of 64 nodes from level 2 on); larger
-  // n the 8 rows of a cube together at the top, XCD-contiguous at levels 2-3
+  // n the slices in block order with XCD ranges at the top, XCD-contiguous at
+  // levels 2-3
   if (n <= 64) {
     t.map[1][0] = t.map[1][1] = FCC_MAP_XCD;
     for (int L = 2; L < 10; ++L) t.map[1][L] = FCC_MAP_NODES64 | FCC_MAP_XCD;
   } else {
-    t.map[1][0] = t.map[1][1] = FCC_MAP_F_INNER;
+    t.map[1][0] = t.map[1][1] = FCC_MAP_CLUSTER | FCC_MAP_XCD;
     t.map[1][2] = t.map[1][3] = FCC_MAP_XCD;
   }
   return t;
@@ -2053,7 +2102,7 @@ bool valid_tuning(const fcc_tuning& t) {
     for (int L = 0; L < 10; ++L) {
       const unsigned m = t.map[d][L];
       if (m & ~unsigned(FCC_MAP_XCD | FCC_MAP_F_INNER | FCC_MAP_NODES8 | FCC_MAP_NODES64 | FCC_MAP_SPLIT |
-                        FCC_MAP_BALANCE | FCC_MAP_XCD16))
+                        FCC_MAP_BALANCE | FCC_MAP_XCD16 | FCC_MAP_CLUSTER))
         return false;
       if ((m & FCC_MAP_NODES8) && (m & FCC_MAP_NODES64)) return false;
     }
@@ -2444,7 +2493,10 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
                                          FCC_MAP_SPLIT | FCC_MAP_BALANCE,
                                          FCC_MAP_SPLIT | FCC_MAP_BALANCE | FCC_MAP_XCD,
                                          FCC_MAP_SPLIT | FCC_MAP_XCD16,
-                                         FCC_MAP_SPLIT | FCC_MAP_F_INNER | FCC_MAP_XCD16};
+                                         FCC_MAP_SPLIT | FCC_MAP_F_INNER | FCC_MAP_XCD16,
+                                         FCC_MAP_SPLIT | FCC_MAP_CLUSTER,
+                                         FCC_MAP_SPLIT | FCC_MAP_CLUSTER | FCC_MAP_XCD,
+                                         FCC_MAP_SPLIT | FCC_MAP_CLUSTER | FCC_MAP_XCD16};
       static const unsigned top_inv[] = {0u,
                                          FCC_MAP_XCD,
                                          FCC_MAP_F_INNER,
@@ -2452,7 +2504,10 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
                                          FCC_MAP_BALANCE,
                                          FCC_MAP_BALANCE | FCC_MAP_XCD,
                                          FCC_MAP_XCD16,
-                                         FCC_MAP_F_INNER | FCC_MAP_XCD16};
+                                         FCC_MAP_F_INNER | FCC_MAP_XCD16,
+                                         FCC_MAP_CLUSTER,
+                                         FCC_MAP_CLUSTER | FCC_MAP_XCD,
+                                         FCC_MAP_CLUSTER | FCC_MAP_XCD16};
       for (int L = 0; L < 2 && L < p->tail_Lt[d] && s == FCC_OK; ++L) {
         const int lgm = p->D - L - 1;
         const int ntiles = L == 0 ? 6 : 4;
@@ -2483,7 +2538,7 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
           }
           bool won = false;
           const unsigned* maps = d == 0 ? top_fwd : top_inv;
-          const int nmaps = d == 0 ? 10 : 8;
+          const int nmaps = d == 0 ? int(sizeof top_fwd / sizeof top_fwd[0]) : int(sizeof top_inv / sizeof top_inv[0]);
           for (int mi = 0; mi < nmaps && s == FCC_OK; ++mi) {
             cur = cand;
             p->tune.tile[d][L][0] = o.la;

@@ -121,6 +121,7 @@ struct DevSide {
   const uint32_t* src;  // packed node-local position
   const uint16_t* pid;  // coefficient polynomial
   CubeOrder order;      // cube order of the slices
+  const int* perm;      // S > 1: groups of 4 slices in block order (see GatherMap::cluster), else nullptr
 };
 struct DevLevel {
   DevSide b, c;        // forward B_nl, inverse C_nl
@@ -142,9 +143,13 @@ struct DevLevel {
 // (decreasing K_f, which keeps every row's lanes aligned), lane k fastest,
 // then cube, then node; off[i] is the first thread of the i-th f in the
 // group and off[8] the group's thread count.
+// cluster (levels 0 and 1): the threads run groups of 4 consecutive slices
+// of one f, the 8 f of the same group one after the other, and the groups in
+// the order DevSide::perm, which keeps the cubes of a block of B (or C)
+// together: they read the same sources, so with xcd these stay in one XCD's L2.
 struct GatherMap {
   int xcd, f_inner, lg;
-  int balance;
+  int balance, cluster;
   unsigned char kf[8], forder[8];
   long long off[9];
 };

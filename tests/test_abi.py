@@ -84,7 +84,7 @@ def _tuning(**kw):
     {"tail_levels": [0, 1]}, {"tail_levels": [1, 5]},
     {"tile": [[[0, 0, -1], [0, 0, 0]], [[0, 0, 0], [0, 0, 0]]]},
     {"tile": [[[0, 0, 0], [0, 0, 0]], [[0, 10, 0], [0, 0, 0]]]},
-    {"map": [[128, 0], [0, 0]]},
+    {"map": [[256, 0], [0, 0]]},
     {"map": [[0, 0, 0], [0, 0, 12]]},
 ])
 def test_plan_tuned_rejects_bad_schedules(bad):

@@ -23,8 +23,8 @@ def tuning(tail=(1, 1), tiles=((0, 0, 0), (0, 0, 0), (0, 0, 0), (0, 0, 0)), maps
             "map": [[maps[0], maps[1]] + [deep[0]] * 8, [maps[2], maps[3]] + [deep[1]] * 8]}
 
 
-N8, N64, SP, BAL, X16 = (fcc.FCC_MAP_NODES8, fcc.FCC_MAP_NODES64, fcc.FCC_MAP_SPLIT, fcc.FCC_MAP_BALANCE,
-                         fcc.FCC_MAP_XCD16)
+N8, N64, SP, BAL, X16, CL = (fcc.FCC_MAP_NODES8, fcc.FCC_MAP_NODES64, fcc.FCC_MAP_SPLIT, fcc.FCC_MAP_BALANCE,
+                             fcc.FCC_MAP_XCD16, fcc.FCC_MAP_CLUSTER)
 SCHEDULES = [
     tuning(),
     tuning(tiles=((2, 2, 2), (1, 1, 1), (2, 2, 2), (2, 2, 2)), maps=(0, 0, 2, 2), deep=(N8, N8 | 1)),
@@ -36,6 +36,10 @@ SCHEDULES = [
     tuning(maps=(SP | BAL | 1, SP, BAL | 2, 0), deep=(SP | BAL, BAL)),
     tuning(tiles=((2, 2, 2), (1, 1, 1), (2, 2, 2), (2, 2, 2)), maps=(SP | X16, SP | X16, 2 | X16, X16),
            deep=(SP | N64 | X16, N64 | X16)),
+    # slices in block order (levels 0 and 1, n >= 16), with and without XCD ranges
+    tuning(tiles=((2, 2, 2), (1, 1, 1), (2, 2, 2), (2, 2, 2)), maps=(SP | CL | 1, SP | CL | X16, CL | 1, CL | 2),
+           deep=(SP | N64, N64 | 1)),
+    tuning(maps=(SP | CL, SP | CL | 1, CL | X16, CL | 1), deep=(SP, 0)),
 ]
 
 

@@ -110,3 +110,50 @@ def test_derivation_is_identical_across_processes():
     outs = {subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, check=True).stdout
             for _ in range(4)}
     assert len(outs) == 1, outs
+
+
+@pytest.mark.parametrize("nl", [8, 32, 64])
+def test_tables_are_block_diagonal_over_cube_orbits(nl):
+    """The blocks the clustered gather map orders by.  B: cubes whose rows
+    share a source, checked against connected components of the cube-source
+    graph (scipy), at most 24 cubes (|W|) and 24 for most cubes; every source
+    is read by one block.  C = B^{-1}: row kappa reads only positions of the
+    block that reads kappa in B."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    t = fcc.fcc_asp_tables(nl)
+    m = t["m"]
+    blk, kblk = t["cube_block"], t["kappa_block"]
+
+    def flat(s):
+        return (s >> 20) * nl * nl + ((s >> 10) & 1023) * nl + (s & 1023)
+
+    rp, src = t["b_rowptr"], t["b_src"]
+    cube = np.repeat(np.arange(8 * m ** 3), np.diff(rp)) // 8
+    k = flat(src)
+    g = coo_matrix((np.ones(len(k)), (cube, m ** 3 + k)), shape=(m ** 3 + nl ** 3,) * 2)
+    _, lab = connected_components(g, directed=False)
+    lab = lab[:m ** 3]
+    pairs = set(zip(lab.tolist(), blk.tolist()))
+    assert len(pairs) == len(set(lab.tolist())) == len(set(blk.tolist()))
+    first = {}
+    for c, b in enumerate(blk.tolist()):
+        first.setdefault(b, c)
+    assert all(first[b] == b for b in first)  # id = smallest cube of the block
+    sizes = np.bincount(blk, minlength=m ** 3)
+    sizes = sizes[sizes > 0]
+    assert sizes.max() <= 24
+    if nl >= 32:
+        assert (sizes == 24).sum() * 24 > 0.6 * m ** 3
+    # every source is read, by exactly the block kappa_block names
+    assert (kblk >= 0).all()
+    assert np.array_equal(kblk[k], blk[cube])
+    # C rows: kappa = i + 2 abc reads positions def + 2 abc' of block kblk[kappa]
+    rp, src = t["c_rowptr"], t["c_src"]
+    row = np.repeat(np.arange(8 * m ** 3), np.diff(rp))
+    c, i = row // 8, row % 8
+    a, b, cc = c // (m * m), (c // m) % m, c % m
+    kap = (2 * a + (i >> 2)) * nl * nl + (2 * b + ((i >> 1) & 1)) * nl + (2 * cc + (i & 1))
+    x, y, z = src >> 20, (src >> 10) & 1023, src & 1023
+    pc = ((x >> 1) * m + (y >> 1)) * m + (z >> 1)
+    assert np.array_equal(blk[pc], kblk[kap])
