@@ -50,7 +50,7 @@ typedef enum {
   FCC_ERR_SINGULAR_SKEW = 3, /* (r,s,t) gives coinciding zeros somewhere in the tree */
   FCC_ERR_OOM = 4,           /* device or host allocation failed                   */
   FCC_ERR_HIP = 5,           /* a HIP runtime call failed                          */
-  FCC_ERR_UNSUPPORTED = 6    /* valid request this build does not serve (n = 1024) */
+  FCC_ERR_UNSUPPORTED = 6    /* valid request this build does not serve (n > 256) */
 } fcc_status;
 
 typedef enum {
@@ -77,9 +77,9 @@ enum {
 /* Build a plan for DCT_{n x n x n}(r,s,t) (Definition 2).
  *   plan  : receives the new plan (set to NULL on failure).
  *   n     : size parameter, a power of two in [1, 1024] (fast algorithm, Sec. IV-B).
- *           n <= 512 is served (n <= 256 is what the tests and measurements
- *           cover; at n = 512 the level-0 tables alone take about 10 GB of
- *           device memory); n = 1024 returns FCC_ERR_UNSUPPORTED.
+ *           n <= 256 is served (the gather tables pack node-local
+ *           coordinates in 8 bits); n = 512 and 1024 return
+ *           FCC_ERR_UNSUPPORTED.
  *   rst   : host pointer to the skew (r,s,t), or NULL for (1/8, 0, 3/8).
  *   prec  : data/compute precision (fcc_precision).  The split-MFMA precisions
  *           apply the dense transform matrix and need n <= 8.
@@ -88,7 +88,7 @@ enum {
  * uploads them, generates FP64 tables on the GPU on `hip_stream`, allocates
  * scratch, and synchronises `hip_stream` once before returning.
  * Errors: FCC_ERR_NOT_POW2, FCC_ERR_SINGULAR_SKEW, FCC_ERR_INVALID_ARG,
- * FCC_ERR_UNSUPPORTED (split precisions with n > 8, n = 1024), FCC_ERR_OOM,
+ * FCC_ERR_UNSUPPORTED (split precisions with n > 8, n > 256), FCC_ERR_OOM,
  * FCC_ERR_HIP. */
 fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precision prec,
                         unsigned flags, void* hip_stream);

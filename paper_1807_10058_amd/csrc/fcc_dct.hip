@@ -270,8 +270,7 @@ __device__ __forceinline__ void load_polys(const DevLevel& lv, double* sp) {
 constexpr int kChunk = 8;
 struct RowCursor {
   int e0, len;
-  uint32_t s8[kChunk];
-  uint16_t p8[kChunk];
+  uint32_t e8[kChunk];
 };
 __device__ __forceinline__ void row_begin(const DevSide& sd, int S, int r, int j, RowCursor& rc, int k = 0,
                                           int kf = 0) {
@@ -285,8 +284,7 @@ __device__ __forceinline__ void row_begin(const DevSide& sd, int S, int r, int j
 #pragma unroll
   for (int u = 0; u < kChunk; ++u) {
     const int e = min(u, rc.len - 1);  // past the row's end: repeat its last entry, unused
-    rc.s8[u] = sd.src[rc.e0 + e * S];
-    rc.p8[u] = sd.pid[rc.e0 + e * S];
+    rc.e8[u] = sd.ent[rc.e0 + e * S];
   }
 }
 // Sum of the parts of a row over its 2^kf adjacent lanes (every lane gets it).
@@ -306,27 +304,19 @@ __device__ __forceinline__ cx<R> row_finish(const TI* __restrict__ in, int n, in
     cx<R> v8[kChunk];
 #pragma unroll
     for (int u = 0; u < kChunk; ++u)
-      v8[u] = IO<TI, R>::ld(in, gpos(n, L, J, int(rc.s8[u] >> 20), int((rc.s8[u] >> 10) & 1023u), int(rc.s8[u] & 1023u)));
-    uint32_t sn[kChunk];
-    uint16_t pn[kChunk];
+      v8[u] = IO<TI, R>::ld(in, gpos(n, L, J, ent_x(rc.e8[u]), ent_y(rc.e8[u]), ent_z(rc.e8[u])));
+    uint32_t en[kChunk];
     const bool more = c + kChunk < len;
     if (more) {
 #pragma unroll
-      for (int u = 0; u < kChunk; ++u) {
-        const int e = min(c + kChunk + u, len - 1);
-        sn[u] = sd.src[e0 + e * S];
-        pn[u] = sd.pid[e0 + e * S];
-      }
+      for (int u = 0; u < kChunk; ++u) en[u] = sd.ent[e0 + min(c + kChunk + u, len - 1) * S];
     }
 #pragma unroll
     for (int u = 0; u < kChunk; ++u)
-      if (c + u < len) acc = acc + poly_value(sp, nconst, rc.p8[u], mono) * v8[u];
+      if (c + u < len) acc = acc + poly_value(sp, nconst, ent_pid(rc.e8[u]), mono) * v8[u];
     if (more) {
 #pragma unroll
-      for (int u = 0; u < kChunk; ++u) {
-        rc.s8[u] = sn[u];
-        rc.p8[u] = pn[u];
-      }
+      for (int u = 0; u < kChunk; ++u) rc.e8[u] = en[u];
     }
   }
   return acc;
@@ -347,21 +337,15 @@ __device__ __forceinline__ cx<R> row_uniform(const TI* __restrict__ in, int n, i
   const int len = __builtin_amdgcn_readfirstlane(sd.len[r]);
   cx<R> acc{R(0), R(0)};
   for (int c = 0; c < len; c += kChunk) {
-    uint32_t s8[kChunk];
-    int p8[kChunk];
+    uint32_t e8[kChunk];
 #pragma unroll
-    for (int u = 0; u < kChunk; ++u) {
-      const int e = min(c + u, len - 1);
-      s8[u] = __builtin_amdgcn_readfirstlane(sd.src[e0 + e]);
-      p8[u] = __builtin_amdgcn_readfirstlane(int(sd.pid[e0 + e]));
-    }
+    for (int u = 0; u < kChunk; ++u) e8[u] = __builtin_amdgcn_readfirstlane(sd.ent[e0 + min(c + u, len - 1)]);
     cx<R> v8[kChunk];
 #pragma unroll
-    for (int u = 0; u < kChunk; ++u)
-      v8[u] = IO<TI, R>::ld(in, gpos(n, L, J, int(s8[u] >> 20), int((s8[u] >> 10) & 1023u), int(s8[u] & 1023u)));
+    for (int u = 0; u < kChunk; ++u) v8[u] = IO<TI, R>::ld(in, gpos(n, L, J, ent_x(e8[u]), ent_y(e8[u]), ent_z(e8[u])));
 #pragma unroll
     for (int u = 0; u < kChunk; ++u)
-      if (c + u < len) acc = acc + poly_value(poly, nconst, p8[u], mono) * v8[u];
+      if (c + u < len) acc = acc + poly_value(poly, nconst, ent_pid(e8[u]), mono) * v8[u];
   }
   return acc;
 }
@@ -835,37 +819,24 @@ __device__ __forceinline__ cx<R> lds_row(const cx<R>* buf, int nl0, int l, const
                                          int len, const double* sp, int nconst, const cx<R> mono[kNumMono]) {
   cx<R> acc{R(0), R(0)};
   if (len <= 0) return acc;
-  uint32_t s8[kChunk];
-  uint16_t p8[kChunk];
+  uint32_t e8[kChunk];
 #pragma unroll
-  for (int u = 0; u < kChunk; ++u) {
-    const int e = min(u, len - 1);
-    s8[u] = sd.src[e0 + e];
-    p8[u] = sd.pid[e0 + e];
-  }
+  for (int u = 0; u < kChunk; ++u) e8[u] = sd.ent[e0 + min(u, len - 1)];
   for (int c = 0; c < len; c += kChunk) {
-    uint32_t sn[kChunk];
-    uint16_t pn[kChunk];
+    uint32_t en[kChunk];
     const bool more = c + kChunk < len;
     if (more) {
 #pragma unroll
-      for (int u = 0; u < kChunk; ++u) {
-        const int e = min(c + kChunk + u, len - 1);
-        sn[u] = sd.src[e0 + e];
-        pn[u] = sd.pid[e0 + e];
-      }
+      for (int u = 0; u < kChunk; ++u) en[u] = sd.ent[e0 + min(c + kChunk + u, len - 1)];
     }
 #pragma unroll
     for (int u = 0; u < kChunk; ++u)
       if (c + u < len)
-        acc = acc + poly_value(sp, nconst, p8[u], mono) *
-                        buf[lpos(nl0, l, jp, int(s8[u] >> 20), int((s8[u] >> 10) & 1023u), int(s8[u] & 1023u))];
+        acc = acc + poly_value(sp, nconst, ent_pid(e8[u]), mono) *
+                        buf[lpos(nl0, l, jp, ent_x(e8[u]), ent_y(e8[u]), ent_z(e8[u]))];
     if (more) {
 #pragma unroll
-      for (int u = 0; u < kChunk; ++u) {
-        s8[u] = sn[u];
-        p8[u] = pn[u];
-      }
+      for (int u = 0; u < kChunk; ++u) e8[u] = en[u];
     }
   }
   return acc;
@@ -1249,6 +1220,7 @@ fcc_status upload_side(const std::vector<int>& rowptr, const std::vector<uint32_
   const int rows = int(rowptr.size()) - 1, cubes = rows / 8, slices = (cubes + S - 1) / S;
   int m = 1, lgm = 0;
   while (m * m * m < cubes) m *= 2, ++lgm;
+  if (2 * m > 256) return FCC_ERR_UNSUPPORTED;  // coordinates of a packed entry have 8 bits
   // natural cube index of the q-th cube in the slice order
   std::vector<int> nat(cubes);
   for (int q = 0; q < cubes; ++q) {
@@ -1270,22 +1242,24 @@ fcc_status upload_side(const std::vector<int>& rowptr, const std::vector<uint32_
       total += size_t(mx) * S;
     }
   if (total > 0x7fffffffu) return FCC_ERR_UNSUPPORTED;
-  std::vector<uint32_t> ssrc(total, 0u);
-  std::vector<uint16_t> spid(total, dp.zero_pid);
+  // packed entries (x << 24) | (y << 16) | (z << 8) | polynomial; padding:
+  // position 0 with the zero polynomial
+  std::vector<uint32_t> sent(total, uint32_t(dp.zero_pid));
   for (int sl = 0; sl < slices; ++sl)
     for (int f = 0; f < 8; ++f)
       for (int j = 0; j < S && sl * S + j < cubes; ++j) {
         const int r = nat[sl * S + j] * 8 + f;
         for (int e = 0; e < rowptr[r + 1] - rowptr[r]; ++e) {
           const size_t q = size_t(start[size_t(sl) * 8 + f]) + size_t(e) * S + j;
-          ssrc[q] = src[rowptr[r] + e];
-          spid[q] = dp.newid[pid[rowptr[r] + e]];
+          const uint32_t sv = src[rowptr[r] + e];
+          sent[q] = ((sv >> 20) << 24) | (((sv >> 10) & 1023u) << 16) | ((sv & 1023u) << 8) |
+                    uint32_t(dp.newid[pid[rowptr[r] + e]]);
         }
       }
   fcc_status s;
   if ((s = upload(start, &out->start, own)) != FCC_OK) return s;
   if ((s = upload(len, &out->len, own)) != FCC_OK) return s;
-  if ((s = upload(ssrc, &out->src, own)) != FCC_OK) return s;
+  if ((s = upload(sent, &out->ent, own)) != FCC_OK) return s;
   out->order = ord;
   out->perm = nullptr;
   if (S > 1 && blocks && slices % 4 == 0) {
@@ -1319,7 +1293,7 @@ fcc_status upload_side(const std::vector<int>& rowptr, const std::vector<uint32_
     for (int i = 0; i < groups; ++i) perm[i] = key[i].second;
     if ((s = upload(perm, &out->perm, own)) != FCC_OK) return s;
   }
-  return upload(spid, &out->pid, own);
+  return FCC_OK;
 }
 
 // The polynomials of node size nl on device dev (cached; caller holds the
@@ -2160,7 +2134,7 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
     return FCC_ERR_INVALID_ARG;
   if (tuning && !valid_tuning(*tuning)) return FCC_ERR_INVALID_ARG;
   if ((prec == FCC_PREC_SPLIT_BF16 || prec == FCC_PREC_SPLIT_FP16) && n > 8) return FCC_ERR_UNSUPPORTED;
-  if (n > 512) return FCC_ERR_UNSUPPORTED;  // level-0 tables of ~80 GB, derived on the host
+  if (n > 256) return FCC_ERR_UNSUPPORTED;  // table entries pack node-local coordinates in 8 bits
   double r[3] = {0.125, 0.0, 0.375};
   if (rst)
     for (int d = 0; d < 3; ++d) {

@@ -109,6 +109,12 @@ __host__ __device__ __forceinline__ void cube_abc(int q, int lgm, CubeOrder o, i
   a[0] = ((tile >> (ntc + ntb)) << o.la) | (inner >> (o.lb + o.lc));
 }
 
+// Fields of a packed table entry (node sizes up to 256).
+__device__ __forceinline__ int ent_x(uint32_t e) { return int(e >> 24); }
+__device__ __forceinline__ int ent_y(uint32_t e) { return int((e >> 16) & 255u); }
+__device__ __forceinline__ int ent_z(uint32_t e) { return int((e >> 8) & 255u); }
+__device__ __forceinline__ int ent_pid(uint32_t e) { return int(e & 255u); }
+
 // Device view of the basis-change tables of one node size, sliced for the
 // wavefronts that read them: the rows of S consecutive cubes form a slice; for
 // each def (or i) the slice stores max-length entries interleaved cube by cube
@@ -118,8 +124,7 @@ __host__ __device__ __forceinline__ void cube_abc(int q, int lgm, CubeOrder o, i
 struct DevSide {
   const int* start;     // per (slice * 8 + f)
   const int* len;       // per (slice * 8 + f)
-  const uint32_t* src;  // packed node-local position
-  const uint16_t* pid;  // coefficient polynomial
+  const uint32_t* ent;  // (x << 24) | (y << 16) | (z << 8) | p: node-local source (x,y,z), polynomial p
   CubeOrder order;      // cube order of the slices
   const int* perm;      // S > 1: groups of 4 slices in block order (see GatherMap::cluster), else nullptr
 };

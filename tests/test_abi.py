@@ -50,9 +50,11 @@ def test_plan_rejects_singular_skew_like_the_oracle():
     assert np.linalg.cond(oracle.matrix(2, (0.31, 0.07, 0.23))) < 1e6
 
 
-def test_plan_rejects_n_1024_as_unsupported():
+@pytest.mark.parametrize("n", [512, 1024])
+def test_plan_rejects_n_above_256_as_unsupported(n):
+    # checked before any device work, so this runs without a GPU
     with pytest.raises(fcc.FccError) as e:
-        fcc.fcc_dct_plan(1024, stream=0)
+        fcc.fcc_dct_plan(n, stream=0)
     assert e.value.status == 6
 
 
