@@ -1477,10 +1477,15 @@ void launch(void (*kernel)(KArgs...), dim3 grid, dim3 block, unsigned shmem, hip
 }
 
 
-dim3 grid_cubes(int n, int nvol) {  // one thread per 2x2x2 cube
-  long long h = n >> 1;
-  long long threads = h * h * h * nvol;
-  return dim3((unsigned)((threads + kBlock - 1) / kBlock), 1, 1);
+// One thread per 2x2x2 cube.  Small passes (fewer than 4 blocks of 256 per
+// CU) use blocks of 64 threads so that they still reach every CU.
+int cube_block(int n, int nvol) {
+  const long long h = n >> 1;
+  return h * h * h * nvol < 1024LL * kBlock ? 64 : kBlock;
+}
+dim3 grid_cubes(int n, int nvol) {
+  const long long h = n >> 1, threads = h * h * h * nvol, b = cube_block(n, nvol);
+  return dim3((unsigned)((threads + b - 1) / b), 1, 1);
 }
 dim3 grid_points(int n, int nvol) {  // one thread per point (gather row)
   long long threads = (long long)n * n * n * nvol;
@@ -1598,9 +1603,9 @@ void fwd_dct2_dispatch(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int 
   const double2* h = phases(p, L);
   const NodeConst* nc = nodes_of(p, L);
   if (to == DT::F32C)
-    launch((k_fwd_dct2<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, h, nc);
+    launch((k_fwd_dct2<R, float2>), g, dim3(cube_block(p->n, nvol)), 0, st, vs, nvol, p->n, L, h, nc);
   else
-    launch((k_fwd_dct2<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, h, nc);
+    launch((k_fwd_dct2<R, double2>), g, dim3(cube_block(p->n, nvol)), 0, st, vs, nvol, p->n, L, h, nc);
 }
 
 template <typename R>
@@ -1609,9 +1614,9 @@ void inv_dct2_dispatch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, int 
   const double2* h = phases(p, L);
   const NodeConst* nc = nodes_of(p, L);
   if (ti == DT::F32C)
-    launch((k_inv_dct2<R, float2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, h, nc);
+    launch((k_inv_dct2<R, float2>), g, dim3(cube_block(p->n, nvol)), 0, st, vs, nvol, p->n, L, h, nc);
   else
-    launch((k_inv_dct2<R, double2>), g, dim3(kBlock), 0, st, vs, nvol, p->n, L, h, nc);
+    launch((k_inv_dct2<R, double2>), g, dim3(cube_block(p->n, nvol)), 0, st, vs, nvol, p->n, L, h, nc);
 }
 template <typename R, bool U>
 void inv_basis_launch(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int nvol, hipStream_t st,
