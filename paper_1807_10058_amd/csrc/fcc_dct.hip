@@ -2049,26 +2049,35 @@ fcc_status fcc_asp_tables(int nl, fcc_level_tables* out) {
 namespace {
 // Built-in schedule: the autotuner's choices on MI355X at n = 64, 128, 256.
 fcc_tuning default_tuning(int n) {
+  // The searches at n = 64, 128 and 256 (fcc_dct_autotune, reps 5), taken
+  // for n <= 64, n = 128 and n >= 256.
+  constexpr unsigned X = FCC_MAP_XCD, FI = FCC_MAP_F_INNER, N8 = FCC_MAP_NODES8, N64 = FCC_MAP_NODES64,
+                     SP = FCC_MAP_SPLIT, X16 = FCC_MAP_XCD16, CL = FCC_MAP_CLUSTER;
+  struct Choice {
+    int tail[2];
+    int tile[2][2][3];  // [direction][level][side]
+    unsigned map[2][10];
+  };
+  static const Choice small = {{1, 1},
+                               {{{1, 2, 3}, {0, 1, 2}}, {{1, 2, 3}, {0, 0, 0}}},
+                               {{SP, SP, SP, SP, SP | N64, SP | N64, SP | N64, SP | N64, SP | N64, SP | N64},
+                                {X, X, X, X, X, N64 | X, N64 | X, N64 | X, N64 | X, N64 | X}}};
+  static const Choice mid = {{1, 1},
+                             {{{2, 2, 2}, {2, 2, 2}}, {{1, 2, 3}, {0, 0, 0}}},
+                             {{SP, SP | X16, SP | N8 | X, SP | N64, SP, SP, SP | N64, SP | N64, SP | N64, SP | N64},
+                              {CL | X, CL | X, N64 | X, X, 0, 0, 0, 0, 0, 0}}};
+  static const Choice large = {{2, 1},
+                               {{{2, 2, 2}, {2, 2, 2}}, {{2, 2, 2}, {0, 0, 0}}},
+                               {{SP, SP | X16 | FI, SP | X16 | N64, SP | N64, SP | X16 | N64, SP | N64, SP | N64,
+                                 SP | N64, SP | N64, SP | N64},
+                                {CL | X, CL | X, N64 | X, N64 | X, 0, 0, X16 | N64, 0, 0, 0}}};
+  const Choice& c = n <= 64 ? small : (n <= 128 ? mid : large);
   fcc_tuning t{};
-  t.tail_levels[0] = n <= 64 ? 1 : 2;
-  t.tail_levels[1] = 1;
-  for (int a = 0; a < 3; ++a) {
-    t.tile[0][0][a] = 2;  // forward level 0: 4x4x4 cube tiles
-    t.tile[0][1][a] = 1;  // forward level 1: 2x2x2
-    t.tile[1][0][a] = 2;  // inverse levels 0 and 1: 4x4x4
-    t.tile[1][1][a] = 2;
-  }
-  // forward: gather and DCT_2 as two passes, groups of 64 nodes from level 2 on
-  for (int L = 0; L < 10; ++L) t.map[0][L] = L < 2 ? FCC_MAP_SPLIT : (FCC_MAP_SPLIT | FCC_MAP_NODES64);
-  // inverse: small n XCD-contiguous (groups of 64 nodes from level 2 on); larger
-  // n the slices in block order with XCD ranges at the top, XCD-contiguous at
-  // levels 2-3
-  if (n <= 64) {
-    t.map[1][0] = t.map[1][1] = FCC_MAP_XCD;
-    for (int L = 2; L < 10; ++L) t.map[1][L] = FCC_MAP_NODES64 | FCC_MAP_XCD;
-  } else {
-    t.map[1][0] = t.map[1][1] = FCC_MAP_CLUSTER | FCC_MAP_XCD;
-    t.map[1][2] = t.map[1][3] = FCC_MAP_XCD;
+  for (int d = 0; d < 2; ++d) {
+    t.tail_levels[d] = c.tail[d];
+    for (int L = 0; L < 2; ++L)
+      for (int a = 0; a < 3; ++a) t.tile[d][L][a] = c.tile[d][L][a];
+    for (int L = 0; L < 10; ++L) t.map[d][L] = c.map[d][L];
   }
   return t;
 }
