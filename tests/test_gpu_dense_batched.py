@@ -110,6 +110,35 @@ def test_ragged_batched_roundtrip_and_graph_replay():
         assert gu.maxrel(outs[i].cpu().numpy()[rows], ref) <= 1e-5
 
 
+def test_ragged_mixed_precision_batch():
+    """The mixed form of the ragged workload in one batched call: n = 8 on the
+    split-BF16 dense path, larger n with the top level in FP32.  Forward
+    against the oracle and round trip within 1e-4, on two graph replays."""
+    ns, xs = workloads.ragged_batch(count=18, seed=4, sizes=(8, 16, 32))
+    plans = {}
+    for n in set(ns):
+        if n <= 8:
+            plans[n] = fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_SPLIT_BF16, flags=fcc.FCC_REAL_INPUT)
+        else:
+            plans[n] = fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP32,
+                                        flags=fcc.FCC_REAL_INPUT | fcc.FCC_LEVEL0_FP32)
+    P = [plans[n] for n in ns]
+    ins = [torch.from_numpy(x).to(gu.DEV) for x in xs]
+    outs = [torch.empty(n ** 3, dtype=torch.complex64, device=gu.DEV) for n in ns]
+    for rep in range(2):
+        for i, x in enumerate(xs):
+            ins[i].copy_(torch.from_numpy(x).to(gu.DEV))
+        fcc.fcc_dct_batched(P, ins, outs, 0)
+        torch.cuda.synchronize()
+        for i, (n, x) in enumerate(zip(ns, xs)):
+            assert gu.maxrel(ins[i].cpu().numpy(), x) <= 1e-4, (rep, i, n)
+    for i in range(0, len(ns), 3):
+        n = ns[i]
+        rows = gu.sample_rows(n, 32, i)
+        ref = oracle.forward_rows(xs[i].astype(np.float64), n, rows)
+        assert gu.maxrel(outs[i].cpu().numpy()[rows], ref) <= 1e-4, (i, n)
+
+
 def test_batched_rejects_bad_arguments():
     plan = fcc.fcc_dct_plan(4, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT)
     x = torch.zeros(64, dtype=torch.float32, device=gu.DEV)

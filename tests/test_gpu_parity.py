@@ -92,6 +92,23 @@ def test_fp32_roundtrip(n):
     assert gu.maxrel(xr, x) <= 1e-5
 
 
+@pytest.mark.parametrize("n", [16, 64])
+def test_level0_fp32_option(n):
+    """FCC_LEVEL0_FP32: the top level in FP32 arithmetic and storage, FP64
+    below.  Rounding at the top level is not amplified by the recursion: the
+    forward stays within the FP32 bound and the round trip within 1e-5."""
+    x = RNG.standard_normal(n ** 3).astype(np.float32)
+    X, _ = gu.forward(x, n, fcc.FCC_PREC_FP32, flags=fcc.FCC_LEVEL0_FP32)
+    if n <= 16:
+        ref = oracle.forward(x.astype(np.float64), n)
+        assert gu.maxrel(X, ref) <= 1e-5
+    else:
+        rows = gu.sample_rows(n, 128, 5)
+        assert gu.maxrel(X[rows], oracle.forward_rows(x.astype(np.float64), n, rows)) <= 1e-5
+    xr = gu.inverse(X.astype(np.complex64), n, fcc.FCC_PREC_FP32, flags=fcc.FCC_LEVEL0_FP32, real_out=True)
+    assert gu.maxrel(xr, x) <= 1e-5
+
+
 def test_error_paths_on_gpu():
     import torch
     n = 4
