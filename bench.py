@@ -11,7 +11,8 @@ Other workloads:
   c3  4096 blocks at n = 8 (8-bit levels / 255), dense split-BF16 MFMA path
       (the FP32 fast path on the same blocks is reported beside it);
   c4  n = 256 trilinear-upsampled field, FP32 data, forward + inverse, with the
-      FP64 round-trip residual computed on the GPU;
+      FP64 round-trip residual computed on the GPU (the variant with the top
+      level in FP32 is reported beside it);
   c5  ragged batch of 512 volumes, n in {8..128}, forward + inverse in one
       graph replay, mixed precision within the workload's 1e-4: n = 8 volumes
       on split-BF16 MFMA, the top level of the others in FP32 (FP64 below);
@@ -228,6 +229,23 @@ def single_volume(args, name):
            "plan_seconds": round(plan_s, 3), "autotune_seconds": round(tune_s, 3), "schedule": sched,
            "wall_seconds_timed": round(wall, 4)}
     extra = {"launches_ms": {s[0]: round(s[2], 5) for s in slots}, "accuracy": acc}
+    if name == "c4":
+        # beside the line: the top level in FP32 (FP64 below), same input
+        p32 = fcc.fcc_dct_plan(n, prec=prec, flags=fcc.FCC_REAL_INPUT | fcc.FCC_LEVEL0_FP32)
+
+        def step32():
+            fcc.fcc_dct_forward(p32, x, X)
+            fcc.fcc_dct_inverse(p32, X, y)
+
+        ms32, _ = time_steps(step32, args.steps, args.warmup)
+        step32()
+        torch.cuda.synchronize()
+        X32 = X.cpu().numpy().astype(np.complex128)
+        extra["variants"] = {"level0_fp32": {
+            "ms_per_step": ms32, "points_per_s": points / (ms32 * 1e-3),
+            "accuracy": {"forward_max_rel_sampled": float(np.abs(X32[rows] - ref).max() / np.abs(ref).max()),
+                         "roundtrip_max_rel_fp64_gpu": fcc.fcc_dct_roundtrip_residual(p32, x, y)}}}
+        fcc.fcc_dct_destroy(p32)
     return points, ms, "f64" if stages64 else "f32", cfg, roof, extra, (x_np, n)
 
 
