@@ -205,9 +205,11 @@ def single_volume(args, name):
     ms, wall = time_steps(step, args.steps, args.warmup)
     points = n ** 3
     slots = []
+    direction_ms = {}
     for d in ([1] if direction == 1 else [1, -1]):
         src, dst = (x, X) if d == 1 else (X, y)
         times = fcc.fcc_dct_time_launches(plan, src, dst, d, reps=max(5, min(args.steps, 50)))
+        direction_ms["forward" if d == 1 else "inverse"] = round(float(sum(times)), 5)
         for (kname, nbytes), t in zip(launch_bytes(n, prec, stages64, True, d, sched), times):
             slots.append((kname, nbytes, t))
     kname, nbytes, tdom = max(slots, key=lambda s: s[2])
@@ -228,7 +230,9 @@ def single_volume(args, name):
            "stages": "f64" if stages64 else "f32", "direction": "forward" if direction == 1 else "forward+inverse",
            "plan_seconds": round(plan_s, 3), "autotune_seconds": round(tune_s, 3), "schedule": sched,
            "wall_seconds_timed": round(wall, 4)}
-    extra = {"launches_ms": {s[0]: round(s[2], 5) for s in slots}, "accuracy": acc}
+    # kernel time of each direction (sum of its launches, HIP events)
+    extra = {"launches_ms": {s[0]: round(s[2], 5) for s in slots}, "direction_kernel_ms": direction_ms,
+             "accuracy": acc}
     if name == "c4":
         # beside the line: the top level in FP32 (FP64 below), same input
         p32 = fcc.fcc_dct_plan(n, prec=prec, flags=fcc.FCC_REAL_INPUT | fcc.FCC_LEVEL0_FP32)
