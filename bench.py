@@ -65,14 +65,19 @@ def launch_bytes(n, prec, stages64, real_in, direction, sched):
     out = []
     if direction > 0:
         Lt = max(0, D - sched["tail_levels"][0])  # levels Lt.. run in one fused LDS launch
+        # the DCT_2 pass of a two-pass level D - 2 runs with the last level
+        last2 = Lt == D - 1 and D >= 3 and bool(sched["map"][0][D - 2] & SPLIT)
         for L in range(Lt):
             bi = rin if L == 0 else st
             if sched["map"][0][L] & SPLIT:
                 out.append(("k_fwd_gather L%d" % L, N * (bi + st)))
-                out.append(("k_fwd_dct2 L%d" % L, N * (st + st)))
+                if not (last2 and L == D - 2):
+                    out.append(("k_fwd_dct2 L%d" % L, N * (st + st)))
             else:
                 out.append(("k_fwd_level L%d" % L, N * (bi + st)))
-        if Lt == D - 1 and D >= 2:  # the last level alone: DCT_2 on the cubes
+        if last2:
+            out.append(("k_fwd_dct2_last2 L%d-%d" % (D - 2, D - 1), N * (st + io_c)))
+        elif Lt == D - 1 and D >= 2:  # the last level alone: DCT_2 on the cubes
             out.append(("k_fwd_dct2 L%d" % (D - 1), N * (st + io_c)))
         else:
             out.append(("k_fwd_tail L%d-%d" % (Lt, D - 1), N * ((rin if Lt == 0 else st) + io_c)))

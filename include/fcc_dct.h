@@ -217,7 +217,9 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
  * average duration in ms of each launch slot to ms[k].
  * Slots in launch order, with Lt = D - tail_levels (at least 0) of the
  * direction: forward = for levels 0..Lt-1 one slot (one-pass level) or two
- * (FCC_MAP_SPLIT: gather pass, DCT_2 pass), then the fused tail; inverse = the fused tail, then (DCT_2^{-1} pass, C gather
+ * (FCC_MAP_SPLIT: gather pass, DCT_2 pass), then the fused tail (with fused depth 1 after
+ * a two-pass level D - 2, n >= 8, that level's DCT_2 pass and the last level are one slot);
+ * inverse = the fused tail, then (DCT_2^{-1} pass, C gather
  * pass) for levels Lt-1 down to 0.  n = 1 and the dense precisions have one
  * slot.  *count receives the number of slots; with ms == NULL only *count is
  * set.

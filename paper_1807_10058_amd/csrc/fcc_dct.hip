@@ -637,6 +637,40 @@ __global__ __launch_bounds__(256) void k_fwd_level(VolSet vs, int nvol, int n, i
                 z);
 }
 
+// y <- DCT_2(phi) y = H_8 A(phi) y for the 8 values of one cube of node J at
+// level L (nodes: the level's node table, or null to form A from the phases).
+template <typename R>
+__device__ __forceinline__ void dct2_apply(const NodeConst* nodes, const double2* __restrict__ hph, int L,
+                                           const int J[3], cx<R> y[8]) {
+  cx<R> tt[8];
+  const int c4[4] = {1, 3, 4, 6}, c3[3] = {2, 5, 7};
+  if (nodes) {
+    const NodeConst& nc = nodes[((long long)J[0] << (2 * L)) | ((long long)J[1] << L) | J[2]];
+    tt[0] = y[0];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      cx<R> s{R(0), R(0)};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) s = s + ldc<R>(nc.a4[4 * i + j]) * y[c4[j]];
+      tt[c4[i]] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      cx<R> s{R(0), R(0)};
+#pragma unroll
+      for (int j = 0; j < 3; ++j) s = s + ldc<R>(nc.a3[3 * i + j]) * y[c3[j]];
+      tt[c3[i]] = s;
+    }
+  } else {
+    cx<R> Q[3][3];
+    node_pos_powers(hph, L, J, Q);
+    apply_A(Q, y, tt);
+  }
+  hadamard8(tt);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) y[i] = tt[i];
+}
+
 // Forward level L, second pass: z = DCT_2(phi) y = H_8 A(phi) y on every cube
 // (may run in place when TO is the stage type).
 template <typename R, typename TO>
@@ -657,33 +691,52 @@ __global__ __launch_bounds__(256) void k_fwd_dct2(VolSet vs, int nvol, int n, in
     pos[i] = gpos(n, L, ci.J, ((i >> 2) & 1) + 2 * ci.a[0], ((i >> 1) & 1) + 2 * ci.a[1], (i & 1) + 2 * ci.a[2]);
     y[i] = in[pos[i]];
   }
-  cx<R> tt[8];
-  const int c4[4] = {1, 3, 4, 6}, c3[3] = {2, 5, 7};
-  if (nodes) {
-    const NodeConst& nc = nodes[((long long)ci.J[0] << (2 * L)) | ((long long)ci.J[1] << L) | ci.J[2]];
-    tt[0] = y[0];
+  dct2_apply(nodes, hph, L, ci.J, y);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      cx<R> s{R(0), R(0)};
+  for (int i = 0; i < 8; ++i) IO<TO, R>::st(out, pos[i], y[i]);
+}
+
+// The DCT_2 pass of level L = D - 2 (node size 4) and the whole last level in
+// one launch.  Lane c of an aligned group of 8 owns cube c of a level-L node J
+// and applies its DCT_2; output i of cube c is value c of child i (node
+// J + 2^L i, a single cube).  The group exchanges the values through LDS, and
+// lane i applies child i's DCT_2 and stores its 8 outputs.  The arithmetic is
+// that of the two separate passes, in the same order.
+template <typename R, typename TO>
+__global__ __launch_bounds__(256) void k_fwd_dct2_last2(VolSet vs, int nvol, int n, int L,
+                                                        const double2* __restrict__ hph0, const NodeConst* nodes0,
+                                                        const double2* __restrict__ hph1, const NodeConst* nodes1) {
+  extern __shared__ unsigned char xch_raw[];
+  cx<R>* xch = reinterpret_cast<cx<R>*>(xch_raw);  // blockDim.x * 8 values
+  const long long h = n >> 1, cubes = h * h * h;     // 8 cubes per level-L node
+  const long long tg = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = tg < cubes * nvol;             // whole groups of 8: cubes is a multiple of 8
+  const long long vol = active ? tg / cubes : 0, t = tg - vol * cubes;
+  const int mask = (1 << L) - 1;
+  const int jf = int(t >> 3), c = int(t & 7);
+  const int J[3] = {jf >> (2 * L), (jf >> L) & mask, jf & mask};
+  cx<R> y[8];
+  if (active) {
+    const cx<R>* in = static_cast<const cx<R>*>(vol_ptr(vs.in, vol));
 #pragma unroll
-      for (int j = 0; j < 4; ++j) s = s + ldc<R>(nc.a4[4 * i + j]) * y[c4[j]];
-      tt[c4[i]] = s;
-    }
+    for (int f = 0; f < 8; ++f)
+      y[f] = in[gpos(n, L, J, ((f >> 2) & 1) + 2 * ((c >> 2) & 1), ((f >> 1) & 1) + 2 * ((c >> 1) & 1),
+                     (f & 1) + 2 * (c & 1))];
+    dct2_apply(nodes0, hph0, L, J, y);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      cx<R> s{R(0), R(0)};
-#pragma unroll
-      for (int j = 0; j < 3; ++j) s = s + ldc<R>(nc.a3[3 * i + j]) * y[c3[j]];
-      tt[c3[i]] = s;
-    }
-  } else {
-    cx<R> Q[3][3];
-    node_pos_powers(hph, L, ci.J, Q);
-    apply_A(Q, y, tt);
+    for (int i = 0; i < 8; ++i) xch[threadIdx.x * 8 + i] = y[i];
   }
-  hadamard8(tt);
+  __syncthreads();
+  if (!active) return;
+  const int base = int(threadIdx.x) & ~7;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) IO<TO, R>::st(out, pos[i], tt[i]);
+  for (int f = 0; f < 8; ++f) y[f] = xch[(base + f) * 8 + c];
+  // child c of node J at level L + 1
+  const int Jc[3] = {J[0] + (((c >> 2) & 1) << L), J[1] + (((c >> 1) & 1) << L), J[2] + ((c & 1) << L)};
+  dct2_apply(nodes1, hph1, L + 1, Jc, y);
+  TO* out = static_cast<TO*>(vol_ptr(vs.out, vol));
+#pragma unroll
+  for (int i = 0; i < 8; ++i) IO<TO, R>::st(out, gpos(n, L + 1, Jc, (i >> 2) & 1, (i >> 1) & 1, i & 1), y[i]);
 }
 
 // Inverse level L, first pass: y = DCT_2(phi)^{-1} z = A(phi)^{-1} H_8 z / 8 on every cube.
@@ -1588,13 +1641,20 @@ void fwd_level_dispatch(const fcc_plan_s* p, int L, DT ti, DT to, const VolSet& 
   }
 }
 bool fwd_split(const fcc_plan_s* p, int L) { return (p->tune.map[0][L] & FCC_MAP_SPLIT) != 0; }
+// The DCT_2 pass of level D - 2 and the last level run as one launch: the
+// last level runs alone (fused depth 1) after a two-pass level D - 2 (D >= 3)
+// in the same arithmetic.
+bool fwd_last2(const fcc_plan_s* p) {
+  return p->D >= 3 && p->tail_Lt[0] == p->D - 1 && fwd_split(p, p->D - 2) &&
+         arith64(p, p->D - 2) == arith64(p, p->D - 1);
+}
 // number of launch slots of one transform in direction d (0 forward, 1 inverse)
 int slot_count(const fcc_plan_s* p, int d) {
   if (p->n == 1 || p->dense) return 1;
   if (d == 1) return 2 * p->tail_Lt[1] + 1;
   int k = 1;
   for (int L = 0; L < p->tail_Lt[0]; ++L) k += fwd_split(p, L) ? 2 : 1;
-  return k;
+  return fwd_last2(p) ? k - 1 : k;
 }
 
 template <typename R>
@@ -1606,6 +1666,20 @@ void fwd_dct2_dispatch(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int 
     launch((k_fwd_dct2<R, float2>), g, dim3(cube_block(p->n, nvol)), 0, st, vs, nvol, p->n, L, h, nc);
   else
     launch((k_fwd_dct2<R, double2>), g, dim3(cube_block(p->n, nvol)), 0, st, vs, nvol, p->n, L, h, nc);
+}
+
+template <typename R>
+void fwd_last2_dispatch(const fcc_plan_s* p, DT to, const VolSet& vs, int nvol, hipStream_t st) {
+  const int L = p->D - 2;
+  const dim3 g = grid_cubes(p->n, nvol);
+  const int b = cube_block(p->n, nvol);
+  const unsigned sh = unsigned(b) * 8u * unsigned(sizeof(cx<R>));
+  if (to == DT::F32C)
+    launch((k_fwd_dct2_last2<R, float2>), g, dim3(b), sh, st, vs, nvol, p->n, L, phases(p, L), nodes_of(p, L),
+           phases(p, L + 1), nodes_of(p, L + 1));
+  else
+    launch((k_fwd_dct2_last2<R, double2>), g, dim3(b), sh, st, vs, nvol, p->n, L, phases(p, L), nodes_of(p, L),
+           phases(p, L + 1), nodes_of(p, L + 1));
 }
 
 template <typename R>
@@ -1763,21 +1837,32 @@ fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
         fwd_level_dispatch<double>(p, L, src_t, to, VolSet{src, a}, nvol, st);
       else
         fwd_level_dispatch<float>(p, L, src_t, to, VolSet{src, a}, nvol, st);
-        } else {
+    } else {
       // pass 1: basis-change gather into a; pass 2: DCT_2 on the cubes of a, in place
       if (arith64(p, L))
         fwd_gather_dispatch<double>(p, L, src_t, VolSet{src, a}, nvol, st);
       else
         fwd_gather_dispatch<float>(p, L, src_t, VolSet{src, a}, nvol, st);
-          if (arith64(p, L))
+      if (L == p->D - 2 && fwd_last2(p)) {
+        // this DCT_2 pass runs with the last level below
+      } else if (arith64(p, L)) {
         fwd_dct2_dispatch<double>(p, L, to, VolSet{a, a}, nvol, st);
-      else
+      } else {
         fwd_dct2_dispatch<float>(p, L, to, VolSet{a, a}, nvol, st);
-        }
+      }
+    }
     src = a;
     src_t = to;
   }
-  // the last level alone (node size 2, B_2 = I): DCT_2 on the cubes
+  // the last level alone (node size 2, B_2 = I): DCT_2 on the cubes, with the
+  // DCT_2 pass of level D - 2 where that level is two-pass
+  if (fwd_last2(p)) {
+    if (arith64(p, p->D - 1))
+      fwd_last2_dispatch<double>(p, cplx_type(p), VolSet{src, out}, nvol, st);
+    else
+      fwd_last2_dispatch<float>(p, cplx_type(p), VolSet{src, out}, nvol, st);
+    return launch_status("forward level launch");
+  }
   if (p->tail_Lt[0] == p->D - 1 && p->D >= 2) {
     if (arith64(p, p->D - 1))
       fwd_dct2_dispatch<double>(p, p->D - 1, cplx_type(p), VolSet{src, out}, nvol, st);
