@@ -83,12 +83,17 @@ def launch_bytes(n, prec, stages64, real_in, direction, sched):
             out.append(("k_fwd_tail L%d-%d" % (Lt, D - 1), N * ((rin if Lt == 0 else st) + io_c)))
     else:
         Lt = max(0, D - sched["tail_levels"][1])
-        if Lt == D - 1 and D >= 2:  # the last level alone: DCT_2^-1 on the cubes
+        # the last level and the DCT_2^-1 pass of level D - 2 run as one launch
+        last2 = Lt == D - 1 and D >= 3
+        if last2:
+            out.append(("k_inv_dct2_last2 L%d-%d" % (D - 1, D - 2), N * (io_c + st)))
+        elif Lt == D - 1 and D >= 2:  # the last level alone: DCT_2^-1 on the cubes
             out.append(("k_inv_dct2 L%d" % (D - 1), N * (io_c + st)))
         else:
             out.append(("k_inv_tail L%d-%d" % (D - 1, Lt), N * (io_c + (rin if Lt == 0 else st))))
         for L in range(Lt - 1, -1, -1):
-            out.append(("k_inv_dct2 L%d" % L, N * (st + st)))
+            if not (last2 and L == D - 2):
+                out.append(("k_inv_dct2 L%d" % L, N * (st + st)))
             bo = rin if L == 0 else st
             out.append(("k_inv_basis L%d" % L, N * (st + bo)))
     return out

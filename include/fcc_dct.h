@@ -220,7 +220,8 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
  * (FCC_MAP_SPLIT: gather pass, DCT_2 pass), then the fused tail (with fused depth 1 after
  * a two-pass level D - 2, n >= 8, that level's DCT_2 pass and the last level are one slot);
  * inverse = the fused tail, then (DCT_2^{-1} pass, C gather
- * pass) for levels Lt-1 down to 0.  n = 1 and the dense precisions have one
+ * pass) for levels Lt-1 down to 0 (with fused depth 1, n >= 8, the last level
+ * and the DCT_2^{-1} pass of level D - 2 are one slot).  n = 1 and the dense precisions have one
  * slot.  *count receives the number of slots; with ms == NULL only *count is
  * set.
  * Errors: FCC_ERR_INVALID_ARG (cap too small, bad pointers or direction),

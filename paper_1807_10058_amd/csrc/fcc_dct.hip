@@ -739,6 +739,39 @@ __global__ __launch_bounds__(256) void k_fwd_dct2_last2(VolSet vs, int nvol, int
   for (int i = 0; i < 8; ++i) IO<TO, R>::st(out, gpos(n, L + 1, Jc, (i >> 2) & 1, (i >> 1) & 1, i & 1), y[i]);
 }
 
+// z <- DCT_2(phi)^{-1} z = A(phi)^{-1} H_8 z / 8 for the 8 values of one cube of
+// node J at level L (4x4 and 3x3 solves with partial pivoting).
+template <typename R>
+__device__ __forceinline__ void idct2_apply(const NodeConst* nodes, const double2* __restrict__ hph, int L,
+                                            const int J[3], cx<R> z[8]) {
+  hadamard8(z);
+  const int c4[4] = {1, 3, 4, 6}, c3[3] = {2, 5, 7};
+  cx<R> a4[4][4], a3[3][3];
+  if (nodes) {
+    const NodeConst& nc = nodes[((long long)J[0] << (2 * L)) | ((long long)J[1] << L) | J[2]];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a4[i / 4][i % 4] = ldc<R>(nc.a4[i]);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) a3[i / 3][i % 3] = ldc<R>(nc.a3[i]);
+  } else {
+    cx<R> Q[3][3];
+    node_pos_powers(hph, L, J, Q);
+    build_A(Q, a4, a3);
+  }
+  cx<R> b4[4], b3[3];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) b4[i] = R(0.125) * z[c4[i]];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) b3[i] = R(0.125) * z[c3[i]];
+  solve_small<R, 4>(a4, b4);
+  solve_small<R, 3>(a3, b3);
+  z[0] = R(0.125) * z[0];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) z[c4[i]] = b4[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) z[c3[i]] = b3[i];
+}
+
 // Inverse level L, first pass: y = DCT_2(phi)^{-1} z = A(phi)^{-1} H_8 z / 8 on every cube.
 template <typename R, typename TI>
 __global__ __launch_bounds__(256) void k_inv_dct2(VolSet vs, int nvol, int n, int L, const double2* __restrict__ hph,
@@ -759,35 +792,51 @@ __global__ __launch_bounds__(256) void k_inv_dct2(VolSet vs, int nvol, int n, in
     pos[i] = gpos(n, L, ci.J, ((i >> 2) & 1) + 2 * ci.a[0], ((i >> 1) & 1) + 2 * ci.a[1], (i & 1) + 2 * ci.a[2]);
     z[i] = IO<TI, R>::ld(in, pos[i]);
   }
-  hadamard8(z);
-  const int c4[4] = {1, 3, 4, 6}, c3[3] = {2, 5, 7};
-  cx<R> y[8];
-  y[0] = R(0.125) * z[0];
-  cx<R> a4[4][4], a3[3][3];
-  if (nodes) {
-    const NodeConst& nc = nodes[((long long)ci.J[0] << (2 * L)) | ((long long)ci.J[1] << L) | ci.J[2]];
+  idct2_apply(nodes, hph, L, ci.J, z);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) a4[i / 4][i % 4] = ldc<R>(nc.a4[i]);
+  for (int i = 0; i < 8; ++i) out[pos[i]] = z[i];
+}
+
+// The whole last level (node size 2) and the DCT_2^{-1} pass of level
+// L = D - 2 in one launch, the mirror of k_fwd_dct2_last2: lane i of an
+// aligned group of 8 inverts child i (node J + 2^L i) of a level-L node J; its
+// value f is output i of cube f of J.  After an exchange through LDS, lane c
+// inverts cube c of J and stores its 8 values (stage type).
+template <typename R, typename TI>
+__global__ __launch_bounds__(256) void k_inv_dct2_last2(VolSet vs, int nvol, int n, int L,
+                                                        const double2* __restrict__ hph0, const NodeConst* nodes0,
+                                                        const double2* __restrict__ hph1, const NodeConst* nodes1) {
+  extern __shared__ unsigned char xch_raw[];
+  cx<R>* xch = reinterpret_cast<cx<R>*>(xch_raw);  // blockDim.x * 8 values
+  const long long h = n >> 1, cubes = h * h * h;     // 8 cubes per level-L node
+  const long long tg = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = tg < cubes * nvol;             // whole groups of 8: cubes is a multiple of 8
+  const long long vol = active ? tg / cubes : 0, t = tg - vol * cubes;
+  const int mask = (1 << L) - 1;
+  const int jf = int(t >> 3), c = int(t & 7);
+  const int J[3] = {jf >> (2 * L), (jf >> L) & mask, jf & mask};
+  cx<R> z[8];
+  if (active) {
+    const TI* in = static_cast<const TI*>(vol_ptr(vs.in, vol));
+    // child c of node J at level L + 1
+    const int Jc[3] = {J[0] + (((c >> 2) & 1) << L), J[1] + (((c >> 1) & 1) << L), J[2] + ((c & 1) << L)};
 #pragma unroll
-    for (int i = 0; i < 9; ++i) a3[i / 3][i % 3] = ldc<R>(nc.a3[i]);
-  } else {
-    cx<R> Q[3][3];
-    node_pos_powers(hph, L, ci.J, Q);
-    build_A(Q, a4, a3);
+    for (int i = 0; i < 8; ++i) z[i] = IO<TI, R>::ld(in, gpos(n, L + 1, Jc, (i >> 2) & 1, (i >> 1) & 1, i & 1));
+    idct2_apply(nodes1, hph1, L + 1, Jc, z);
+#pragma unroll
+    for (int f = 0; f < 8; ++f) xch[threadIdx.x * 8 + f] = z[f];
   }
-  cx<R> b4[4], b3[3];
+  __syncthreads();
+  if (!active) return;
+  const int base = int(threadIdx.x) & ~7;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) b4[i] = R(0.125) * z[c4[i]];
+  for (int i = 0; i < 8; ++i) z[i] = xch[(base + i) * 8 + c];
+  idct2_apply(nodes0, hph0, L, J, z);
+  cx<R>* out = static_cast<cx<R>*>(vol_ptr(vs.out, vol));
 #pragma unroll
-  for (int i = 0; i < 3; ++i) b3[i] = R(0.125) * z[c3[i]];
-  solve_small<R, 4>(a4, b4);
-  solve_small<R, 3>(a3, b3);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) y[c4[i]] = b4[i];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) y[c3[i]] = b3[i];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) out[pos[i]] = y[i];
+  for (int f = 0; f < 8; ++f)
+    out[gpos(n, L, J, ((f >> 2) & 1) + 2 * ((c >> 2) & 1), ((f >> 1) & 1) + 2 * ((c >> 1) & 1), (f & 1) + 2 * (c & 1))] =
+        z[f];
 }
 
 // Inverse level L, second pass: x(kappa) = sum C_nl(phi)[kappa, (def,abc)] y(def + 2 abc),
@@ -1648,10 +1697,16 @@ bool fwd_last2(const fcc_plan_s* p) {
   return p->D >= 3 && p->tail_Lt[0] == p->D - 1 && fwd_split(p, p->D - 2) &&
          arith64(p, p->D - 2) == arith64(p, p->D - 1);
 }
+// The inverse counterpart: the last level alone, then the DCT_2^{-1} pass of
+// level D - 2, as one launch.
+bool inv_last2(const fcc_plan_s* p) {
+  return p->D >= 3 && p->tail_Lt[1] == p->D - 1 && buf_type(p, p->D - 1) == stage_type(p) &&
+         arith64(p, p->D - 2) == arith64(p, p->D - 1);
+}
 // number of launch slots of one transform in direction d (0 forward, 1 inverse)
 int slot_count(const fcc_plan_s* p, int d) {
   if (p->n == 1 || p->dense) return 1;
-  if (d == 1) return 2 * p->tail_Lt[1] + 1;
+  if (d == 1) return 2 * p->tail_Lt[1] + 1 - (inv_last2(p) ? 1 : 0);
   int k = 1;
   for (int L = 0; L < p->tail_Lt[0]; ++L) k += fwd_split(p, L) ? 2 : 1;
   return fwd_last2(p) ? k - 1 : k;
@@ -1679,6 +1734,20 @@ void fwd_last2_dispatch(const fcc_plan_s* p, DT to, const VolSet& vs, int nvol, 
            phases(p, L + 1), nodes_of(p, L + 1));
   else
     launch((k_fwd_dct2_last2<R, double2>), g, dim3(b), sh, st, vs, nvol, p->n, L, phases(p, L), nodes_of(p, L),
+           phases(p, L + 1), nodes_of(p, L + 1));
+}
+
+template <typename R>
+void inv_last2_dispatch(const fcc_plan_s* p, DT ti, const VolSet& vs, int nvol, hipStream_t st) {
+  const int L = p->D - 2;
+  const dim3 g = grid_cubes(p->n, nvol);
+  const int b = cube_block(p->n, nvol);
+  const unsigned sh = unsigned(b) * 8u * unsigned(sizeof(cx<R>));
+  if (ti == DT::F32C)
+    launch((k_inv_dct2_last2<R, float2>), g, dim3(b), sh, st, vs, nvol, p->n, L, phases(p, L), nodes_of(p, L),
+           phases(p, L + 1), nodes_of(p, L + 1));
+  else
+    launch((k_inv_dct2_last2<R, double2>), g, dim3(b), sh, st, vs, nvol, p->n, L, phases(p, L), nodes_of(p, L),
            phases(p, L + 1), nodes_of(p, L + 1));
 }
 
@@ -1888,7 +1957,14 @@ fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
   // the last level alone (node size 2, C_2 = I): DCT_2^{-1} on the cubes
   // (its output type is the stage type of level D-1)
   const bool last_only = p->tail_Lt[1] == p->D - 1 && p->D >= 2 && buf_type(p, p->D - 1) == stage_type(p);
-  if (last_only) {
+  if (inv_last2(p)) {
+    // with the DCT_2^{-1} pass of level D - 2 (its result lands in ws0, where
+    // that pass would have written it)
+    if (arith64(p, p->D - 1))
+      inv_last2_dispatch<double>(p, cplx_type(p), VolSet{in, ws0}, nvol, st);
+    else
+      inv_last2_dispatch<float>(p, cplx_type(p), VolSet{in, ws0}, nvol, st);
+  } else if (last_only) {
     if (arith64(p, p->D - 1))
       inv_dct2_dispatch<double>(p, p->D - 1, cplx_type(p), VolSet{in, ws0}, nvol, st);
     else
@@ -1912,17 +1988,20 @@ fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
     // the DCT_2^{-1} pass reads level L+1's result (or the user's X) and
     // writes level L's cube values in level L's arithmetic type
     DT ti = cur_is_user ? cplx_type(p) : buf_type(p, L + 1);
-    if (arith64(p, L))
+    if (L == p->D - 2 && inv_last2(p)) {
+      // done with the last level above
+    } else if (arith64(p, L)) {
       inv_dct2_dispatch<double>(p, L, ti, VolSet{cur, a}, nvol, st);
-    else
+    } else {
       inv_dct2_dispatch<float>(p, L, ti, VolSet{cur, a}, nvol, st);
-      VolPtrs dst = L == 0 ? out : b;
+    }
+    VolPtrs dst = L == 0 ? out : b;
     DT to = L == 0 ? real_or_cplx : buf_type(p, L);
     if (arith64(p, L))
       inv_basis_dispatch<double>(p, L, to, VolSet{a, dst}, nvol, st);
     else
       inv_basis_dispatch<float>(p, L, to, VolSet{a, dst}, nvol, st);
-      cur = b;
+    cur = b;
     cur_is_user = false;
     which ^= 1;
   }
@@ -2550,7 +2629,7 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
       // 2. tile shape and thread map of the level-0 and level-1 gather
       // passes, by the time of that level's launches
       auto level_ms = [&](int L) {
-        if (d == 1) return double(ms[2 * (p->tail_Lt[1] - L)]);  // the C gather pass
+        if (d == 1) return double(ms[2 * (p->tail_Lt[1] - L) - (inv_last2(p) ? 1 : 0)]);  // the C gather pass
         int k = 0;
         for (int l = 0; l < L; ++l) k += fwd_split(p, l) ? 2 : 1;
         return double(ms[k]) + (fwd_split(p, L) ? double(ms[k + 1]) : 0.0);
