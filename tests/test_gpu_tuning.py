@@ -144,3 +144,25 @@ def test_batched_groups_respect_schedules():
     torch.cuda.synchronize()
     for x, X in zip(xs, outs):
         assert gu.maxrel(X.cpu().numpy(), oracle.forward(x.astype(np.float64), n)) <= 1e-5
+
+
+@pytest.mark.parametrize("n", [8, 16, 64])
+@pytest.mark.parametrize("tail", [(1, 1), (2, 1), (3, 3)])
+@pytest.mark.parametrize("split", [True, False])
+def test_launch_slots_match_the_bench_accounting(n, tail, split):
+    """The launch slots fcc_dct_time_launches reports (including the fused
+    last-level launches) are the ones bench.py prices, in number and order."""
+    import bench
+    maps = (SP, SP, 0, 0) if split else (0, 0, 0, 0)
+    t = tuning(tail=tail, maps=maps, deep=(SP if split else 0, 0))
+    plan = fcc.fcc_dct_plan_tuned(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT, tuning=t)
+    sched = fcc.fcc_dct_get_tuning(plan)
+    x = torch.rand(n ** 3, device=gu.DEV)
+    X = torch.empty(n ** 3, dtype=torch.complex64, device=gu.DEV)
+    y = torch.empty(n ** 3, device=gu.DEV)
+    for d, (src, dst) in ((1, (x, X)), (-1, (X, y))):
+        ms = fcc.fcc_dct_time_launches(plan, src, dst, d, reps=1)
+        slots = bench.launch_bytes(n, fcc.FCC_PREC_FP32, True, True, d, sched)
+        assert len(ms) == len(slots), (n, tail, split, d, [s[0] for s in slots])
+        assert all(v > 0 for v in ms)
+    fcc.fcc_dct_destroy(plan)
