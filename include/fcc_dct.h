@@ -273,6 +273,47 @@ typedef struct {
 
 fcc_status fcc_asp_tables(int nl, fcc_level_tables* out);
 
+/* Orbit-block form of the same basis change (node size nl = 2m, 4 <= nl <= 1024).
+ * Let W act on the cube grid [0,m)^3 by q -> (g q) mod m.  For each orbit O,
+ * the B_nl rows (def, q), q in O, read exactly the sources kappa = q' + m o
+ * (q' in O, o in {0,1}^3), and no other rows read them; C_nl = B_nl^{-1} has
+ * the same blocks.  Labelled relative to its representative p0 (the orbit's
+ * smallest cube index), a block's matrix depends only on the orbit's kind,
+ * so a level is described by a few templates and the representatives of
+ * each kind:
+ *   template t: cube slot j < nc is the cube q_j = (G[w[j]] p0) mod m;
+ *     B row j*8 + def gives the coordinate stored at position def + 2 q_j, with
+ *       entries (s << 8) | poly reading the source q_{s/8} + m o, o = s % 8
+ *       as (o>>2, (o>>1)&1, o&1);
+ *     C row s = j'*8 + o gives x at q_{j'} + m o, with entries (j*8 + def) << 8 | poly
+ *       reading position def + 2 q_j;
+ *   rep[i]: representative p0 packed (x << 20) | (y << 10) | z, Morton order.
+ *   poly p: coefficients poly[5p + q] of the monomials 1, c3, c1, c2, c1 c3 of
+ *     c = (sigma, tau, rho)(node); ids below nconst are constants.
+ *   group: the 24 matrices G[w] of W, row-major 3x3 integers.
+ * Templates are read off the derived tables of one small node size and the
+ * orbits of nl are classified into them (Sec. IV-B, B_n; see the tests).
+ * Pointers stay valid until the process ends.  Errors: FCC_ERR_NOT_POW2 for a
+ * bad nl, FCC_ERR_UNSUPPORTED if an orbit matches no template, FCC_ERR_OOM. */
+typedef struct {
+  int nc;
+  const int* w;
+  const int* b_rowptr;          /* 8 nc + 1 */
+  const unsigned short* b_ent;
+  const int* c_rowptr;          /* 8 nc + 1 */
+  const unsigned short* c_ent;
+  int nrep;
+  const unsigned* rep;
+} fcc_orbit_template;
+typedef struct {
+  int nl, m, npoly, nconst, ntempl;
+  const double* poly;
+  const int* group;
+  fcc_orbit_template templ[16];
+} fcc_orbit_blocks;
+
+fcc_status fcc_asp_orbit_blocks(int nl, fcc_orbit_blocks* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,6 +36,19 @@ class _LevelTables(ctypes.Structure):
                 ("cube_block", ctypes.POINTER(ctypes.c_int)), ("kappa_block", ctypes.POINTER(ctypes.c_int))]
 
 
+class _OrbitTemplate(ctypes.Structure):
+    _fields_ = [("nc", ctypes.c_int), ("w", ctypes.POINTER(ctypes.c_int)),
+                ("b_rowptr", ctypes.POINTER(ctypes.c_int)), ("b_ent", ctypes.POINTER(ctypes.c_ushort)),
+                ("c_rowptr", ctypes.POINTER(ctypes.c_int)), ("c_ent", ctypes.POINTER(ctypes.c_ushort)),
+                ("nrep", ctypes.c_int), ("rep", ctypes.POINTER(ctypes.c_uint))]
+
+
+class _OrbitBlocks(ctypes.Structure):
+    _fields_ = [("nl", ctypes.c_int), ("m", ctypes.c_int), ("npoly", ctypes.c_int), ("nconst", ctypes.c_int),
+                ("ntempl", ctypes.c_int), ("poly", ctypes.POINTER(ctypes.c_double)),
+                ("group", ctypes.POINTER(ctypes.c_int)), ("templ", _OrbitTemplate * 16)]
+
+
 class _Tuning(ctypes.Structure):
     _fields_ = [("tail_levels", ctypes.c_int * 2), ("tile", ((ctypes.c_int * 3) * 2) * 2),
                 ("map", (ctypes.c_uint * _MAX_LEVELS) * 2)]
@@ -79,8 +92,9 @@ _lib.fcc_dct_time_launches.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int
 _lib.fcc_status_string.argtypes = [ctypes.c_int]
 _lib.fcc_status_string.restype = ctypes.c_char_p
 _lib.fcc_asp_tables.argtypes = [ctypes.c_int, ctypes.POINTER(_LevelTables)]
+_lib.fcc_asp_orbit_blocks.argtypes = [ctypes.c_int, ctypes.POINTER(_OrbitBlocks)]
 for _f in ("fcc_dct_plan", "fcc_dct_plan_tuned", "fcc_dct_get_tuning", "fcc_dct_autotune", "fcc_dct_forward", "fcc_dct_inverse", "fcc_dct_batched", "fcc_dct_destroy",
-           "fcc_asp_tables", "fcc_dct_time_launches", "fcc_dct_roundtrip_residual"):
+           "fcc_asp_tables", "fcc_asp_orbit_blocks", "fcc_dct_time_launches", "fcc_dct_roundtrip_residual"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -250,4 +264,27 @@ def fcc_asp_tables(nl):
         out[side + "_pid"] = arr(getattr(t, side + "_pid"), int(rp[-1]), np.int64)
     out["cube_block"] = arr(t.cube_block, t.m ** 3, np.int64)
     out["kappa_block"] = arr(t.kappa_block, t.nl ** 3, np.int64)
+    return out
+
+
+def fcc_asp_orbit_blocks(nl):
+    """Host copies of the orbit-block templates and representatives for node size nl."""
+    b = _OrbitBlocks()
+    _check(_lib.fcc_asp_orbit_blocks(int(nl), ctypes.byref(b)), "fcc_asp_orbit_blocks")
+
+    def arr(p, k, dt):
+        return np.ctypeslib.as_array(p, shape=(k,)).astype(dt).copy() if k else np.zeros(0, dt)
+
+    out = {"nl": b.nl, "m": b.m, "npoly": b.npoly, "nconst": b.nconst,
+           "poly": arr(b.poly, 5 * b.npoly, np.float64).reshape(b.npoly, 5),
+           "group": arr(b.group, 24 * 9, np.int64).reshape(24, 3, 3), "templ": []}
+    for t in range(b.ntempl):
+        T = b.templ[t]
+        nc = T.nc
+        brp = arr(T.b_rowptr, 8 * nc + 1, np.int64)
+        crp = arr(T.c_rowptr, 8 * nc + 1, np.int64)
+        out["templ"].append({"nc": nc, "w": arr(T.w, nc, np.int64),
+                             "b_rowptr": brp, "b_ent": arr(T.b_ent, int(brp[-1]), np.int64),
+                             "c_rowptr": crp, "c_ent": arr(T.c_ent, int(crp[-1]), np.int64),
+                             "rep": arr(T.rep, T.nrep, np.int64)})
     return out

@@ -20,6 +20,7 @@
 #include "asp_tables.hpp"
 #include "fcc_dct.h"
 #include "kernels.hpp"
+#include "orbit_blocks.hpp"
 #include "orbits.inc"
 #include "plan.hpp"
 
@@ -2205,6 +2206,40 @@ fcc_status fcc_asp_tables(int nl, fcc_level_tables* out) {
   if (!gb) return FCC_ERR_OOM;
   out->cube_block = gb->cube.data();
   out->kappa_block = gb->kappa.data();
+  return FCC_OK;
+}
+
+fcc_status fcc_asp_orbit_blocks(int nl, fcc_orbit_blocks* out) {
+  if (!out) return FCC_ERR_INVALID_ARG;
+  if (nl < 4 || !is_pow2(nl)) return FCC_ERR_NOT_POW2;
+  const OrbitBlocks* B = orbit_blocks(nl);
+  if (!B) return FCC_ERR_UNSUPPORTED;
+  if (B->templ.size() > sizeof out->templ / sizeof out->templ[0]) return FCC_ERR_UNSUPPORTED;
+  static const std::vector<int> group = [] {
+    std::vector<int> g;
+    for (const auto& w : weyl_group()) g.insert(g.end(), w.begin(), w.end());
+    return g;
+  }();
+  *out = fcc_orbit_blocks{};
+  out->nl = B->nl;
+  out->m = B->m;
+  out->npoly = B->npoly;
+  out->nconst = B->nconst;
+  out->ntempl = int(B->templ.size());
+  out->poly = B->poly.data();
+  out->group = group.data();
+  for (size_t t = 0; t < B->templ.size(); ++t) {
+    const OrbitTemplate& T = B->templ[t];
+    fcc_orbit_template& o = out->templ[t];
+    o.nc = T.nc;
+    o.w = T.w.data();
+    o.b_rowptr = T.b_rowptr.data();
+    o.b_ent = T.b_ent.data();
+    o.c_rowptr = T.c_rowptr.data();
+    o.c_ent = T.c_ent.data();
+    o.nrep = int(B->reps[t].size());
+    o.rep = B->reps[t].data();
+  }
   return FCC_OK;
 }
 
