@@ -98,6 +98,25 @@ fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precis
  *   x : n^3 reals (FCC_REAL_INPUT) or complex; X : n^3 complex. */
 fcc_status fcc_dct_forward(fcc_plan_t plan, const void* x, void* X, void* hip_stream);
 
+/* fcc_dct_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and result bits, but the two scratch buffers come from a
+ * static device array of 8 MiB per device instead of the plan's buffers, and
+ * the call makes no allocation of any kind.
+ *   plan : a plan made on the current device (its set-up looked up the
+ *          array's address on that device).
+ *   x, X : as for fcc_dct_forward (device pointers, 16-byte aligned, disjoint).
+ * Limit: 2 n^3 stage-precision complex values must fit in 8 MiB, i.e.
+ * n <= 64 (FP64 or FP32 stages); larger n returns FCC_ERR_UNSUPPORTED.  Dense
+ * (split-MFMA) plans keep their per-row scale there too.
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents (no call needs it cleared): calls that overlap in time on one
+ * device (two streams, two threads) race and give wrong results.
+ * Errors: FCC_ERR_INVALID_ARG (null or misaligned pointers, current device is
+ * not the plan's), FCC_ERR_UNSUPPORTED (in place, n above the limit),
+ * FCC_ERR_HIP (the array's address could not be looked up). */
+fcc_status fcc_dct_forward_static(fcc_plan_t plan, const void* x, void* X, void* hip_stream);
+
 /* x = DCT_n(r,s,t)^{-1} X: the factors of eq. FastAlgorithm inverted in reverse
  * order (P_n^T, inverse skew sub-transforms, DCT_2^{-1} (x) I, then the
  * product expansion C_n = B_n^{-1}).

@@ -83,6 +83,7 @@ _lib.fcc_dct_autotune.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                   ctypes.c_int, ctypes.POINTER(_Tuning), _vp]
 _lib.fcc_dct_forward.argtypes = [_vp, _vp, _vp, _vp]
 _lib.fcc_dct_inverse.argtypes = [_vp, _vp, _vp, _vp]
+_lib.fcc_dct_forward_static.argtypes = [_vp, _vp, _vp, _vp]
 _lib.fcc_dct_batched.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                  ctypes.c_int, _vp]
 _lib.fcc_dct_destroy.argtypes = [_vp]
@@ -93,7 +94,7 @@ _lib.fcc_status_string.argtypes = [ctypes.c_int]
 _lib.fcc_status_string.restype = ctypes.c_char_p
 _lib.fcc_asp_tables.argtypes = [ctypes.c_int, ctypes.POINTER(_LevelTables)]
 _lib.fcc_asp_orbit_blocks.argtypes = [ctypes.c_int, ctypes.POINTER(_OrbitBlocks)]
-for _f in ("fcc_dct_plan", "fcc_dct_plan_tuned", "fcc_dct_get_tuning", "fcc_dct_autotune", "fcc_dct_forward", "fcc_dct_inverse", "fcc_dct_batched", "fcc_dct_destroy",
+for _f in ("fcc_dct_plan", "fcc_dct_plan_tuned", "fcc_dct_get_tuning", "fcc_dct_autotune", "fcc_dct_forward", "fcc_dct_forward_static", "fcc_dct_inverse", "fcc_dct_batched", "fcc_dct_destroy",
            "fcc_asp_tables", "fcc_asp_orbit_blocks", "fcc_dct_time_launches", "fcc_dct_roundtrip_residual"):
     getattr(_lib, _f).restype = ctypes.c_int
 
@@ -193,6 +194,11 @@ def _torch_cuda():
 
 def fcc_dct_forward(plan, x, X, stream=None):
     _check(_lib.fcc_dct_forward(plan.handle, _ptr(x), _ptr(X), _stream(stream)), "fcc_dct_forward")
+
+
+def fcc_dct_forward_static(plan, x, X, stream=None):
+    """fcc_dct_forward with scratch in the library's static device array (no allocation; n <= 64)."""
+    _check(_lib.fcc_dct_forward_static(plan.handle, _ptr(x), _ptr(X), _stream(stream)), "fcc_dct_forward_static")
 
 
 def fcc_dct_inverse(plan, X, x, stream=None):

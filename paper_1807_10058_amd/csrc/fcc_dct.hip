@@ -2246,6 +2246,7 @@ fcc_status fcc_asp_orbit_blocks(int nl, fcc_orbit_blocks* out) {
 }  // extern "C"
 
 namespace {
+void lookup_static_scratch(int dev);  // allocation-free entry point (below)
 // Built-in schedule: the autotuner's choices on MI355X at n = 64, 128, 256.
 fcc_tuning default_tuning(int n) {
   // The searches at n = 64, 128 and 256 (fcc_dct_autotune, reps 5), taken
@@ -2385,6 +2386,7 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
       return hip_fail(e, "hipGetDevice", __LINE__);
     }
   }
+  lookup_static_scratch(p->device);
   if (tuning) {
     resolve_tuning(p, *tuning);
   } else {
@@ -2526,6 +2528,60 @@ fcc_status fcc_dct_forward(fcc_plan_t p, const void* x, void* X, void* hip_strea
     return dense_run(p, p->dfwd, 1, nullptr, nullptr, x, X, p->rowscale, static_cast<hipStream_t>(hip_stream));
   return enqueue_forward(p, 1, one_vol(x), one_vol(X), one_vol(p->ws[0]), one_vol(p->ws[1]),
                          static_cast<hipStream_t>(hip_stream));
+}
+
+}  // extern "C"
+
+// ---- allocation-free forward: scratch in a static device array -------------
+namespace {
+// The two ping-pong buffers of fcc_dct_forward_static live in this array, one
+// copy per device.  Host code never names it directly (the name is a host-side
+// stand-in, not a device address): its address on each device is looked up
+// once, with that device current, and kept in scratch_addr.
+constexpr size_t kStaticScratchBytes = size_t(8) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex scratch_mu;
+void* scratch_addr[kMaxDevices] = {};
+hipError_t scratch_err[kMaxDevices] = {};
+bool scratch_tried[kMaxDevices] = {};
+
+// Called at plan set-up with the plan's device current.
+void lookup_static_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_tried[dev]) return;
+  scratch_tried[dev] = true;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  scratch_err[dev] = e;
+  if (e == hipSuccess) scratch_addr[dev] = ptr;
+}
+void* static_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  return scratch_addr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+fcc_status fcc_dct_forward_static(fcc_plan_t p, const void* x, void* X, void* hip_stream) {
+  if (!p || !x || !X || !aligned16(x) || !aligned16(X)) return FCC_ERR_INVALID_ARG;
+  if (x == X) return FCC_ERR_UNSUPPORTED;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device) return FCC_ERR_INVALID_ARG;
+  (void)hipGetLastError();
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  char* base = static_cast<char*>(static_scratch(p->device));
+  if (!base) return FCC_ERR_HIP;
+  // dense path: its per-row input scale (one float) in the array
+  if (p->dense) return dense_run(p, p->dfwd, 1, nullptr, nullptr, x, X, reinterpret_cast<float*>(base), st);
+  const size_t half = size_t(p->n) * p->n * p->n * (p->stages64 ? sizeof(double2) : sizeof(float2));
+  // the two buffers, each 256-byte aligned
+  const size_t stride = (half + 255) & ~size_t(255);
+  if (2 * stride > kStaticScratchBytes) return FCC_ERR_UNSUPPORTED;
+  return enqueue_forward(p, 1, one_vol(x), one_vol(X), one_vol(base), one_vol(base + stride), st);
 }
 
 fcc_status fcc_dct_inverse(fcc_plan_t p, const void* X, void* x, void* hip_stream) {
