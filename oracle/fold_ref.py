@@ -11,6 +11,11 @@ two sums: with lambda = g k,
 i.e. a twiddled fold onto the n-torus followed by an unnormalised inverse
 3-D DFT.  It shares nothing with the direct oracle except the group, which it
 rebuilds itself, and is checked against the direct oracle at small n.
+
+The inverse runs the two steps backwards: Fh = DFT(X) / n^3, then x = Fold^{-1}
+Fh.  Fold only moves k inside its orbit under W acting on the n-torus
+(g k mod n), so Fold is block diagonal over those orbits (at most 24 points
+each) and every block is solved on its own.
 """
 import numpy as np
 
@@ -34,14 +39,80 @@ def _group():
     return out
 
 
+def _grid(n):
+    return np.stack(np.meshgrid(*([np.arange(n, dtype=np.int64)] * 3), indexing="ij"), -1).reshape(-1, 3)
+
+
+def _flat(v, n):
+    return (v[..., 0] * n + v[..., 1]) * n + v[..., 2]
+
+
 def fold_forward(x, n, rst=DEFAULT_RST):
     rst = np.asarray(rst, dtype=np.float64)
     x = np.asarray(x, dtype=np.complex128).reshape(-1)
-    k = np.stack(np.meshgrid(*([np.arange(n)] * 3), indexing="ij"), -1).reshape(-1, 3)
-    Fh = np.zeros((n, n, n), dtype=np.complex128)
+    k = _grid(n)
+    N = n ** 3
+    re = np.zeros(N)
+    im = np.zeros(N)
     for g in _group():
         lam = k @ g.T
-        tw = np.exp(2j * np.pi * (lam @ rst) / n)
-        mu = np.mod(lam, n)
-        np.add.at(Fh, (mu[:, 0], mu[:, 1], mu[:, 2]), x * tw / 24.0)
-    return (np.fft.ifftn(Fh) * n ** 3).reshape(-1)
+        v = x * np.exp(2j * np.pi * (lam @ rst) / n) / 24.0
+        mu = _flat(np.mod(lam, n), n)
+        re += np.bincount(mu, weights=v.real, minlength=N)
+        im += np.bincount(mu, weights=v.imag, minlength=N)
+    Fh = (re + 1j * im).reshape(n, n, n)
+    return (np.fft.ifftn(Fh) * N).reshape(-1)
+
+
+def torus_orbits(n):
+    """Orbits of W on the n-torus: for every point its orbit's smallest flat
+    index, and the points sorted by (orbit, flat index)."""
+    k = _grid(n)
+    rep = _flat(k, n)
+    for g in _group():
+        rep = np.minimum(rep, _flat(np.mod(k @ g.T, n), n))
+    order = np.lexsort((np.arange(n ** 3), rep))
+    return rep, order
+
+
+def fold_inverse(X, n, rst=DEFAULT_RST, points=None):
+    """x = DCT_n(rst)^{-1} X through Fh = DFT(X)/n^3 and per-orbit solves of
+    Fold x = Fh.  With `points` (flat indices), only the orbits holding them
+    are solved and x is returned at those points."""
+    rst = np.asarray(rst, dtype=np.float64)
+    N = n ** 3
+    Fh = (np.fft.fftn(np.asarray(X, dtype=np.complex128).reshape(n, n, n)) / N).reshape(-1)
+    rep, order = torus_orbits(n)
+    srep = rep[order]
+    starts = np.flatnonzero(np.r_[True, srep[1:] != srep[:-1]])
+    sizes = np.diff(np.r_[starts, N])
+    local = np.empty(N, dtype=np.int64)
+    local[order] = np.arange(N) - np.repeat(starts, sizes)
+    orbit_of = np.empty(N, dtype=np.int64)
+    orbit_of[order] = np.repeat(np.arange(len(starts)), sizes)
+    wanted = np.ones(len(starts), dtype=bool)
+    if points is not None:
+        wanted[:] = False
+        wanted[orbit_of[np.asarray(points)]] = True
+    x = np.zeros(N, dtype=np.complex128)
+    G = _group()
+    for s in np.unique(sizes):
+        ids = np.flatnonzero((sizes == s) & wanted)
+        for c0 in range(0, len(ids), 50000):
+            oid = ids[c0:c0 + 50000]
+            mem = order[(starts[oid][:, None] + np.arange(s)[None, :]).reshape(-1)]  # members, orbit-major
+            kv = np.stack([mem // (n * n), (mem // n) % n, mem % n], -1)
+            blk = np.repeat(np.arange(len(oid)), s)
+            re = np.zeros(len(oid) * s * s)
+            im = np.zeros(len(oid) * s * s)
+            for g in G:
+                lam = kv @ g.T
+                w = np.exp(2j * np.pi * (lam @ rst) / n) / 24.0
+                row = local[_flat(np.mod(lam, n), n)]
+                idx = (blk * s + row) * s + local[mem]
+                re += np.bincount(idx, weights=w.real, minlength=re.size)
+                im += np.bincount(idx, weights=w.imag, minlength=im.size)
+            A = (re + 1j * im).reshape(len(oid), s, s)
+            rhs = Fh[mem].reshape(len(oid), s, 1)
+            x[mem] = np.linalg.solve(A, rhs).reshape(-1)
+    return x if points is None else x[np.asarray(points)]

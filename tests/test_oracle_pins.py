@@ -217,3 +217,43 @@ def test_invertible_and_roundtrip(n):
     X = RNG.standard_normal(n ** 3) + 1j * RNG.standard_normal(n ** 3)
     x = oracle.inverse(X, n)
     assert np.abs(oracle.forward(x, n) - X).max() <= 1e-12 * np.abs(X).max()
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8])
+@pytest.mark.parametrize("rst", [(1 / 8, 0, 3 / 8), (0.31, 0.07, 0.23)])
+def test_fold_inverse_matches_dense_inverse(n, rst):
+    """The fold inverse (DFT, then per-orbit solves of the fold) equals the
+    oracle's dense LU inverse of the explicit matrix (Sec. IV-A, Lemma 2)."""
+    X = RNG.standard_normal(n ** 3) + 1j * RNG.standard_normal(n ** 3)
+    x = oracle.inverse(X, n, rst)
+    y = fold_ref.fold_inverse(X, n, rst)
+    assert np.abs(x - y).max() <= 1e-12 * np.abs(x).max()
+
+
+def test_fold_inverse_orbits_partition_the_torus():
+    """The blocks of the fold are the orbits of W on the n-torus: every point
+    lies in one, g k mod n stays in its orbit, and no orbit has more than 24 points."""
+    n = 16
+    rep, order = fold_ref.torus_orbits(n)
+    k = np.stack(np.meshgrid(*([np.arange(n)] * 3), indexing="ij"), -1).reshape(-1, 3)
+    for g in oracle.group():
+        img = np.mod(k @ g.T, n)
+        assert np.array_equal(rep[(img[:, 0] * n + img[:, 1]) * n + img[:, 2]], rep)
+    assert np.bincount(np.unique(rep, return_counts=True)[1]).nonzero()[0].max() <= 24
+    assert np.array_equal(np.sort(order), np.arange(n ** 3))
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_fold_inverse_undoes_the_direct_forward(n):
+    """fold_inverse(forward(x)) = x, with forward from the direct sum at n = 16
+    and from sampled direct rows plus the fold at n = 32; sampled points alone
+    give the same values as the full solve."""
+    x = RNG.standard_normal(n ** 3)
+    X = oracle.forward(x, n) if n == 16 else fold_ref.fold_forward(x, n)
+    if n == 32:
+        rows = RNG.choice(n ** 3, 16, replace=False)
+        assert np.abs(oracle.forward_rows(x, n, rows) - X[rows]).max() <= 1e-12 * np.abs(X).max()
+    y = fold_ref.fold_inverse(X, n)
+    assert np.abs(y - x).max() <= 1e-12 * np.abs(x).max()
+    pts = RNG.choice(n ** 3, 40, replace=False)
+    assert np.array_equal(fold_ref.fold_inverse(X, n, points=pts), y[pts])
