@@ -128,12 +128,22 @@ fcc_status fcc_dct_inverse(fcc_plan_t plan, const void* X, void* x, void* hip_st
  *   -1 inverse (in -> out), 0 forward then inverse (in -> out, then out -> in,
  *   overwriting in[i] with the round trip).
  * The first call with a given (plans, pointers, direction) records the launch
- * sequence into a HIP graph; later identical calls replay it.  Volumes with
- * the same plan configuration share each level launch.
+ * sequence into a HIP graph; later identical calls replay it (at most 4
+ * recorded graphs are kept, least recently used freed first; see
+ * fcc_dct_batched_release).  Volumes with the same plan configuration form a
+ * group and share each level launch, in chunks of up to 2^25 points that
+ * reuse one scratch pair; groups run on up to 4 concurrent branches of the
+ * graph.  Calls that overlap in time must not pass the same buffers.
  * Errors: FCC_ERR_INVALID_ARG (count < 1, null entries, direction), plus the
  * errors of the single-volume calls. */
 fcc_status fcc_dct_batched(const fcc_plan_t* plans, int count, const void* const* in,
                            void* const* out, int direction, void* hip_stream);
+
+/* Free every graph (and its scratch) that fcc_dct_batched has recorded.  At
+ * most 4 are kept anyway (the least recently used is freed when a new one is
+ * recorded); this releases them at once.  Waits for the device first.
+ * Errors: FCC_ERR_HIP. */
+fcc_status fcc_dct_batched_release(void);
 
 /* Free the plan's device tables, scratch and cached graphs.  NULL is a no-op. */
 fcc_status fcc_dct_destroy(fcc_plan_t plan);
@@ -187,7 +197,18 @@ const char* fcc_status_string(fcc_status s);
  *                    sources and no others, so with FCC_MAP_XCD or
  *                    FCC_MAP_XCD16 those sources are fetched into one XCD's
  *                    L2 once.  It takes precedence over FCC_MAP_F_INNER and
- *                    FCC_MAP_BALANCE and changes no result bit. */
+ *                    FCC_MAP_BALANCE and changes no result bit.
+ *                    FCC_MAP_ORBIT (node sizes n / 2^L >= 16) runs the
+ *                    level as one launch over the orbits of W on the node's
+ *                    cube grid: a block loads the sources of 16 orbits of one
+ *                    kind once, forms their rows from the kind's template (the
+ *                    basis change is block diagonal over the orbits) and
+ *                    applies DCT_2 (x) I (inverse: DCT_2^{-1} (x) I, then C)
+ *                    before storing; no per-row table is read.  It takes
+ *                    precedence over every other bit of the level.  Plans with
+ *                    n > 256 need it on every level with node size >= 32 in
+ *                    both directions (the per-row tables pack coordinates in
+ *                    8 bits). */
 enum {
   FCC_MAP_XCD = 1u << 0,
   FCC_MAP_F_INNER = 1u << 1,
@@ -196,7 +217,8 @@ enum {
   FCC_MAP_SPLIT = 1u << 4,
   FCC_MAP_BALANCE = 1u << 5,
   FCC_MAP_XCD16 = 1u << 6,
-  FCC_MAP_CLUSTER = 1u << 7
+  FCC_MAP_CLUSTER = 1u << 7,
+  FCC_MAP_ORBIT = 1u << 8
 };
 typedef struct {
   int tail_levels[2];
@@ -247,6 +269,35 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
  * FCC_ERR_HIP. */
 fcc_status fcc_dct_time_launches(fcc_plan_t plan, const void* in, void* out, int direction, int reps,
                                  float* ms, int cap, int* count, void* hip_stream);
+
+/* One launch slot of a transform: kernel and level(s), the points it covers,
+ * and the algorithmic bytes per point it reads and writes -- each element of
+ * the method's own input and output once, in the plan's data precision (real
+ * 4 or 8 bytes, complex 8 or 16), whatever the stage precision. */
+typedef struct {
+  char name[64];
+  long long points;
+  int in_bytes, out_bytes;
+} fcc_launch_info;
+
+/* The launch slots of one transform in `direction` (+1 forward, -1 inverse),
+ * in the order fcc_dct_time_launches reports them.  *count receives their
+ * number; info (may be NULL) receives up to cap entries.
+ * Errors: FCC_ERR_INVALID_ARG (bad plan or direction, cap too small). */
+fcc_status fcc_dct_describe_launches(fcc_plan_t plan, int direction, fcc_launch_info* info, int cap, int* count);
+
+/* Per-launch timing of fcc_dct_batched's work: the same groups (volumes with
+ * the same plan configuration) and chunks of volumes, enqueued eagerly on
+ * `hip_stream` one group after the other, `reps` times, each kernel between
+ * its own start and stop events.  ms[k] receives the average duration of slot
+ * k and info[k] (may be NULL) its description, named "n<n> x<volumes> <kernel
+ * and levels>"; *nslots receives the slot count (with ms == NULL only that is
+ * set).  direction as for fcc_dct_batched (0 overwrites in[i] with the round
+ * trip).  Allocates and frees its own scratch and waits for `hip_stream`.
+ * Errors: those of fcc_dct_batched, FCC_ERR_INVALID_ARG (cap too small, reps < 1). */
+fcc_status fcc_dct_batched_time_launches(const fcc_plan_t* plans, int count, const void* const* in,
+                                         void* const* out, int direction, int reps, float* ms,
+                                         fcc_launch_info* info, int cap, int* nslots, void* hip_stream);
 
 /* FP64 round-trip residual on the GPU: *result = max_k |x_k - y_k| / max_k |x_k|
  * over the plan's n^3 elements, x and y laid out like the forward input

@@ -13,7 +13,7 @@ FCC_OK = 0
 FCC_PREC_FP64, FCC_PREC_FP32, FCC_PREC_SPLIT_BF16, FCC_PREC_SPLIT_FP16 = 0, 1, 2, 3
 FCC_REAL_INPUT, FCC_STAGES_FP32, FCC_STAGES_FP64, FCC_LEVEL0_FP32 = 1, 2, 4, 8
 (FCC_MAP_XCD, FCC_MAP_F_INNER, FCC_MAP_NODES8, FCC_MAP_NODES64, FCC_MAP_SPLIT, FCC_MAP_BALANCE, FCC_MAP_XCD16,
- FCC_MAP_CLUSTER) = 1, 2, 4, 8, 16, 32, 64, 128
+ FCC_MAP_CLUSTER, FCC_MAP_ORBIT) = 1, 2, 4, 8, 16, 32, 64, 128, 256
 _MAX_LEVELS = 10
 
 # torch is loaded first so that libfccdct.so binds to the HIP runtime torch
@@ -73,6 +73,11 @@ def _tuning_from_c(c):
             "map": [[c.map[d][L] for L in range(_MAX_LEVELS)] for d in range(2)]}
 
 
+class _LaunchInfo(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 64), ("points", ctypes.c_longlong),
+                ("in_bytes", ctypes.c_int), ("out_bytes", ctypes.c_int)]
+
+
 _vp = ctypes.c_void_p
 _lib.fcc_dct_plan.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                               ctypes.c_uint, _vp]
@@ -87,6 +92,13 @@ _lib.fcc_dct_forward_static.argtypes = [_vp, _vp, _vp, _vp]
 _lib.fcc_dct_batched.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                  ctypes.c_int, _vp]
 _lib.fcc_dct_destroy.argtypes = [_vp]
+_lib.fcc_dct_batched_release.argtypes = []
+_lib.fcc_dct_describe_launches.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_LaunchInfo), ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_int)]
+_lib.fcc_dct_batched_time_launches.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp),
+                                               ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int,
+                                               ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_LaunchInfo),
+                                               ctypes.c_int, ctypes.POINTER(ctypes.c_int), _vp]
 _lib.fcc_dct_roundtrip_residual.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp]
 _lib.fcc_dct_time_launches.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float),
                                        ctypes.c_int, ctypes.POINTER(ctypes.c_int), _vp]
@@ -94,7 +106,8 @@ _lib.fcc_status_string.argtypes = [ctypes.c_int]
 _lib.fcc_status_string.restype = ctypes.c_char_p
 _lib.fcc_asp_tables.argtypes = [ctypes.c_int, ctypes.POINTER(_LevelTables)]
 _lib.fcc_asp_orbit_blocks.argtypes = [ctypes.c_int, ctypes.POINTER(_OrbitBlocks)]
-for _f in ("fcc_dct_plan", "fcc_dct_plan_tuned", "fcc_dct_get_tuning", "fcc_dct_autotune", "fcc_dct_forward", "fcc_dct_forward_static", "fcc_dct_inverse", "fcc_dct_batched", "fcc_dct_destroy",
+for _f in ("fcc_dct_plan", "fcc_dct_plan_tuned", "fcc_dct_get_tuning", "fcc_dct_autotune", "fcc_dct_forward", "fcc_dct_forward_static", "fcc_dct_inverse", "fcc_dct_batched", "fcc_dct_destroy", "fcc_dct_batched_release",
+           "fcc_dct_describe_launches", "fcc_dct_batched_time_launches",
            "fcc_asp_tables", "fcc_asp_orbit_blocks", "fcc_dct_time_launches", "fcc_dct_roundtrip_residual"):
     getattr(_lib, _f).restype = ctypes.c_int
 
@@ -224,6 +237,43 @@ class BatchedCall:
 
 def fcc_dct_batched(plans, ins, outs, direction, stream=None):
     BatchedCall(plans, ins, outs, direction)(stream)
+
+
+def fcc_dct_batched_release():
+    """Free every graph fcc_dct_batched has recorded."""
+    _check(_lib.fcc_dct_batched_release(), "fcc_dct_batched_release")
+
+
+def _infos(arr, k):
+    return [{"name": arr[i].name.decode(), "points": int(arr[i].points), "in_bytes": int(arr[i].in_bytes),
+             "out_bytes": int(arr[i].out_bytes)} for i in range(k)]
+
+
+def fcc_dct_describe_launches(plan, direction):
+    """Launch slots of one transform: name, points, algorithmic bytes per point read and written."""
+    cnt = ctypes.c_int(0)
+    _check(_lib.fcc_dct_describe_launches(plan.handle, int(direction), None, 0, ctypes.byref(cnt)),
+           "fcc_dct_describe_launches")
+    arr = (_LaunchInfo * max(1, cnt.value))()
+    _check(_lib.fcc_dct_describe_launches(plan.handle, int(direction), arr, cnt.value, ctypes.byref(cnt)),
+           "fcc_dct_describe_launches")
+    return _infos(arr, cnt.value)
+
+
+def fcc_dct_batched_time_launches(plans, ins, outs, direction, reps=5, stream=None):
+    """Average duration (ms) and description of every launch slot of the batched work."""
+    c = BatchedCall(plans, ins, outs, direction)
+    cnt = ctypes.c_int(0)
+    _check(_lib.fcc_dct_batched_time_launches(c.P, c.cnt, c.I, c.O, c.direction, 1, None, None, 0,
+                                              ctypes.byref(cnt), _stream(stream)), "fcc_dct_batched_time_launches")
+    ms = (ctypes.c_float * cnt.value)()
+    arr = (_LaunchInfo * cnt.value)()
+    _check(_lib.fcc_dct_batched_time_launches(c.P, c.cnt, c.I, c.O, c.direction, int(reps), ms, arr, cnt.value,
+                                              ctypes.byref(cnt), _stream(stream)), "fcc_dct_batched_time_launches")
+    out = _infos(arr, cnt.value)
+    for i, v in enumerate(out):
+        v["ms"] = float(ms[i])
+    return out
 
 
 def fcc_dct_time_launches(plan, x, out, direction, reps=10, stream=None):

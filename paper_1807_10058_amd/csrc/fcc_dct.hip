@@ -15,6 +15,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "asp_tables.hpp"
@@ -1244,6 +1245,9 @@ __global__ void k_phase_table(double2* out, int D, double r0, double r1, double 
 
 }  // namespace fcc
 
+#include "orbit_level.hpp"
+
+
 // ===========================================================================
 // Host side
 // ===========================================================================
@@ -1501,6 +1505,102 @@ fcc_status device_level(int dev, int nl, int S, CubeOrder ob, CubeOrder oc, DevL
   return FCC_OK;
 }
 
+// ---- orbit-block templates on the device (see orbit_level.hpp) --------------
+
+// Cube slots of one kind in wavefront order: quads of 4 slots whose rows have
+// the same lengths first (no lane of a wavefront waits for another), then the
+// rest by decreasing row total; -1 pads the last quad.
+std::vector<int16_t> quad_order(const std::vector<int>& rowptr, int nc) {
+  std::map<std::array<int, 8>, std::vector<int>> byprof;
+  for (int j = 0; j < nc; ++j) {
+    std::array<int, 8> pr{};
+    for (int f = 0; f < 8; ++f) pr[f] = rowptr[j * 8 + f + 1] - rowptr[j * 8 + f];
+    byprof[pr].push_back(j);
+  }
+  std::vector<int16_t> out;
+  std::vector<std::pair<int, int>> rest;  // (-total, slot)
+  for (const auto& kv : byprof) {
+    int tot = 0;
+    for (int v : kv.first) tot += v;
+    const auto& js = kv.second;
+    const size_t whole = js.size() / 4 * 4;
+    for (size_t i = 0; i < whole; ++i) out.push_back(int16_t(js[i]));
+    for (size_t i = whole; i < js.size(); ++i) rest.push_back({-tot, js[i]});
+  }
+  std::sort(rest.begin(), rest.end());
+  for (const auto& r : rest) out.push_back(int16_t(r.second));
+  while (out.size() % 4) out.push_back(-1);
+  return out;
+}
+
+// Templates and representatives of node size nl on device dev (cached; the
+// caller holds the cache lock).  FCC_ERR_UNSUPPORTED if a kind does not fit
+// the kernels' LDS arrays.
+fcc_status device_orbit_level(int dev, int nl, DevOrbitLevel* out) {
+  static std::map<std::array<int, 2>, DevOrbitLevel> levels;
+  const std::array<int, 2> key{dev, nl};
+  auto it = levels.find(key);
+  if (it != levels.end()) {
+    *out = it->second;
+    return FCC_OK;
+  }
+  const OrbitBlocks* ob = orbit_blocks(nl);
+  if (!ob) return FCC_ERR_UNSUPPORTED;
+  if (ob->npoly > kMaxPoly) return FCC_ERR_UNSUPPORTED;
+  std::vector<DevOrbitKind> kinds;
+  std::vector<int16_t> perm;
+  std::vector<uint16_t> rowptr, ent;
+  std::vector<int8_t> wmat;
+  std::vector<uint32_t> reps;
+  std::vector<int4> chunks;
+  const auto& G = weyl_group();
+  for (size_t t = 0; t < ob->templ.size(); ++t) {
+    const OrbitTemplate& T = ob->templ[t];
+    if (T.nc < 1 || T.nc > kOrbitMaxCubes) return FCC_ERR_UNSUPPORTED;
+    DevOrbitKind k{};
+    k.nc = T.nc;
+    k.off_w = int(wmat.size());
+    for (int j = 0; j < T.nc; ++j)
+      for (int i = 0; i < 9; ++i) wmat.push_back(int8_t(G[T.w[j]][i]));
+    for (int side = 0; side < 2; ++side) {
+      const std::vector<int>& rp = side ? T.c_rowptr : T.b_rowptr;
+      const std::vector<uint16_t>& en = side ? T.c_ent : T.b_ent;
+      if (en.size() > size_t(kOrbitMaxEnt)) return FCC_ERR_UNSUPPORTED;
+      k.off_rowptr[side] = int(rowptr.size());
+      for (int v : rp) rowptr.push_back(uint16_t(v));
+      k.off_ent[side] = int(ent.size());
+      ent.insert(ent.end(), en.begin(), en.end());
+      k.off_perm[side] = int(perm.size());
+      const std::vector<int16_t> q = quad_order(rp, T.nc);
+      perm.insert(perm.end(), q.begin(), q.end());
+    }
+    kinds.push_back(k);
+    const std::vector<uint32_t>& r = ob->reps[t];
+    for (size_t r0 = 0; r0 < r.size(); r0 += kOrbitUnits)
+      chunks.push_back(make_int4(int(t), int(reps.size() + r0), int(std::min<size_t>(kOrbitUnits, r.size() - r0)), 0));
+    reps.insert(reps.end(), r.begin(), r.end());
+  }
+  DevOrbitLevel lv{};
+  fcc_status s = FCC_OK;
+  if (s == FCC_OK) s = upload(kinds, &lv.kinds);
+  if (s == FCC_OK) s = upload(perm, &lv.perm);
+  if (s == FCC_OK) s = upload(rowptr, &lv.rowptr);
+  if (s == FCC_OK) s = upload(ent, &lv.ent);
+  if (s == FCC_OK) s = upload(wmat, &lv.wmat);
+  if (s == FCC_OK) s = upload(reps, &lv.reps);
+  if (s == FCC_OK) s = upload(chunks, &lv.chunks);
+  if (s == FCC_OK) s = upload(ob->poly, &lv.poly);
+  if (s != FCC_OK) return s;
+  lv.nchunk = int(chunks.size());
+  lv.npoly = ob->npoly;
+  lv.nconst = ob->nconst;
+  lv.lgm = 0;
+  while ((1 << lv.lgm) < ob->m) ++lv.lgm;
+  levels.emplace(key, lv);
+  *out = lv;
+  return FCC_OK;
+}
+
 bool is_pow2(int n) { return n >= 1 && n <= 1024 && (n & (n - 1)) == 0; }
 
 // Coinciding zeros: theta_j and theta_j' give the same (x,y,z) iff
@@ -1690,7 +1790,14 @@ void fwd_level_dispatch(const fcc_plan_s* p, int L, DT ti, DT to, const VolSet& 
     case DT::F64C: fwd_level_out<R, double2>(p, L, to, vs, nvol, st); break;
   }
 }
-bool fwd_split(const fcc_plan_s* p, int L) { return (p->tune.map[0][L] & FCC_MAP_SPLIT) != 0; }
+// Level L of direction d (0 forward, 1 inverse) runs as one orbit-block
+// launch (orbit_level.hpp): the schedule asks for it, the node size is at
+// least 16, the level is above the fused tail and its templates are on the GPU.
+bool orbit_at(const fcc_plan_s* p, int d, int L) {
+  return L < 10 && (p->tune.map[d][L] & FCC_MAP_ORBIT) && (p->n >> L) >= 16 && L < p->tail_Lt[d] &&
+         L < int(p->olv.size()) && p->olv[L].kinds != nullptr;
+}
+bool fwd_split(const fcc_plan_s* p, int L) { return !orbit_at(p, 0, L) && (p->tune.map[0][L] & FCC_MAP_SPLIT) != 0; }
 // The DCT_2 pass of level D - 2 and the last level run as one launch: the
 // last level runs alone (fused depth 1) after a two-pass level D - 2 (D >= 3)
 // in the same arithmetic.
@@ -1707,10 +1814,129 @@ bool inv_last2(const fcc_plan_s* p) {
 // number of launch slots of one transform in direction d (0 forward, 1 inverse)
 int slot_count(const fcc_plan_s* p, int d) {
   if (p->n == 1 || p->dense) return 1;
-  if (d == 1) return 2 * p->tail_Lt[1] + 1 - (inv_last2(p) ? 1 : 0);
   int k = 1;
+  if (d == 1) {
+    for (int L = 0; L < p->tail_Lt[1]; ++L) k += orbit_at(p, 1, L) ? 1 : 2;
+    return inv_last2(p) ? k - 1 : k;
+  }
   for (int L = 0; L < p->tail_Lt[0]; ++L) k += fwd_split(p, L) ? 2 : 1;
   return fwd_last2(p) ? k - 1 : k;
+}
+// First launch slot of level L (L < tail_Lt[d]) in direction d.
+int level_slot(const fcc_plan_s* p, int d, int L) {
+  int k = 0;
+  if (d == 0) {
+    for (int l = 0; l < L; ++l) k += fwd_split(p, l) ? 2 : 1;
+    return k;
+  }
+  k = 1;  // the tail, or the last level (with the DCT_2^{-1} pass of level D - 2)
+  for (int l = p->tail_Lt[1] - 1; l > L; --l) k += orbit_at(p, 1, l) ? 1 : (l == p->D - 2 && inv_last2(p) ? 1 : 2);
+  return k;
+}
+
+// Names and algorithmic element sizes of the launch slots of one transform in
+// direction d, in launch order (the same decisions as enqueue_forward and
+// enqueue_inverse).  A launch is priced by the method's own input and output:
+// each element read once and written once, in the plan's data precision
+// (real input 4 or 8 bytes, complex 8 or 16), whatever its stage precision.
+struct SlotDesc {
+  std::string name;
+  int in_b, out_b;
+};
+std::vector<SlotDesc> describe_slots(const fcc_plan_s* p, int d) {
+  const int r = p->prec == FCC_PREC_FP64 ? 8 : 4, c = 2 * r;
+  const int rin = (p->flags & FCC_REAL_INPUT) ? r : c;
+  std::vector<SlotDesc> v;
+  auto L_ = [](int L) { return " L" + std::to_string(L); };
+  if (p->n == 1) return {{d == 0 ? "k_copy1" : "k_copy1", d == 0 ? rin : c, d == 0 ? c : rin}};
+  if (p->dense) return {{std::string("k_split_gemm") + (p->prec == FCC_PREC_SPLIT_FP16 ? "<f16>" : "<bf16>"),
+                         d == 0 ? rin : c, d == 0 ? c : rin}};
+  const int D = p->D;
+  if (d == 0) {
+    for (int L = 0; L < p->tail_Lt[0]; ++L) {
+      const int bi = L == 0 ? rin : c;
+      if (orbit_at(p, 0, L)) {
+        v.push_back({"k_fwd_orbit" + L_(L), bi, c});
+      } else if (fwd_split(p, L)) {
+        v.push_back({"k_fwd_gather" + L_(L), bi, c});
+        if (!(L == D - 2 && fwd_last2(p))) v.push_back({"k_fwd_dct2" + L_(L), c, c});
+      } else {
+        v.push_back({"k_fwd_level" + L_(L), bi, c});
+      }
+    }
+    if (fwd_last2(p))
+      v.push_back({"k_fwd_dct2_last2 L" + std::to_string(D - 2) + "-" + std::to_string(D - 1), c, c});
+    else if (p->tail_Lt[0] == D - 1 && D >= 2)
+      v.push_back({"k_fwd_dct2" + L_(D - 1), c, c});
+    else
+      v.push_back({"k_fwd_tail L" + std::to_string(p->tail_Lt[0]) + "-" + std::to_string(D - 1),
+                   p->tail_Lt[0] == 0 ? rin : c, c});
+    return v;
+  }
+  const int Lt = p->tail_Lt[1];
+  if (inv_last2(p))
+    v.push_back({"k_inv_dct2_last2 L" + std::to_string(D - 1) + "-" + std::to_string(D - 2), c, c});
+  else if (Lt == D - 1 && D >= 2 && buf_type(p, D - 1) == stage_type(p))
+    v.push_back({"k_inv_dct2" + L_(D - 1), c, c});
+  else
+    v.push_back({"k_inv_tail L" + std::to_string(D - 1) + "-" + std::to_string(Lt), c, Lt == 0 ? rin : c});
+  for (int L = Lt - 1; L >= 0; --L) {
+    const int bo = L == 0 ? rin : c;
+    if (orbit_at(p, 1, L)) {
+      v.push_back({"k_inv_orbit" + L_(L), c, bo});
+      continue;
+    }
+    if (!(L == D - 2 && inv_last2(p))) v.push_back({"k_inv_dct2" + L_(L), c, c});
+    v.push_back({"k_inv_basis" + L_(L), c, bo});
+  }
+  return v;
+}
+
+// ---- orbit-block level launches -------------------------------------------
+dim3 orbit_grid(const fcc_plan_s* p, int L, int nvol) {
+  const long long total = (long long)p->olv[L].nchunk * (1LL << (3 * L)) * nvol;
+  return dim3(unsigned(((total + 7) >> 3) << 3));
+}
+template <typename R, typename TI, typename TO>
+void fwd_orbit_launch(const fcc_plan_s* p, int L, const VolSet& vs, int nvol, hipStream_t st) {
+  launch((k_fwd_orbit<R, TI, TO>), orbit_grid(p, L, nvol), dim3(kOrbitThreads), 0, st, vs, nvol, p->n, L, p->olv[L],
+         phases(p, L), nodes_of(p, L));
+}
+void fwd_orbit_dispatch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, int nvol, hipStream_t st) {
+  if (arith64(p, L)) {
+    switch (ti) {
+      case DT::F32R: fwd_orbit_launch<double, float, double2>(p, L, vs, nvol, st); break;
+      case DT::F64R: fwd_orbit_launch<double, double, double2>(p, L, vs, nvol, st); break;
+      case DT::F32C: fwd_orbit_launch<double, float2, double2>(p, L, vs, nvol, st); break;
+      case DT::F64C: fwd_orbit_launch<double, double2, double2>(p, L, vs, nvol, st); break;
+    }
+  } else {
+    // FP32 arithmetic: FP32 data in, complex64 out (FP32 stages or FP32 top level)
+    if (ti == DT::F32R)
+      fwd_orbit_launch<float, float, float2>(p, L, vs, nvol, st);
+    else
+      fwd_orbit_launch<float, float2, float2>(p, L, vs, nvol, st);
+  }
+}
+template <typename R, typename TI, typename TO>
+void inv_orbit_launch(const fcc_plan_s* p, int L, const VolSet& vs, int nvol, hipStream_t st) {
+  launch((k_inv_orbit<R, TI, TO>), orbit_grid(p, L, nvol), dim3(kOrbitThreads), 0, st, vs, nvol, p->n, L, p->olv[L],
+         phases(p, L), nodes_of(p, L));
+}
+void inv_orbit_dispatch(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int nvol, hipStream_t st) {
+  if (arith64(p, L)) {
+    switch (to) {
+      case DT::F32R: inv_orbit_launch<double, double2, float>(p, L, vs, nvol, st); break;
+      case DT::F64R: inv_orbit_launch<double, double2, double>(p, L, vs, nvol, st); break;
+      case DT::F32C: inv_orbit_launch<double, double2, float2>(p, L, vs, nvol, st); break;
+      case DT::F64C: inv_orbit_launch<double, double2, double2>(p, L, vs, nvol, st); break;
+    }
+  } else {
+    if (to == DT::F32R)
+      inv_orbit_launch<float, float2, float>(p, L, vs, nvol, st);
+    else
+      inv_orbit_launch<float, float2, float2>(p, L, vs, nvol, st);
+  }
 }
 
 template <typename R>
@@ -1901,7 +2127,10 @@ fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
   for (int L = 0; L < p->tail_Lt[0]; ++L) {
     VolPtrs a = (L & 1) ? ws1 : ws0;
     const DT to = buf_type(p, L + 1);
-    if (!fwd_split(p, L)) {
+    if (orbit_at(p, 0, L)) {
+      // basis change and DCT_2 over whole orbits, into a
+      fwd_orbit_dispatch(p, L, src_t, VolSet{src, a}, nvol, st);
+    } else if (!fwd_split(p, L)) {
       // basis change and DCT_2 in one launch, into a
       if (arith64(p, L))
         fwd_level_dispatch<double>(p, L, src_t, to, VolSet{src, a}, nvol, st);
@@ -1989,6 +2218,16 @@ fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
     // the DCT_2^{-1} pass reads level L+1's result (or the user's X) and
     // writes level L's cube values in level L's arithmetic type
     DT ti = cur_is_user ? cplx_type(p) : buf_type(p, L + 1);
+    if (orbit_at(p, 1, L)) {
+      // DCT_2^{-1} and the basis change over whole orbits, cur -> dst
+      VolPtrs dst = L == 0 ? out : b;
+      DT to = L == 0 ? real_or_cplx : buf_type(p, L);
+      inv_orbit_dispatch(p, L, to, VolSet{cur, dst}, nvol, st);
+      cur = b;
+      cur_is_user = false;
+      which ^= 1;
+      continue;
+    }
     if (L == p->D - 2 && inv_last2(p)) {
       // done with the last level above
     } else if (arith64(p, L)) {
@@ -2043,6 +2282,9 @@ std::mutex& batch_mu() {
   static std::mutex m;
   return m;
 }
+// Recorded graphs, most recently used last; at most kBatchCacheCap are kept
+// (the oldest is freed when a new one is recorded).
+constexpr size_t kBatchCacheCap = 4;
 std::vector<BatchExec*>& batch_cache() {
   static std::vector<BatchExec*> c;
   return c;
@@ -2057,71 +2299,11 @@ void free_batch(BatchExec* b) {
 
 bool same_config(const fcc_plan_s* a, const fcc_plan_s* b) {
   return a->n == b->n && a->prec == b->prec && a->flags == b->flags && a->stages64 == b->stages64 &&
-         a->dense == b->dense && a->rst[0] == b->rst[0] && a->rst[1] == b->rst[1] && a->rst[2] == b->rst[2] &&
-         std::memcmp(&a->tune, &b->tune, sizeof a->tune) == 0;
+         a->dense == b->dense && a->level0_fp32 == b->level0_fp32 && a->rst[0] == b->rst[0] &&
+         a->rst[1] == b->rst[1] && a->rst[2] == b->rst[2] && std::memcmp(&a->tune, &b->tune, sizeof a->tune) == 0;
 }
 
-// Resources of one group, allocated before capture (no allocation or
-// synchronous copy may happen while a stream is being captured).
-struct GroupRes {
-  void** rows = nullptr;   // device pointer arrays: in, out, scratch 0, scratch 1 (cnt each)
-  float* scale = nullptr;  // dense FP16: per-row scales
-  void* ws = nullptr;      // fast path: per-volume scratch pairs
-  size_t wb = 0;
-};
-
-fcc_status prepare_group(BatchExec* bx, const BatchGroup& g, const void* const* in, void* const* out, GroupRes* r) {
-  const fcc_plan_s* p = g.p;
-  const int cnt = int(g.vols.size());
-  const bool scratch = !p->dense && p->n > 1;
-  if (scratch) {
-    const size_t N = size_t(p->n) * p->n * p->n;
-    r->wb = N * (p->stages64 ? sizeof(double2) : sizeof(float2));
-    if (hipMalloc(&r->ws, r->wb * 2 * cnt) != hipSuccess) return FCC_ERR_OOM;
-    bx->allocations.push_back(r->ws);
-  }
-  std::vector<void*> ptr(size_t(4) * cnt, nullptr);
-  for (int v = 0; v < cnt; ++v) {
-    ptr[v] = const_cast<void*>(in[g.vols[v]]);
-    ptr[cnt + v] = out[g.vols[v]];
-    if (scratch) {
-      ptr[2 * cnt + v] = static_cast<char*>(r->ws) + r->wb * (2 * size_t(v));
-      ptr[3 * cnt + v] = static_cast<char*>(r->ws) + r->wb * (2 * size_t(v) + 1);
-    }
-  }
-  void* d = nullptr;
-  if (hipMalloc(&d, sizeof(void*) * ptr.size() + sizeof(float) * cnt) != hipSuccess) return FCC_ERR_OOM;
-  bx->allocations.push_back(d);
-  r->rows = static_cast<void**>(d);
-  r->scale = reinterpret_cast<float*>(r->rows + ptr.size());
-  if (hipMemcpy(r->rows, ptr.data(), sizeof(void*) * ptr.size(), hipMemcpyHostToDevice) != hipSuccess)
-    return FCC_ERR_HIP;
-  return FCC_OK;
-}
-
-fcc_status record_group(const BatchGroup& g, const GroupRes& r, int dir, hipStream_t st) {
-  const fcc_plan_s* p = g.p;
-  const int cnt = int(g.vols.size());
-  void** in = r.rows;
-  void** out = r.rows + cnt;
-  void** w0 = r.rows + 2 * cnt;
-  void** w1 = r.rows + 3 * cnt;
-  if (p->dense) {
-    fcc_status s = FCC_OK;
-    if (dir >= 0) s = dense_run(p, p->dfwd, cnt, in, out, nullptr, nullptr, r.scale, st);
-    if (s == FCC_OK && dir == 0) s = dense_run(p, p->dinv, cnt, out, in, nullptr, nullptr, r.scale, st);
-    if (s == FCC_OK && dir < 0) s = dense_run(p, p->dinv, cnt, in, out, nullptr, nullptr, r.scale, st);
-    return s;
-  }
-  fcc_status s = FCC_OK;
-  if (dir >= 0) s = enqueue_forward(p, cnt, many_vol(in), many_vol(out), many_vol(w0), many_vol(w1), st);
-  if (s == FCC_OK && dir == 0) s = enqueue_inverse(p, cnt, many_vol(out), many_vol(in), many_vol(w0), many_vol(w1), st);
-  if (s == FCC_OK && dir < 0) s = enqueue_inverse(p, cnt, many_vol(in), many_vol(out), many_vol(w0), many_vol(w1), st);
-  return s;
-}
-
-fcc_status build_batch(BatchExec* bx, const fcc_plan_t* plans, int count, const void* const* in, void* const* out,
-                       int dir) {
+std::vector<BatchGroup> group_plans(const fcc_plan_t* plans, int count) {
   std::vector<BatchGroup> groups;
   for (int i = 0; i < count; ++i) {
     bool placed = false;
@@ -2138,30 +2320,162 @@ fcc_status build_batch(BatchExec* bx, const fcc_plan_t* plans, int count, const 
       groups.push_back(g);
     }
   }
-  // record on a private stream (the caller's may be the legacy default stream,
-  // which cannot be captured); kernels only, no memset nodes
-  hipStream_t cap = nullptr;
-  if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return FCC_ERR_HIP;
+  return groups;
+}
+
+// A group's volumes run in chunks of at most this many points per launch; the
+// chunks share one scratch pair (they run one after the other on the group's
+// stream), which bounds the scratch of a group to ~2 x 2^25 stage values.
+constexpr long long kBatchChunkPoints = 1LL << 25;
+int chunk_volumes(const fcc_plan_s* p, int cnt) {
+  const long long N = (long long)p->n * p->n * p->n;
+  return int(std::max<long long>(1, std::min<long long>(cnt, kBatchChunkPoints / std::max<long long>(1, N))));
+}
+
+// Resources of one group, allocated before capture (no allocation or
+// synchronous copy may happen while a stream is being captured).
+struct GroupRes {
+  void** rows = nullptr;   // device pointer arrays: in, out, scratch 0, scratch 1 (cnt each)
+  float* scale = nullptr;  // dense FP16: per-row scales
+  void* ws = nullptr;      // fast path: one scratch pair per volume of a chunk
+  size_t wb = 0;
+  int chunk = 1;           // volumes per chunk
+};
+
+fcc_status prepare_group(std::vector<void*>* allocs, const BatchGroup& g, const void* const* in, void* const* out,
+                         GroupRes* r) {
+  const fcc_plan_s* p = g.p;
+  const int cnt = int(g.vols.size());
+  const bool scratch = !p->dense && p->n > 1;
+  r->chunk = p->dense ? cnt : chunk_volumes(p, cnt);
+  if (scratch) {
+    const size_t N = size_t(p->n) * p->n * p->n;
+    r->wb = N * (p->stages64 ? sizeof(double2) : sizeof(float2));
+    if (hipMalloc(&r->ws, r->wb * 2 * r->chunk) != hipSuccess) return FCC_ERR_OOM;
+    allocs->push_back(r->ws);
+  }
+  std::vector<void*> ptr(size_t(4) * cnt, nullptr);
+  for (int v = 0; v < cnt; ++v) {
+    ptr[v] = const_cast<void*>(in[g.vols[v]]);
+    ptr[cnt + v] = out[g.vols[v]];
+    if (scratch) {
+      const int slot = v % r->chunk;
+      ptr[2 * cnt + v] = static_cast<char*>(r->ws) + r->wb * (2 * size_t(slot));
+      ptr[3 * cnt + v] = static_cast<char*>(r->ws) + r->wb * (2 * size_t(slot) + 1);
+    }
+  }
+  void* d = nullptr;
+  if (hipMalloc(&d, sizeof(void*) * ptr.size() + sizeof(float) * cnt) != hipSuccess) return FCC_ERR_OOM;
+  allocs->push_back(d);
+  r->rows = static_cast<void**>(d);
+  r->scale = reinterpret_cast<float*>(r->rows + ptr.size());
+  if (hipMemcpy(r->rows, ptr.data(), sizeof(void*) * ptr.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return FCC_ERR_HIP;
+  return FCC_OK;
+}
+
+// Enqueue direction d (+1 forward in -> out, -1 inverse in -> out; the round
+// trip calls forward, then inverse with in and out swapped) for one group,
+// chunk by chunk.  ev (optional): start/stop events for every launch slot of
+// every chunk (dense groups: around each GEMM).
+fcc_status enqueue_group(const BatchGroup& g, const GroupRes& r, int d, bool swap, hipStream_t st,
+                         std::vector<hipEvent_t>* ev, size_t* evpos) {
+  const fcc_plan_s* p = g.p;
+  const int cnt = int(g.vols.size());
+  void** in = r.rows + (swap ? cnt : 0);
+  void** out = r.rows + (swap ? 0 : cnt);
+  void** w0 = r.rows + 2 * cnt;
+  void** w1 = r.rows + 3 * cnt;
+  fcc_status s = FCC_OK;
+  if (p->dense) {
+    if (ev) (void)hipEventRecord((*ev)[(*evpos)++], st);
+    s = dense_run(p, d > 0 ? p->dfwd : p->dinv, cnt, in, out, nullptr, nullptr, r.scale, st);
+    if (ev) (void)hipEventRecord((*ev)[(*evpos)++], st);
+    return s;
+  }
+  for (int v0 = 0; v0 < cnt && s == FCC_OK; v0 += r.chunk) {
+    const int k = std::min(r.chunk, cnt - v0);
+    LaunchTimer tm;
+    if (ev) {
+      tm.ev = ev;
+      tm.next = *evpos;
+      t_timer = &tm;
+    }
+    s = d > 0 ? enqueue_forward(p, k, many_vol(in + v0), many_vol(out + v0), many_vol(w0 + v0), many_vol(w1 + v0), st)
+              : enqueue_inverse(p, k, many_vol(in + v0), many_vol(out + v0), many_vol(w0 + v0), many_vol(w1 + v0), st);
+    t_timer = nullptr;
+    if (ev) *evpos = tm.next;
+  }
+  return s;
+}
+
+fcc_status record_group(const BatchGroup& g, const GroupRes& r, int dir, hipStream_t st) {
+  fcc_status s = FCC_OK;
+  if (dir >= 0) s = enqueue_group(g, r, 1, false, st, nullptr, nullptr);
+  if (s == FCC_OK && dir == 0) s = enqueue_group(g, r, -1, true, st, nullptr, nullptr);
+  if (s == FCC_OK && dir < 0) s = enqueue_group(g, r, -1, false, st, nullptr, nullptr);
+  return s;
+}
+
+// Up to this many branches of the graph run side by side: group k is
+// recorded on branch k mod kBatchBranches, between a fork and a join.
+constexpr int kBatchBranches = 4;
+
+fcc_status build_batch(BatchExec* bx, const fcc_plan_t* plans, int count, const void* const* in, void* const* out,
+                       int dir) {
+  std::vector<BatchGroup> groups = group_plans(plans, count);
+  // largest groups first: they start at once on their own branch
+  std::stable_sort(groups.begin(), groups.end(), [](const BatchGroup& a, const BatchGroup& b) {
+    return (long long)a.p->n * a.p->n * a.p->n * (long long)a.vols.size() >
+           (long long)b.p->n * b.p->n * b.p->n * (long long)b.vols.size();
+  });
   fcc_status s = FCC_OK;
   std::vector<GroupRes> res(groups.size());
-  for (size_t gi = 0; gi < groups.size() && s == FCC_OK; ++gi) s = prepare_group(bx, groups[gi], in, out, &res[gi]);
-  if (s != FCC_OK) {
-    (void)hipStreamDestroy(cap);
-    return s;
+  for (size_t gi = 0; gi < groups.size() && s == FCC_OK; ++gi)
+    s = prepare_group(&bx->allocations, groups[gi], in, out, &res[gi]);
+  if (s != FCC_OK) return s;
+  // record on private default-priority streams (the caller's may be the
+  // legacy default stream, which cannot be captured); kernels only, no
+  // memset nodes
+  const int nb = std::min<int>(kBatchBranches, int(groups.size()));
+  std::vector<hipStream_t> br(nb, nullptr);
+  std::vector<hipEvent_t> evs(1 + nb, nullptr);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking);
+  for (size_t i = 0; i < evs.size() && e == hipSuccess; ++i)
+    e = hipEventCreateWithFlags(&evs[i], hipEventDisableTiming);
+  auto cleanup = [&]() {
+    for (auto q : br)
+      if (q) (void)hipStreamDestroy(q);
+    for (auto v : evs)
+      if (v) (void)hipEventDestroy(v);
+  };
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "hipStreamCreate(batch branches)", __LINE__);
   }
-  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-    (void)hipStreamDestroy(cap);
-    return FCC_ERR_HIP;
+  if ((e = hipStreamBeginCapture(br[0], hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "hipStreamBeginCapture", __LINE__);
   }
-  for (size_t gi = 0; gi < groups.size() && s == FCC_OK; ++gi) s = record_group(groups[gi], res[gi], dir, cap);
+  // fork: the other branches wait for an event of the capturing stream
+  e = hipEventRecord(evs[0], br[0]);
+  for (int i = 1; i < nb && e == hipSuccess; ++i) e = hipStreamWaitEvent(br[i], evs[0], 0);
+  for (size_t gi = 0; gi < groups.size() && s == FCC_OK && e == hipSuccess; ++gi)
+    s = record_group(groups[gi], res[gi], dir, br[gi % nb]);
+  // join
+  for (int i = 1; i < nb && s == FCC_OK && e == hipSuccess; ++i) {
+    e = hipEventRecord(evs[i], br[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(br[0], evs[i], 0);
+  }
   hipGraph_t graph = nullptr;
-  hipError_t e = hipStreamEndCapture(cap, &graph);
-  (void)hipStreamDestroy(cap);
-  if (s != FCC_OK) {
+  hipError_t ee = hipStreamEndCapture(br[0], &graph);
+  cleanup();
+  if (s != FCC_OK || e != hipSuccess || ee != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
-    return s;
+    if (s != FCC_OK) return s;
+    return hip_fail(e != hipSuccess ? e : ee, "batch graph capture", __LINE__);
   }
-  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture", __LINE__);
   bx->graph = graph;
   e = hipGraphInstantiate(&bx->exec, graph, nullptr, nullptr, 0);
   if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate", __LINE__);
@@ -2277,7 +2591,8 @@ fcc_tuning default_tuning(int n) {
     t.tail_levels[d] = c.tail[d];
     for (int L = 0; L < 2; ++L)
       for (int a = 0; a < 3; ++a) t.tile[d][L][a] = c.tile[d][L][a];
-    for (int L = 0; L < 10; ++L) t.map[d][L] = c.map[d][L];
+    // orbit-block launches for every level with node size >= 32
+    for (int L = 0; L < 10; ++L) t.map[d][L] = c.map[d][L] | ((n >> L) >= 32 ? unsigned(FCC_MAP_ORBIT) : 0u);
   }
   return t;
 }
@@ -2290,7 +2605,7 @@ bool valid_tuning(const fcc_tuning& t) {
     for (int L = 0; L < 10; ++L) {
       const unsigned m = t.map[d][L];
       if (m & ~unsigned(FCC_MAP_XCD | FCC_MAP_F_INNER | FCC_MAP_NODES8 | FCC_MAP_NODES64 | FCC_MAP_SPLIT |
-                        FCC_MAP_BALANCE | FCC_MAP_XCD16 | FCC_MAP_CLUSTER))
+                        FCC_MAP_BALANCE | FCC_MAP_XCD16 | FCC_MAP_CLUSTER | FCC_MAP_ORBIT))
         return false;
       if ((m & FCC_MAP_NODES8) && (m & FCC_MAP_NODES64)) return false;
     }
@@ -2347,8 +2662,11 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
   if (flags & ~(unsigned)(FCC_REAL_INPUT | FCC_STAGES_FP32 | FCC_STAGES_FP64 | FCC_LEVEL0_FP32))
     return FCC_ERR_INVALID_ARG;
   if (tuning && !valid_tuning(*tuning)) return FCC_ERR_INVALID_ARG;
+  // per-row tables pack node-local coordinates in 8 bits: node sizes above 256
+  // need orbit-block launches in both directions
+  for (int L = 0; tuning && L < 10 && (n >> L) > 256; ++L)
+    if (!(tuning->map[0][L] & tuning->map[1][L] & FCC_MAP_ORBIT)) return FCC_ERR_UNSUPPORTED;
   if ((prec == FCC_PREC_SPLIT_BF16 || prec == FCC_PREC_SPLIT_FP16) && n > 8) return FCC_ERR_UNSUPPORTED;
-  if (n > 256) return FCC_ERR_UNSUPPORTED;  // table entries pack node-local coordinates in 8 bits
   double r[3] = {0.125, 0.0, 0.375};
   if (rst)
     for (int d = 0; d < 3; ++d) {
@@ -2401,15 +2719,34 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   fcc_status s = FCC_OK;
   (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
+  // Levels that run as orbit-block launches in both directions read no
+  // per-row table; the others need one, and its packed entries hold node-local
+  // coordinates in 8 bits (node size <= 256).
+  bool tables[16] = {};
+  for (int L = 0; L < p->D; ++L) {
+    const bool orb = (n >> L) >= 16 && L < 10 && (p->tune.map[0][L] & FCC_MAP_ORBIT) &&
+                     (p->tune.map[1][L] & FCC_MAP_ORBIT);
+    tables[L] = !orb;
+    if (tables[L] && (n >> L) > 256) {
+      delete p;
+      return FCC_ERR_UNSUPPORTED;
+    }
+  }
   {
     std::lock_guard<std::mutex> lock(cache().mu);
+    p->olv.assign(p->D, DevOrbitLevel{});
+    for (int L = 0; s == FCC_OK && L < p->D && L < 10; ++L)
+      if ((n >> L) >= 16 && ((p->tune.map[0][L] | p->tune.map[1][L]) & FCC_MAP_ORBIT))
+        s = device_orbit_level(p->device, n >> L, &p->olv[L]);
     for (int L = 0; s == FCC_OK && L < p->D; ++L) {
-      DevLevel lv;
-      s = device_level(p->device, n >> L, slice_cubes(L), tile_order(p, 0, L), tile_order(p, 1, L), &lv);
+      DevLevel lv{};
+      if (tables[L])
+        s = device_level(p->device, n >> L, slice_cubes(L), tile_order(p, 0, L), tile_order(p, 1, L), &lv);
       p->lv.push_back(lv);
     }
     // balanced map: lanes per row from the mean row length of each f
     for (int L = 0; s == FCC_OK && L < p->D; ++L) {
+      if (!tables[L]) continue;
       const LevelTables* T = level_tables(n >> L);
       if (!T) {
         s = FCC_ERR_OOM;
@@ -2430,7 +2767,7 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
     // tail may cover (node sizes <= 16); levels >= 2 have them already
     p->tlv.resize(p->D);
     for (int L = std::max(0, p->D - 4); s == FCC_OK && L < p->D; ++L) {
-      if (L >= 2)
+      if (L >= 2 && tables[L])
         p->tlv[L] = p->lv[L];
       else
         s = device_level(p->device, n >> L, 1, CubeOrder{0, 0, 0}, CubeOrder{0, 0, 0}, &p->tlv[L]);
@@ -2720,9 +3057,8 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
       // 2. tile shape and thread map of the level-0 and level-1 gather
       // passes, by the time of that level's launches
       auto level_ms = [&](int L) {
-        if (d == 1) return double(ms[2 * (p->tail_Lt[1] - L) - (inv_last2(p) ? 1 : 0)]);  // the C gather pass
-        int k = 0;
-        for (int l = 0; l < L; ++l) k += fwd_split(p, l) ? 2 : 1;
+        const int k = level_slot(p, d, L);
+        if (d == 1) return double(ms[k + ((L == p->D - 2 && inv_last2(p)) ? 0 : 1)]);  // the C gather pass
         return double(ms[k]) + (fwd_split(p, L) ? double(ms[k + 1]) : 0.0);
       };
       static const int tiles0[][3] = {{0, 0, 0}, {2, 2, 2}, {1, 2, 3}, {0, 3, 3}, {3, 3, 3}, {2, 2, 4}};
@@ -2752,6 +3088,7 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
                                          FCC_MAP_CLUSTER | FCC_MAP_XCD,
                                          FCC_MAP_CLUSTER | FCC_MAP_XCD16};
       for (int L = 0; L < 2 && L < p->tail_Lt[d] && s == FCC_OK; ++L) {
+        if (orbit_at(p, d, L)) continue;  // no table, no map to search
         const int lgm = p->D - L - 1;
         const int ntiles = L == 0 ? 6 : 4;
         DevSide& cur = d == 0 ? p->lv[L].b : p->lv[L].c;
@@ -2845,6 +3182,7 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
                                           FCC_MAP_BALANCE | FCC_MAP_XCD,
                                           FCC_MAP_NODES64 | FCC_MAP_XCD16};
       for (int L = 2; L < p->tail_Lt[d] && s == FCC_OK; ++L) {
+        if (orbit_at(p, d, L)) continue;
         unsigned best_m = p->tune.map[d][L];
         double best_ms = 1e30;
         const unsigned* maps = d == 0 ? deep_fwd : deep_inv;
@@ -2928,10 +3266,22 @@ fcc_status fcc_dct_batched(const fcc_plan_t* plans, int count, const void* const
     key.push_back(reinterpret_cast<uintptr_t>(out[i]));
   }
   std::lock_guard<std::mutex> lock(batch_mu());
+  auto& cache_v = batch_cache();
   BatchExec* bx = nullptr;
-  for (BatchExec* b : batch_cache())
-    if (b->key == key) bx = b;
+  for (size_t i = 0; i < cache_v.size(); ++i)
+    if (cache_v[i]->key == key) {
+      bx = cache_v[i];
+      cache_v.erase(cache_v.begin() + i);
+      cache_v.push_back(bx);  // most recently used last
+      break;
+    }
   if (!bx) {
+    if (cache_v.size() >= kBatchCacheCap) {
+      // the oldest graph may still run on a stream: wait for the device first
+      (void)hipDeviceSynchronize();
+      free_batch(cache_v.front());
+      cache_v.erase(cache_v.begin());
+    }
     bx = new (std::nothrow) BatchExec;
     if (!bx) return FCC_ERR_OOM;
     bx->key = key;
@@ -2940,11 +3290,116 @@ fcc_status fcc_dct_batched(const fcc_plan_t* plans, int count, const void* const
       free_batch(bx);
       return s;
     }
-    batch_cache().push_back(bx);
+    cache_v.push_back(bx);
   }
   hipError_t e = hipGraphLaunch(bx->exec, st);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch", __LINE__);
   return FCC_OK;
+}
+
+fcc_status fcc_dct_batched_release(void) {
+  std::lock_guard<std::mutex> lock(batch_mu());
+  auto& c = batch_cache();
+  if (c.empty()) return FCC_OK;
+  hipError_t e = hipDeviceSynchronize();
+  for (BatchExec* b : c) free_batch(b);
+  c.clear();
+  return e == hipSuccess ? FCC_OK : hip_fail(e, "hipDeviceSynchronize", __LINE__);
+}
+
+fcc_status fcc_dct_describe_launches(fcc_plan_t p, int direction, fcc_launch_info* info, int cap, int* count) {
+  if (!p || !count || (direction != 1 && direction != -1)) return FCC_ERR_INVALID_ARG;
+  const std::vector<SlotDesc> v = describe_slots(p, direction > 0 ? 0 : 1);
+  *count = int(v.size());
+  if (!info) return FCC_OK;
+  if (cap < int(v.size())) return FCC_ERR_INVALID_ARG;
+  const long long N = (long long)p->n * p->n * p->n;
+  for (size_t i = 0; i < v.size(); ++i) {
+    std::memset(&info[i], 0, sizeof info[i]);
+    std::snprintf(info[i].name, sizeof info[i].name, "%s", v[i].name.c_str());
+    info[i].points = N;
+    info[i].in_bytes = v[i].in_b;
+    info[i].out_bytes = v[i].out_b;
+  }
+  return FCC_OK;
+}
+
+fcc_status fcc_dct_batched_time_launches(const fcc_plan_t* plans, int count, const void* const* in,
+                                         void* const* out, int direction, int reps, float* ms,
+                                         fcc_launch_info* info, int cap, int* nslots, void* hip_stream) {
+  if (!plans || !in || !out || count < 1 || !nslots || reps < 1) return FCC_ERR_INVALID_ARG;
+  if (direction < -1 || direction > 1) return FCC_ERR_INVALID_ARG;
+  for (int i = 0; i < count; ++i)
+    if (!plans[i] || !in[i] || !out[i] || !aligned16(in[i]) || !aligned16(out[i]) || in[i] == out[i])
+      return FCC_ERR_INVALID_ARG;
+  std::vector<BatchGroup> groups = group_plans(plans, count);
+  // the slots: per group, the forward then the inverse launches of every chunk
+  std::vector<fcc_launch_info> slots;
+  std::vector<int> per_run;  // slots of one pass over all groups
+  for (const BatchGroup& g : groups) {
+    const int cnt = int(g.vols.size());
+    const int chunk = g.p->dense ? cnt : chunk_volumes(g.p, cnt);
+    for (int d = 0; d < 2; ++d) {
+      if ((d == 0 && direction < 0) || (d == 1 && direction > 0)) continue;
+      const std::vector<SlotDesc> v = describe_slots(g.p, d);
+      for (int v0 = 0; v0 < cnt; v0 += chunk) {
+        const int k = std::min(chunk, cnt - v0);
+        for (const SlotDesc& sd : v) {
+          fcc_launch_info li{};
+          std::snprintf(li.name, sizeof li.name, "n%d x%d %s", g.p->n, k, sd.name.c_str());
+          li.points = (long long)k * g.p->n * g.p->n * g.p->n;
+          li.in_bytes = sd.in_b;
+          li.out_bytes = sd.out_b;
+          slots.push_back(li);
+        }
+      }
+    }
+  }
+  *nslots = int(slots.size());
+  if (!ms) return FCC_OK;
+  if (cap < int(slots.size())) return FCC_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  (void)hipGetLastError();
+  std::vector<void*> allocs;
+  std::vector<GroupRes> res(groups.size());
+  fcc_status s = FCC_OK;
+  for (size_t gi = 0; gi < groups.size() && s == FCC_OK; ++gi) s = prepare_group(&allocs, groups[gi], in, out, &res[gi]);
+  std::vector<hipEvent_t> ev(size_t(2) * slots.size() * reps, nullptr);
+  for (size_t i = 0; i < ev.size() && s == FCC_OK; ++i) {
+    hipError_t he = hipEventCreate(&ev[i]);
+    if (he != hipSuccess) s = hip_fail(he, "hipEventCreate", __LINE__);
+  }
+  size_t pos = 0;
+  for (int r = 0; r < reps && s == FCC_OK; ++r)
+    for (size_t gi = 0; gi < groups.size() && s == FCC_OK; ++gi) {
+      if (direction >= 0) s = enqueue_group(groups[gi], res[gi], 1, false, st, &ev, &pos);
+      if (s == FCC_OK && direction == 0) s = enqueue_group(groups[gi], res[gi], -1, true, st, &ev, &pos);
+      if (s == FCC_OK && direction < 0) s = enqueue_group(groups[gi], res[gi], -1, false, st, &ev, &pos);
+    }
+  if (s == FCC_OK && pos != ev.size()) s = FCC_ERR_HIP;  // launch count differs from the slot count
+  if (s == FCC_OK) {
+    hipError_t he = hipStreamSynchronize(st);
+    if (he != hipSuccess) s = hip_fail(he, "hipStreamSynchronize", __LINE__);
+  }
+  if (s == FCC_OK) {
+    const size_t ns = slots.size();
+    for (size_t k = 0; k < ns; ++k) {
+      double acc = 0.0;
+      for (int r = 0; r < reps; ++r) {
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, ev[(size_t(r) * ns + k) * 2], ev[(size_t(r) * ns + k) * 2 + 1]);
+        acc += t;
+      }
+      ms[k] = float(acc / reps);
+      if (info) info[k] = slots[k];
+    }
+  } else {
+    (void)hipStreamSynchronize(st);
+  }
+  for (auto e : ev)
+    if (e) (void)hipEventDestroy(e);
+  for (void* a : allocs) (void)hipFree(a);
+  return s;
 }
 
 }  // extern "C"

@@ -159,6 +159,30 @@ struct GatherMap {
   long long off[9];
 };
 
+// Orbit-block form of the basis change (orbit_level.hpp).
+// One orbit kind on the device.
+struct DevOrbitKind {
+  int nc;             // cubes of the orbit
+  int off_w;          // wmat: 9 nc entries, the matrices G[w_j] of the cube slots (row-major)
+  int off_perm[2];    // i16: 4 ceil(nc/4) cube slots in wavefront order (-1: idle lane), [0] B, [1] C
+  int off_rowptr[2];  // u16: 8 nc + 1 row starts of B (C), relative to off_ent
+  int off_ent[2];     // u16: entries (slot << 8) | polynomial id
+};
+// Templates and representatives of one node size.
+struct DevOrbitLevel {
+  const DevOrbitKind* kinds;
+  const int16_t* perm;
+  const uint16_t* rowptr;
+  const uint16_t* ent;
+  const int8_t* wmat;
+  const uint32_t* reps;  // representatives p0 packed (x << 20) | (y << 10) | z
+  const int4* chunks;    // {kind, first representative, count <= 16, 0}
+  int nchunk;
+  const double* poly;    // npoly * kNumMono, ids below nconst are constants
+  int npoly, nconst;
+  int lgm;               // log2 m
+};
+
 // Where the volumes of one launch live: one volume at `one` (arr == nullptr)
 // or one pointer per volume in the device array `arr`.
 struct VolPtrs {

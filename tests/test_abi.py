@@ -51,10 +51,17 @@ def test_plan_rejects_singular_skew_like_the_oracle():
 
 
 @pytest.mark.parametrize("n", [512, 1024])
-def test_plan_rejects_n_above_256_as_unsupported(n):
-    # checked before any device work, so this runs without a GPU
+def test_plan_rejects_table_levels_above_256_as_unsupported(n):
+    """Per-row gather tables pack node-local coordinates in 8 bits, so node
+    sizes above 256 are served only by orbit-block launches; a schedule that
+    asks for tables there is refused before any device work (runs without a GPU)."""
+    tuning = {"tail_levels": [1, 1], "tile": [[[0, 0, 0]] * 2] * 2, "map": [[0] * 10, [0] * 10]}
     with pytest.raises(fcc.FccError) as e:
-        fcc.fcc_dct_plan(n, stream=0)
+        fcc.fcc_dct_plan_tuned(n, tuning=tuning, stream=0)
+    assert e.value.status == 6
+    tuning["map"] = [[fcc.FCC_MAP_ORBIT] * 10, [0] * 10]
+    with pytest.raises(fcc.FccError) as e:
+        fcc.fcc_dct_plan_tuned(n, tuning=tuning, stream=0)
     assert e.value.status == 6
 
 
@@ -86,7 +93,7 @@ def _tuning(**kw):
     {"tail_levels": [0, 1]}, {"tail_levels": [1, 5]},
     {"tile": [[[0, 0, -1], [0, 0, 0]], [[0, 0, 0], [0, 0, 0]]]},
     {"tile": [[[0, 0, 0], [0, 0, 0]], [[0, 10, 0], [0, 0, 0]]]},
-    {"map": [[256, 0], [0, 0]]},
+    {"map": [[512, 0], [0, 0]]},
     {"map": [[0, 0, 0], [0, 0, 12]]},
 ])
 def test_plan_tuned_rejects_bad_schedules(bad):

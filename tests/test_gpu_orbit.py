@@ -1,0 +1,132 @@
+"""Orbit-block level launches (FCC_MAP_ORBIT, the default for node sizes >= 32)
+against the independent fold references and against the per-row table path.
+
+The basis change B_nl (C_nl) of Sec. IV-B is block diagonal over the orbits
+of W on the cube grid mod m; a launch applies whole blocks from LDS and fuses
+DCT_2 (x) I (DCT_2^{-1} (x) I).  Tolerances are those of the other parity
+tests: FP64 bounds that grow with n (ill-conditioned skew children), FP32 data
+1e-5 relative."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1807_10058_amd as fcc
+import workloads
+from oracle import fold_ref
+
+pytestmark = pytest.mark.gpu
+gu = pytest.importorskip("tests.gpu_util")
+RNG = np.random.default_rng(77)
+FP64_TOL = {32: 1e-10, 64: 1e-8, 128: 1e-7}
+
+
+def _tables_only(plan):
+    t = fcc.fcc_dct_get_tuning(plan)
+    t["map"] = [[m & ~fcc.FCC_MAP_ORBIT for m in row] for row in t["map"]]
+    return t
+
+
+def _run(plan, x, prec, real):
+    n = plan.n
+    rdt, cdt = gu.rdtype(prec), gu.cdtype(prec)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to(gu.DEV, rdt if real else cdt)
+    X = torch.empty(n ** 3, dtype=cdt, device=gu.DEV)
+    y = torch.empty(n ** 3, dtype=rdt if real else cdt, device=gu.DEV)
+    fcc.fcc_dct_forward(plan, xt, X)
+    fcc.fcc_dct_inverse(plan, X, y)
+    torch.cuda.synchronize()
+    return xt, X, y
+
+
+def test_default_schedule_uses_orbit_levels():
+    plan = fcc.fcc_dct_plan(64, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT)
+    t = fcc.fcc_dct_get_tuning(plan)
+    for d in range(2):
+        assert [bool(t["map"][d][L] & fcc.FCC_MAP_ORBIT) for L in range(6)] == [True, True, False, False, False,
+                                                                                False]
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_orbit_fp64_complex_against_fold(n):
+    x = RNG.standard_normal(n ** 3) + 1j * RNG.standard_normal(n ** 3)
+    plan = fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP64, flags=0)
+    _, X, y = _run(plan, x, fcc.FCC_PREC_FP64, False)
+    Xh = X.cpu().numpy()
+    assert gu.maxrel(Xh, fold_ref.fold_forward(x, n)) <= FP64_TOL[n]
+    assert gu.maxrel(y.cpu().numpy(), x) <= 10 * FP64_TOL[n]
+    # the inverse alone, on the exact spectrum of another input
+    x2 = RNG.standard_normal(n ** 3) + 1j * RNG.standard_normal(n ** 3)
+    X2 = fold_ref.fold_forward(x2, n)
+    xi = gu.inverse(X2, n, fcc.FCC_PREC_FP64)
+    assert gu.maxrel(xi, fold_ref.fold_inverse(X2, n)) <= 10 * FP64_TOL[n]
+
+
+@pytest.mark.parametrize("n", [32, 64, 128])
+def test_orbit_and_table_paths_agree(n):
+    """Same transform through orbit-block launches and through per-row table
+    gathers (FP64 stages, FP32 data): both within 1e-5 of the fold reference
+    and within 1e-6 of each other."""
+    x = workloads.upsampled_field(n, seed=n)
+    p_orbit = fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT)
+    p_table = fcc.fcc_dct_plan_tuned(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT,
+                                     tuning=_tables_only(p_orbit))
+    xo, Xo, yo = _run(p_orbit, x, fcc.FCC_PREC_FP32, True)
+    _, Xt, yt = _run(p_table, x, fcc.FCC_PREC_FP32, True)
+    ref = fold_ref.fold_forward(x.astype(np.float64), n)
+    assert gu.maxrel(Xo.cpu().numpy(), ref) <= 1e-5
+    assert gu.maxrel(Xt.cpu().numpy(), ref) <= 1e-5
+    assert gu.maxrel(Xo.cpu().numpy(), Xt.cpu().numpy()) <= 1e-6
+    assert fcc.fcc_dct_roundtrip_residual(p_orbit, xo, yo) <= 1e-5
+    assert fcc.fcc_dct_roundtrip_residual(p_table, xo, yt) <= 1e-5
+
+
+@pytest.mark.parametrize("flags", [fcc.FCC_LEVEL0_FP32, fcc.FCC_STAGES_FP64])
+def test_orbit_precision_variants(flags):
+    n = 64
+    x = RNG.standard_normal(n ** 3).astype(np.float32)
+    plan = fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT | flags)
+    xt, X, y = _run(plan, x, fcc.FCC_PREC_FP32, True)
+    ref = fold_ref.fold_forward(x.astype(np.float64), n)
+    assert gu.maxrel(X.cpu().numpy(), ref) <= 1e-5
+    assert fcc.fcc_dct_roundtrip_residual(plan, xt, y) <= 1e-5
+
+
+def test_orbit_generic_skew():
+    n = 32
+    rst = (0.31, 0.07, 0.23)
+    x = RNG.standard_normal(n ** 3)
+    plan = fcc.fcc_dct_plan(n, rst=rst, prec=fcc.FCC_PREC_FP64, flags=fcc.FCC_REAL_INPUT)
+    _, X, y = _run(plan, x, fcc.FCC_PREC_FP64, True)
+    assert gu.maxrel(X.cpu().numpy(), fold_ref.fold_forward(x, n, rst)) <= 1e-9
+    assert gu.maxrel(y.cpu().numpy(), x) <= 1e-9
+
+
+def test_orbit_batched_matches_single():
+    """Volumes of mixed n through fcc_dct_batched (one launch per level per
+    size) give the single-volume results bit for bit."""
+    ns = [32, 64, 32, 64, 16]
+    xs_np = [RNG.standard_normal(n ** 3).astype(np.float32) for n in ns]
+    plans = {n: fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT) for n in set(ns)}
+    xs = [torch.from_numpy(x).to(gu.DEV) for x in xs_np]
+    outs = [torch.empty(n ** 3, dtype=torch.complex64, device=gu.DEV) for n in ns]
+    fcc.fcc_dct_batched([plans[n] for n in ns], xs, outs, 1)
+    torch.cuda.synchronize()
+    for i, n in enumerate(ns):
+        X = torch.empty(n ** 3, dtype=torch.complex64, device=gu.DEV)
+        fcc.fcc_dct_forward(plans[n], xs[i], X)
+        torch.cuda.synchronize()
+        assert torch.equal(X, outs[i]), (i, n)
+
+
+def test_n512_forward_rows_and_roundtrip():
+    """n = 512 (served only through orbit-block launches above node size 16):
+    sampled direct oracle rows and the FP64 round-trip residual."""
+    n = 512
+    x_np = workloads.upsampled_field(n, seed=5)
+    plan = fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT)
+    xt, X, y = _run(plan, x_np, fcc.FCC_PREC_FP32, True)
+    rows = gu.sample_rows(n, 4, 9)
+    ref = oracle.forward_rows(x_np.astype(np.float64), n, rows)
+    assert gu.maxrel(X.cpu().numpy()[rows], ref) <= 1e-5
+    assert fcc.fcc_dct_roundtrip_residual(plan, xt, y) <= 1e-5
