@@ -1,27 +1,36 @@
 """Benchmark of the fast FCC cosine transform on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5] [--no-cpu] [--autotune]
-                [--copy-calibration]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5|c1|c2|c3|c4] [--no-cpu] [--autotune]
+                [--copy-calibration] [--pmc-pass] [--summarize DIR]
 
 A step is one pass of the whole fast path over the workload's input, which is
-already resident in HBM.  Default workload (c2): one forward DCT_{64x64x64} of
-a smooth field (16 random Gaussians plus N(0, 0.01) noise, seed 1), FP32 data.
+already resident in HBM.  Default workload (c5): the ragged batch of 512
+volumes, n drawn from {8, 16, 32, 64, 128} (seed 4), N(0,1) FP32 data,
+forward then inverse in one replay of the recorded HIP graph.  Its line is the
+mixed-precision variant (n = 8 volumes on the split-BF16 MFMA path, the top
+level of the others in FP32 arithmetic, FP64 stages below); the split-only and
+the plain variant (FP32 data, FP64 stages) are reported beside it, with the
+n = 256 single-volume forward + inverse (c4).
 Other workloads:
   c1  n = 4, FP64, forward + inverse;
+  c2  n = 64 forward of a smooth field, FP32 data;
   c3  4096 blocks at n = 8 (8-bit levels / 255), dense split-BF16 MFMA path
       (the FP32 fast path on the same blocks is reported beside it);
   c4  n = 256 trilinear-upsampled field, FP32 data, forward + inverse, with the
-      FP64 round-trip residual computed on the GPU (the variant with the top
-      level in FP32 is reported beside it);
-  c5  ragged batch of 512 volumes, n in {8..128}, forward + inverse in one
-      graph replay, mixed precision within the workload's 1e-4: n = 8 volumes
-      on split-BF16 MFMA, the top level of the others in FP32 (FP64 below);
-      the split-only and the plain FP32 variants are reported beside it.
-Prints ONE JSON line: points/s, the roofline of the dominant kernel (its
-algorithmic bytes or flops per launch / its average duration, timed with HIP
-events on the launch stream) and the CPU oracle timed on a bounded sample.
+      FP64 round-trip residual computed on the GPU.
+Prints ONE JSON line: points/s, the roofline of the dominant kernel (the
+launch slot with the longest average duration, timed with start/stop events
+recorded by each launch on its own stream; its algorithmic bytes = the
+method's input and output of that launch, each element once, in the data
+precision) and the CPU oracle timed on a bounded sample.
+
+--pmc-pass runs only the workload's launch slots once, eagerly, in slot order
+(for rocprofv3 counter runs) and writes their list to gpurun_out/slots_<w>.json;
+--summarize DIR turns a counter run's CSV output in DIR into the traffic table
+of profiles/traffic_<w>.md.
 """
 import argparse
+import glob
 import json
 import os
 import sys
@@ -32,75 +41,30 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
 MFMA_BF16_PEAK_TFS = 2500.0  # dense BF16 MFMA
+KERNEL_SOURCES = ("paper_1807_10058_amd/csrc/fcc_dct.hip", "paper_1807_10058_amd/csrc/kernels.hpp",
+                  "paper_1807_10058_amd/csrc/orbit_level.hpp", "paper_1807_10058_amd/csrc/dense.hip",
+                  "paper_1807_10058_amd/csrc/orbits.inc")
+TRAFFIC_PROFILE = {"c2": "traffic_c2_n64_forward.md", "c4": "traffic_c4_n256_forward_inverse.md",
+                   "c5": "traffic_c5_ragged512_forward_inverse.md"}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c5", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-c4", action="store_true", help="c5: skip the n = 256 single-volume report beside the line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the workload, copy a 1 GiB device buffer once (the plain-copy reference for "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE scaling)")
     ap.add_argument("--autotune", action="store_true",
                     help="search the schedule before planning (setup, untimed) instead of the built-in one")
+    ap.add_argument("--pmc-pass", action="store_true", help="one eager pass of the launch slots only")
+    ap.add_argument("--summarize", metavar="DIR", help="write the traffic table of a counter run in DIR")
     return ap.parse_args()
-
-
-def launch_bytes(n, prec, stages64, real_in, direction, sched):
-    """Algorithmic bytes of each launch slot of a single-volume transform (each
-    element read once and written once), in the plan's launch order."""
-    N = n ** 3
-    io_c = 16 if prec == 0 else 8
-    io_r = 8 if prec == 0 else 4
-    st = 16 if stages64 else 8
-    D = n.bit_length() - 1
-    SPLIT = 16
-    if n == 1:
-        return [("k_copy1", N * ((io_r if real_in else io_c) + io_c))]
-    rin = io_r if real_in else io_c
-    out = []
-    if direction > 0:
-        Lt = max(0, D - sched["tail_levels"][0])  # levels Lt.. run in one fused LDS launch
-        # the DCT_2 pass of a two-pass level D - 2 runs with the last level
-        last2 = Lt == D - 1 and D >= 3 and bool(sched["map"][0][D - 2] & SPLIT)
-        for L in range(Lt):
-            bi = rin if L == 0 else st
-            if sched["map"][0][L] & SPLIT:
-                out.append(("k_fwd_gather L%d" % L, N * (bi + st)))
-                if not (last2 and L == D - 2):
-                    out.append(("k_fwd_dct2 L%d" % L, N * (st + st)))
-            else:
-                out.append(("k_fwd_level L%d" % L, N * (bi + st)))
-        if last2:
-            out.append(("k_fwd_dct2_last2 L%d-%d" % (D - 2, D - 1), N * (st + io_c)))
-        elif Lt == D - 1 and D >= 2:  # the last level alone: DCT_2 on the cubes
-            out.append(("k_fwd_dct2 L%d" % (D - 1), N * (st + io_c)))
-        else:
-            out.append(("k_fwd_tail L%d-%d" % (Lt, D - 1), N * ((rin if Lt == 0 else st) + io_c)))
-    else:
-        Lt = max(0, D - sched["tail_levels"][1])
-        # the last level and the DCT_2^-1 pass of level D - 2 run as one launch
-        last2 = Lt == D - 1 and D >= 3
-        if last2:
-            out.append(("k_inv_dct2_last2 L%d-%d" % (D - 1, D - 2), N * (io_c + st)))
-        elif Lt == D - 1 and D >= 2:  # the last level alone: DCT_2^-1 on the cubes
-            out.append(("k_inv_dct2 L%d" % (D - 1), N * (io_c + st)))
-        else:
-            out.append(("k_inv_tail L%d-%d" % (D - 1, Lt), N * (io_c + (rin if Lt == 0 else st))))
-        for L in range(Lt - 1, -1, -1):
-            if not (last2 and L == D - 2):
-                out.append(("k_inv_dct2 L%d" % L, N * (st + st)))
-            bo = rin if L == 0 else st
-            out.append(("k_inv_basis L%d" % L, N * (st + bo)))
-    return out
-
-
-KERNEL_SOURCES = ("paper_1807_10058_amd/csrc/fcc_dct.hip", "paper_1807_10058_amd/csrc/kernels.hpp",
-                  "paper_1807_10058_amd/csrc/dense.hip", "paper_1807_10058_amd/csrc/orbits.inc")
 
 
 def kernel_source_sha1():
@@ -113,15 +77,13 @@ def kernel_source_sha1():
 
 
 def measured_traffic(workload, slot):
-    """HBM bytes of one launch of `slot` from the committed rocprofv3 counter
-    profile of this workload (FETCH_SIZE and WRITE_SIZE scaled by a plain copy),
-    or None when there is none or the kernel sources changed since it was taken."""
+    """HBM bytes of one launch of `slot` (mean over the slots of that name) from
+    the committed rocprofv3 counter table of this workload, or None when there
+    is none or the kernel sources changed since it was taken."""
     import re
-    name = {"c2": "traffic_c2_n64_forward.md", "c4": "traffic_c4_n256_forward_inverse.md"}.get(workload)
-    if not name:
-        return None
-    path = os.path.join(ROOT, "profiles", name)
-    if not os.path.exists(path):
+    name = TRAFFIC_PROFILE.get(workload)
+    path = os.path.join(ROOT, "profiles", name) if name else None
+    if not path or not os.path.exists(path):
         return None
     text = open(path).read()
     m = re.search(r"kernel sources sha1: ([0-9a-f]{40})", text)
@@ -129,13 +91,23 @@ def measured_traffic(workload, slot):
         return None
     for line in text.splitlines():
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cells) >= 4 and cells[0] == slot:
+        if len(cells) >= 5 and cells[0] == slot:
             try:
-                return {"read_bytes": float(cells[2]), "write_bytes": float(cells[3]),
-                        "total_bytes": float(cells[2]) + float(cells[3]), "source": "profiles/" + name}
+                rd, wr = float(cells[2]), float(cells[3])
             except ValueError:
                 return None
+            return {"read_bytes": rd, "write_bytes": wr, "total_bytes": rd + wr, "source": "profiles/" + name}
     return None
+
+
+def roofline(workload, slots):
+    """Roofline entry of the dominant (slowest) launch slot."""
+    dom = max(slots, key=lambda s: s["ms"])
+    nbytes = dom["points"] * (dom["in_bytes"] + dom["out_bytes"])
+    achieved = nbytes / (dom["ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(workload, dom["name"]),
+            "launch_ms": dom["ms"], "algorithmic_bytes": nbytes}
 
 
 def cpu_baseline(x, n, seconds, rng_seed=11):
@@ -163,7 +135,6 @@ def time_steps(step, steps, warmup):
         step()
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     wall0 = time.perf_counter()
     ev0.record()
     for _ in range(steps):
@@ -171,6 +142,18 @@ def time_steps(step, steps, warmup):
     ev1.record()
     torch.cuda.synchronize()
     return ev0.elapsed_time(ev1) / steps, time.perf_counter() - wall0
+
+
+def single_slots(plan, pairs, reps):
+    """Timed launch slots of a single-volume plan: [(direction, src, dst)]."""
+    import paper_1807_10058_amd as fcc
+    out = []
+    for d, src, dst in pairs:
+        info = fcc.fcc_dct_describe_launches(plan, d)
+        times = fcc.fcc_dct_time_launches(plan, src, dst, d, reps=reps)
+        for i, t in zip(info, times):
+            out.append(dict(i, ms=float(t), direction="forward" if d > 0 else "inverse"))
+    return out
 
 
 def single_volume(args, name):
@@ -201,11 +184,12 @@ def single_volume(args, name):
     t0 = time.perf_counter()
     plan = fcc.fcc_dct_plan(n, prec=prec, flags=fcc.FCC_REAL_INPUT)
     plan_s = time.perf_counter() - t0
-    sched = fcc.fcc_dct_get_tuning(plan)
-    stages64 = prec == fcc.FCC_PREC_FP64 or n > 4
     x = torch.from_numpy(np.ascontiguousarray(x_np)).to(dev, rdt)
     X = torch.empty(n ** 3, dtype=cdt, device=dev)
     y = torch.empty(n ** 3, dtype=rdt, device=dev)
+    pairs = [(1, x, X)] + ([(-1, X, y)] if direction == 0 else [])
+    if args.pmc_pass:
+        return pmc_pass(name, lambda: single_slots(plan, pairs, 1))
 
     def step():
         fcc.fcc_dct_forward(plan, x, X)
@@ -213,20 +197,8 @@ def single_volume(args, name):
             fcc.fcc_dct_inverse(plan, X, y)
 
     ms, wall = time_steps(step, args.steps, args.warmup)
-    points = n ** 3
-    slots = []
-    direction_ms = {}
-    for d in ([1] if direction == 1 else [1, -1]):
-        src, dst = (x, X) if d == 1 else (X, y)
-        times = fcc.fcc_dct_time_launches(plan, src, dst, d, reps=max(5, min(args.steps, 50)))
-        direction_ms["forward" if d == 1 else "inverse"] = round(float(sum(times)), 5)
-        for (kname, nbytes), t in zip(launch_bytes(n, prec, stages64, True, d, sched), times):
-            slots.append((kname, nbytes, t))
-    kname, nbytes, tdom = max(slots, key=lambda s: s[2])
-    achieved = nbytes / (tdom * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name, kname), "launch_ms": tdom,
-            "algorithmic_bytes": nbytes}
+    slots = single_slots(plan, pairs, max(5, min(args.steps, 50)))
+    roof = roofline(name, slots)
     step()
     torch.cuda.synchronize()
     rows = sample_rows(n, 48, 5)
@@ -236,31 +208,63 @@ def single_volume(args, name):
            "rows": int(len(rows))}
     if direction == 0:
         acc["roundtrip_max_rel_fp64_gpu"] = fcc.fcc_dct_roundtrip_residual(plan, x, y)
-    cfg = {"workload": desc, "n": n, "points": points, "io_dtype": "f64" if prec == 0 else "f32",
-           "stages": "f64" if stages64 else "f32", "direction": "forward" if direction == 1 else "forward+inverse",
-           "plan_seconds": round(plan_s, 3), "autotune_seconds": round(tune_s, 3), "schedule": sched,
-           "wall_seconds_timed": round(wall, 4)}
-    # kernel time of each direction (sum of its launches, HIP events)
-    extra = {"launches_ms": {s[0]: round(s[2], 5) for s in slots}, "direction_kernel_ms": direction_ms,
+    cfg = {"workload": desc, "n": n, "points": n ** 3, "io_dtype": "f64" if prec == 0 else "f32",
+           "direction": "forward" if direction == 1 else "forward+inverse",
+           "plan_seconds": round(plan_s, 3), "autotune_seconds": round(tune_s, 3),
+           "schedule": fcc.fcc_dct_get_tuning(plan), "wall_seconds_timed": round(wall, 4)}
+    dirs = {}
+    for s in slots:
+        dirs[s["direction"]] = round(dirs.get(s["direction"], 0.0) + s["ms"], 5)
+    extra = {"launches_ms": {s["name"]: round(s["ms"], 5) for s in slots}, "direction_kernel_ms": dirs,
              "accuracy": acc}
-    if name == "c4":
-        # beside the line: the top level in FP32 (FP64 below), same input
-        p32 = fcc.fcc_dct_plan(n, prec=prec, flags=fcc.FCC_REAL_INPUT | fcc.FCC_LEVEL0_FP32)
+    dtype = "f64" if prec == fcc.FCC_PREC_FP64 else "f32 data, f64 stages"
+    return n ** 3, ms, dtype, cfg, roof, extra, (x_np, n)
 
-        def step32():
-            fcc.fcc_dct_forward(p32, x, X)
-            fcc.fcc_dct_inverse(p32, X, y)
 
-        ms32, _ = time_steps(step32, args.steps, args.warmup)
-        step32()
-        torch.cuda.synchronize()
-        X32 = X.cpu().numpy().astype(np.complex128)
-        extra["variants"] = {"level0_fp32": {
-            "ms_per_step": ms32, "points_per_s": points / (ms32 * 1e-3),
-            "accuracy": {"forward_max_rel_sampled": float(np.abs(X32[rows] - ref).max() / np.abs(ref).max()),
-                         "roundtrip_max_rel_fp64_gpu": fcc.fcc_dct_roundtrip_residual(p32, x, y)}}}
-        fcc.fcc_dct_destroy(p32)
-    return points, ms, "f64" if stages64 else "f32", cfg, roof, extra, (x_np, n)
+def pmc_pass(name, run_slots):
+    """One eager pass of the launch slots (for counter runs); writes their list."""
+    import torch
+    slots = run_slots()
+    torch.cuda.synchronize()
+    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+    path = os.path.join(ROOT, "gpurun_out", "slots_%s.json" % name)
+    with open(path, "w") as f:
+        json.dump([{k: s[k] for k in ("name", "points", "in_bytes", "out_bytes")} for s in slots], f)
+    print(json.dumps({"pmc_pass": name, "slots": len(slots), "list": path}), flush=True)
+    return None
+
+
+def c4_beside(args):
+    """The n = 256 single-volume forward + inverse, reported beside the c5 line."""
+    import numpy as np
+    import torch
+
+    import paper_1807_10058_amd as fcc
+    import workloads
+    n = 256
+    dev = torch.device("cuda:0")
+    x_np = workloads.upsampled_field(n, 3)
+    plan = fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT)
+    x = torch.from_numpy(np.ascontiguousarray(x_np)).to(dev)
+    X = torch.empty(n ** 3, dtype=torch.complex64, device=dev)
+    y = torch.empty_like(x)
+
+    def step():
+        fcc.fcc_dct_forward(plan, x, X)
+        fcc.fcc_dct_inverse(plan, X, y)
+
+    ms, _ = time_steps(step, max(5, args.steps // 2), 2)
+    slots = single_slots(plan, [(1, x, X), (-1, X, y)], 10)
+    roof = roofline("c4", slots)
+    dirs = {}
+    for s in slots:
+        dirs[s["direction"]] = round(dirs.get(s["direction"], 0.0) + s["ms"], 5)
+    step()
+    torch.cuda.synchronize()
+    return {"workload": "c4: n=256 forward+inverse, trilinear-upsampled field, FP32 data, FP64 stages",
+            "ms_per_step": ms, "points_per_s": n ** 3 / (ms * 1e-3), "direction_kernel_ms": dirs,
+            "roofline": roof, "roundtrip_max_rel_fp64_gpu": fcc.fcc_dct_roundtrip_residual(plan, x, y),
+            "step_frac_of_hbm_floor": (n ** 3 * 28) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def batched(args, name):
@@ -293,10 +297,10 @@ def batched(args, name):
                 fcc.fcc_dct_autotune(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT, reps=3)
     tune_s = time.perf_counter() - t0
 
-    def plan_for(n, prec):
-        if (n, prec) not in cache:
-            cache[(n, prec)] = fcc.fcc_dct_plan(n, prec=prec, flags=fcc.FCC_REAL_INPUT)
-        return cache[(n, prec)]
+    def plan_for(n, prec, flags=fcc.FCC_REAL_INPUT):
+        if (n, prec, flags) not in cache:
+            cache[(n, prec, flags)] = fcc.fcc_dct_plan(n, prec=prec, flags=flags)
+        return cache[(n, prec, flags)]
 
     if name == "c3":
         flat = torch.from_numpy(np.ascontiguousarray(blocks)).to(dev)
@@ -306,19 +310,27 @@ def batched(args, name):
     outs = [torch.empty(n ** 3, dtype=torch.complex64, device=dev) for n in ns]
 
     def plan_for_variant(n, variant):
-        # split: split-BF16 dense path for n <= 8; mixed: that, and the top level
-        # in FP32 for larger n (round trip ~4e-6, within the 1e-4 of this workload)
+        # split: the split-BF16 dense MFMA path for n <= 8; mixed: that, and the
+        # top level in FP32 arithmetic for larger n (FP64 stages below)
         if variant in ("split", "mixed") and n <= 8:
             return plan_for(n, fcc.FCC_PREC_SPLIT_BF16)
         if variant == "mixed":
-            key = (n, "level0_fp32")
-            if key not in cache:
-                cache[key] = fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP32,
-                                              flags=fcc.FCC_REAL_INPUT | fcc.FCC_LEVEL0_FP32)
-            return cache[key]
+            return plan_for(n, fcc.FCC_PREC_FP32, fcc.FCC_REAL_INPUT | fcc.FCC_LEVEL0_FP32)
         return plan_for(n, fcc.FCC_PREC_FP32)
 
-    def run(variant):
+    main_variant = "split" if name == "c3" else "mixed"
+    if args.pmc_pass:
+        plans = [plan_for_variant(n, main_variant) for n in ns]
+        return pmc_pass(name, lambda: fcc.fcc_dct_batched_time_launches(plans, xs, outs, direction, reps=1))
+
+    originals = [x.clone() for x in xs] if direction == 0 else None
+    res = {}
+    slots_main = None
+    variants = ("split", "fp32") if name == "c3" else ("mixed", "split", "fp32")
+    for variant in variants:
+        if direction == 0:
+            for x, o in zip(xs, originals):
+                x.copy_(o)
         plans = [plan_for_variant(n, variant) for n in ns]
         step = fcc.BatchedCall(plans, xs, outs, direction)
         t0 = time.perf_counter()
@@ -326,16 +338,8 @@ def batched(args, name):
         torch.cuda.synchronize()
         build_s = time.perf_counter() - t0
         ms, wall = time_steps(step, args.steps, args.warmup)
-        return plans, step, ms, wall, build_s
-
-    originals = [x.clone() for x in xs] if direction == 0 else None
-    res = {}
-    variants = ("split", "fp32") if name == "c3" else ("mixed", "split", "fp32")
-    for variant in variants:
-        if direction == 0:
-            for x, o in zip(xs, originals):
-                x.copy_(o)
-        plans, step, ms, wall, build_s = run(variant)
+        if variant == main_variant:
+            slots_main = fcc.fcc_dct_batched_time_launches(plans, xs, outs, direction, reps=3)
         # accuracy: forward outputs vs oracle (sampled), round trip vs input
         if direction == 0:
             for x, o in zip(xs, originals):
@@ -358,29 +362,110 @@ def batched(args, name):
             acc["roundtrip_max_rel"] = worst_rt
         res[variant] = {"ms_per_step": ms, "points_per_s": points / (ms * 1e-3), "accuracy": acc,
                         "graph_build_s": round(build_s, 3), "wall_seconds_timed": round(wall, 4)}
-    main = res["split"] if name == "c3" else res["mixed"]
+        fcc.fcc_dct_batched_release()
+    main = res[main_variant]
     if name == "c3":
         # one GEMM launch per step: out[4096 x 1024] = in[4096 x 512] W^T, 3 split products
         flops = 2.0 * 4096 * 1024 * 512 * 3
-        achieved = flops / (main["ms_per_step"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "kernel": "k_split_gemm<bf16>", "achieved": achieved,
+        t = slots_main[0]["ms"]
+        achieved = flops / (t * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": slots_main[0]["name"], "achieved": achieved,
                 "peak": MFMA_BF16_PEAK_TFS, "unit": "TFLOP/s", "frac": achieved / MFMA_BF16_PEAK_TFS,
-                "traffic": None, "launch_ms": main["ms_per_step"], "algorithmic_flops": flops}
+                "traffic": None, "launch_ms": t, "algorithmic_flops": flops}
         dtype = "bf16x3 (split) / f32 acc"
     else:
-        # dominant kernels are the fast-path levels of the n = 128 volumes; report the whole-step
-        # algorithmic bytes (FP32 in 4 + complex64 out 8, then back) over the step time
-        nbytes = points * (4 + 8 + 8 + 4)
-        achieved = nbytes / (main["ms_per_step"] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": "whole step (graph replay)", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "launch_ms": main["ms_per_step"], "algorithmic_bytes": nbytes}
-        dtype = "f64 stages, f32 top level (n >= 16); bf16x3 split (n = 8)"
+        roof = roofline(name, slots_main)
+        dtype = "mixed: f32 top level + f64 stages (n >= 16), bf16x3 split MFMA (n = 8); f32 data"
     cfg = {"workload": desc, "volumes": len(ns), "points": points, "io_dtype": "f32",
-           "sizes": {str(k): ns.count(k) for k in sorted(set(ns))}, "autotune_seconds": round(tune_s, 3)}
-    extra = {"variants": res, "accuracy": main["accuracy"]}
+           "sizes": {str(k): ns.count(k) for k in sorted(set(ns))}, "autotune_seconds": round(tune_s, 3),
+           "variants": {"mixed": "split-BF16 MFMA for n = 8; FP32 top level, FP64 stages below for n >= 16",
+                        "split": "split-BF16 MFMA for n = 8; FP64 stages for n >= 16",
+                        "fp32": "FP32 data, FP64 stages for every n (plain fast path)"}}
+    slot_ms = {}
+    for s in slots_main:
+        slot_ms[s["name"]] = round(slot_ms.get(s["name"], 0.0) + s["ms"], 5)
+    extra = {"variants": res, "accuracy": main["accuracy"], "slot_ms_sum": round(sum(slot_ms.values()), 4),
+             "launches_ms": slot_ms}
+    if name == "c5" and not args.no_c4:
+        extra["c4_beside"] = c4_beside(args)
     big = max(range(len(ns)), key=lambda i: ns[i])
     return points, main["ms_per_step"], dtype, cfg, roof, extra, (xs_np[big], ns[big])
+
+
+def _fcc_dispatches(rows):
+    """(dispatch id, kernel name) of the transform's own kernels, in dispatch order."""
+    out = [(d, kn) for d, kn in rows if "fcc::k_" in kn]
+    return [r for r in out if "k_phase_table" not in r[1] and "k_node_table" not in r[1]]
+
+
+def summarize(directory, workload):
+    """Per-slot tables of a --pmc-pass run under rocprofv3 (the last len(slots)
+    transform dispatches are the slots, in order): from a kernel trace
+    (DIR/prof_<w>: durations) or from a FETCH_SIZE and a WRITE_SIZE counter
+    run (DIR/pmc_<w>_FETCH_SIZE, DIR/pmc_<w>_WRITE_SIZE, each ending with the
+    1 GiB calibration copy of --copy-calibration)."""
+    import csv
+    slots = json.load(open(os.path.join(ROOT, "gpurun_out", "slots_%s.json" % workload)))
+    print("kernel sources sha1: %s" % kernel_source_sha1())
+    trace = glob.glob(os.path.join(directory, "prof_%s" % workload, "**", "*kernel_trace.csv"), recursive=True)
+    if trace:
+        rows = []
+        for r in csv.DictReader(open(trace[0])):
+            rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+        rows.sort()
+        dur = {d: t for d, _, t in rows}
+        last = _fcc_dispatches([(d, kn) for d, kn, _ in rows])[-len(slots):]
+        agg = {}
+        for sl, (d, kn) in zip(slots, last):
+            a = agg.setdefault(sl["name"], {"kernel": kn, "k": 0, "ns": 0.0, "alg": 0.0})
+            a["k"] += 1
+            a["ns"] += dur[d]
+            a["alg"] += sl["points"] * (sl["in_bytes"] + sl["out_bytes"])
+        print("| Slot | Kernel | Launches | Trace mean (us) | Algorithmic GB/s |")
+        print("|:--|:--|--:|--:|--:|")
+        for nm, a in agg.items():
+            print("| %s | %s | %d | %.2f | %.0f |" % (nm, a["kernel"].replace("void fcc::", "").split("(")[0], a["k"],
+                                                     a["ns"] / a["k"] / 1e3, a["alg"] / a["ns"]))
+    if not glob.glob(os.path.join(directory, "pmc_%s_FETCH_SIZE" % workload)):
+        return
+    vals = {}
+    for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+        files = glob.glob(os.path.join(directory, "pmc_%s_%s" % (workload, counter), "**", "*counter_collection.csv"),
+                          recursive=True)
+        if not files:
+            raise SystemExit("no counter_collection.csv for %s under %s" % (counter, directory))
+        per, names = {}, {}
+        for r in csv.DictReader(open(files[0])):
+            d = int(r["Dispatch_Id"])
+            per[d] = per.get(d, 0.0) + float(r["Counter_Value"])
+            names[d] = r["Kernel_Name"]
+        order = sorted(per)
+        copies = [d for d in order if "copyBuffer" in names[d]]
+        calib = per[copies[-1]] if copies else None
+        last = _fcc_dispatches([(d, names[d]) for d in order])[-len(slots):]
+        vals[counter] = ([per[d] for d, _ in last], [kn for _, kn in last], calib)
+    fetch, names, cal_f = vals["FETCH_SIZE"]
+    write, _, cal_w = vals["WRITE_SIZE"]
+    gib_kib = 1 << 20
+    f_scale = gib_kib / cal_f if cal_f else 2.0
+    w_scale = gib_kib / cal_w if cal_w else 1.0
+    agg = {}
+    for sl, kn, f, w in zip(slots, names, fetch, write):
+        a = agg.setdefault(sl["name"], {"kernel": kn, "k": 0, "f": 0.0, "w": 0.0, "alg": 0.0})
+        a["k"] += 1
+        a["f"] += f * f_scale * 1024
+        a["w"] += w * w_scale * 1024
+        a["alg"] += sl["points"] * (sl["in_bytes"] + sl["out_bytes"])
+    print("read bytes = %.4f x FETCH_SIZE x 1024, written bytes = %.4f x WRITE_SIZE x 1024 "
+          "(the 1 GiB copy reads FETCH_SIZE %.0f KiB, writes WRITE_SIZE %.0f KiB)" % (f_scale, w_scale, cal_f or 0,
+                                                                                    cal_w or 0))
+    print("| Slot | Kernel | Read bytes | Written bytes | Algorithmic bytes | Measured / algorithmic |")
+    print("|:--|:--|--:|--:|--:|--:|")
+    for nm, a in agg.items():
+        k = a["k"]
+        print("| %s | %s | %.0f | %.0f | %.0f | %.2f |" % (nm, a["kernel"].replace("void fcc::", "").split("(")[0],
+                                                           a["f"] / k, a["w"] / k, a["alg"] / k,
+                                                           (a["f"] + a["w"]) / a["alg"]))
 
 
 def main():
@@ -388,10 +473,18 @@ def main():
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.summarize:
+        summarize(args.summarize, args.workload)
+        return
     if args.workload in ("c1", "c2", "c4"):
-        points, ms, dtype, cfg, roof, extra, cpu_case = single_volume(args, args.workload)
+        r = single_volume(args, args.workload)
     else:
-        points, ms, dtype, cfg, roof, extra, cpu_case = batched(args, args.workload)
+        r = batched(args, args.workload)
+    if r is None:  # --pmc-pass
+        if args.copy_calibration:
+            copy_calibration()
+        return
+    points, ms, dtype, cfg, roof, extra, cpu_case = r
     out = {
         "metric": "FCC-DCT points/s", "value": points / (ms * 1e-3), "unit": "points/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
@@ -400,14 +493,18 @@ def main():
     }
     out.update(extra)
     if args.copy_calibration:
-        import torch
-        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0")
-        b = a.clone()
-        torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = int(b.numel() * 4)
+        out["copy_calibration_bytes"] = copy_calibration()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cpu_case[0], cpu_case[1], args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def copy_calibration():
+    import torch
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0")
+    b = a.clone()
+    torch.cuda.synchronize()
+    return int(b.numel() * 4)
 
 
 if __name__ == "__main__":

@@ -151,18 +151,28 @@ def test_batched_groups_respect_schedules():
 @pytest.mark.parametrize("split", [True, False])
 def test_launch_slots_match_the_bench_accounting(n, tail, split):
     """The launch slots fcc_dct_time_launches reports (including the fused
-    last-level launches) are the ones bench.py prices, in number and order."""
-    import bench
+    last-level launches and the orbit-block levels) are the ones
+    fcc_dct_describe_launches names and bench.py prices, in number and order:
+    each slot reads and writes the method's elements once (FP32 data: real
+    input 4 bytes at the top of the forward and the bottom of the inverse,
+    complex 8 bytes elsewhere)."""
     maps = (SP, SP, 0, 0) if split else (0, 0, 0, 0)
     t = tuning(tail=tail, maps=maps, deep=(SP if split else 0, 0))
-    plan = fcc.fcc_dct_plan_tuned(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT, tuning=t)
-    sched = fcc.fcc_dct_get_tuning(plan)
-    x = torch.rand(n ** 3, device=gu.DEV)
-    X = torch.empty(n ** 3, dtype=torch.complex64, device=gu.DEV)
-    y = torch.empty(n ** 3, device=gu.DEV)
-    for d, (src, dst) in ((1, (x, X)), (-1, (X, y))):
-        ms = fcc.fcc_dct_time_launches(plan, src, dst, d, reps=1)
-        slots = bench.launch_bytes(n, fcc.FCC_PREC_FP32, True, True, d, sched)
-        assert len(ms) == len(slots), (n, tail, split, d, [s[0] for s in slots])
-        assert all(v > 0 for v in ms)
-    fcc.fcc_dct_destroy(plan)
+    for orbit in (False, True):
+        if orbit:
+            t["map"] = [[m | (fcc.FCC_MAP_ORBIT if (n >> L) >= 32 else 0) for L, m in enumerate(row)]
+                        for row in t["map"]]
+        plan = fcc.fcc_dct_plan_tuned(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT, tuning=t)
+        x = torch.rand(n ** 3, device=gu.DEV)
+        X = torch.empty(n ** 3, dtype=torch.complex64, device=gu.DEV)
+        y = torch.empty(n ** 3, device=gu.DEV)
+        for d, (src, dst) in ((1, (x, X)), (-1, (X, y))):
+            ms = fcc.fcc_dct_time_launches(plan, src, dst, d, reps=1)
+            slots = fcc.fcc_dct_describe_launches(plan, d)
+            assert len(ms) == len(slots), (n, tail, split, d, [s["name"] for s in slots])
+            assert all(v > 0 for v in ms)
+            assert all(s["points"] == n ** 3 for s in slots)
+            assert slots[0]["in_bytes"] == (4 if d > 0 else 8) and slots[-1]["out_bytes"] == (8 if d > 0 else 4)
+            assert all(s["in_bytes"] == 8 for s in slots[1:]) and all(s["out_bytes"] == 8 for s in slots[:-1])
+            assert any("orbit" in s["name"] for s in slots) == (orbit and n >= 32)
+        fcc.fcc_dct_destroy(plan)
