@@ -641,13 +641,14 @@ __global__ __launch_bounds__(256) void k_fwd_level(VolSet vs, int nvol, int n, i
 
 // y <- DCT_2(phi) y = H_8 A(phi) y for the 8 values of one cube of node J at
 // level L (nodes: the level's node table, or null to form A from the phases).
+// (direct: `nodes` points at node J's own entry, e.g. a copy in LDS.)
 template <typename R>
 __device__ __forceinline__ void dct2_apply(const NodeConst* nodes, const double2* __restrict__ hph, int L,
-                                           const int J[3], cx<R> y[8]) {
+                                           const int J[3], cx<R> y[8], bool direct = false) {
   cx<R> tt[8];
   const int c4[4] = {1, 3, 4, 6}, c3[3] = {2, 5, 7};
   if (nodes) {
-    const NodeConst& nc = nodes[((long long)J[0] << (2 * L)) | ((long long)J[1] << L) | J[2]];
+    const NodeConst& nc = direct ? nodes[0] : nodes[((long long)J[0] << (2 * L)) | ((long long)J[1] << L) | J[2]];
     tt[0] = y[0];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -745,12 +746,12 @@ __global__ __launch_bounds__(256) void k_fwd_dct2_last2(VolSet vs, int nvol, int
 // node J at level L (4x4 and 3x3 solves with partial pivoting).
 template <typename R>
 __device__ __forceinline__ void idct2_apply(const NodeConst* nodes, const double2* __restrict__ hph, int L,
-                                            const int J[3], cx<R> z[8]) {
+                                            const int J[3], cx<R> z[8], bool direct = false) {
   hadamard8(z);
   const int c4[4] = {1, 3, 4, 6}, c3[3] = {2, 5, 7};
   cx<R> a4[4][4], a3[3][3];
   if (nodes) {
-    const NodeConst& nc = nodes[((long long)J[0] << (2 * L)) | ((long long)J[1] << L) | J[2]];
+    const NodeConst& nc = direct ? nodes[0] : nodes[((long long)J[0] << (2 * L)) | ((long long)J[1] << L) | J[2]];
 #pragma unroll
     for (int i = 0; i < 16; ++i) a4[i / 4][i % 4] = ldc<R>(nc.a4[i]);
 #pragma unroll
@@ -772,6 +773,38 @@ __device__ __forceinline__ void idct2_apply(const NodeConst* nodes, const double
   for (int i = 0; i < 4; ++i) z[c4[i]] = b4[i];
 #pragma unroll
   for (int i = 0; i < 3; ++i) z[c3[i]] = b3[i];
+}
+
+// Dense DCT_2(phi) = H_8 A(phi) and its inverse A(phi)^{-1} H_8 / 8 of every
+// node of one level, for the orbit-block launches: column-major 8 x 8 FP64
+// complex, D[f * 8 + i] = DCT_2[i][f] and Dinv[i * 8 + f] = DCT_2^{-1}[f][i]
+// (the column a cube's value f, or i, multiplies).  The inverse columns are
+// the solves of A (partial pivoting) for the unit vectors e_i.
+struct OrbitNode {
+  double2 D[64];
+  double2 Dinv[64];
+};
+__global__ void k_orbit_nodes(OrbitNode* out, int L, const double2* __restrict__ hph) {
+  const long long node = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= (1LL << (3 * L))) return;
+  const int mask = (1 << L) - 1;
+  const int J[3] = {int(node >> (2 * L)), int((node >> L) & mask), int(node & mask)};
+  cx<double> Q[3][3];
+  node_pos_powers(hph, L, J, Q);
+  OrbitNode& on = out[node];
+  for (int f = 0; f < 8; ++f) {
+    cx<double> y[8], t[8];
+    for (int k = 0; k < 8; ++k) y[k] = {k == f ? 1.0 : 0.0, 0.0};
+    apply_A(Q, y, t);
+    hadamard8(t);
+    for (int i = 0; i < 8; ++i) on.D[f * 8 + i] = make_double2(t[i].x, t[i].y);
+  }
+  for (int i = 0; i < 8; ++i) {
+    cx<double> z[8];
+    for (int k = 0; k < 8; ++k) z[k] = {k == i ? 1.0 : 0.0, 0.0};
+    idct2_apply<double>(nullptr, hph, L, J, z, false);
+    for (int f = 0; f < 8; ++f) on.Dinv[i * 8 + f] = make_double2(z[f].x, z[f].y);
+  }
 }
 
 // Inverse level L, first pass: y = DCT_2(phi)^{-1} z = A(phi)^{-1} H_8 z / 8 on every cube.
@@ -1191,8 +1224,12 @@ __global__ __launch_bounds__(256) void k_residual(const T* __restrict__ x, const
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x) {
     const cx<double> a = IO<T, double>::ld(x, i), b = IO<T, double>::ld(y, i);
     const double dx = a.x - b.x, dy = a.y - b.y;
-    dmax = fmax(dmax, sqrt(dx * dx + dy * dy));
-    xmax = fmax(xmax, sqrt(a.x * a.x + a.y * a.y));
+    // a NaN difference counts as infinitely large (fmax below would drop it)
+    double d = sqrt(dx * dx + dy * dy), m = sqrt(a.x * a.x + a.y * a.y);
+    if (d != d) d = INFINITY;
+    if (m != m) m = INFINITY;
+    dmax = fmax(dmax, d);
+    xmax = fmax(xmax, m);
   }
   __shared__ double sd[256], sx[256];
   sd[threadIdx.x] = dmax;
@@ -1507,14 +1544,15 @@ fcc_status device_level(int dev, int nl, int S, CubeOrder ob, CubeOrder oc, DevL
 
 // ---- orbit-block templates on the device (see orbit_level.hpp) --------------
 
-// Cube slots of one kind in wavefront order: quads of 4 slots whose rows have
-// the same lengths first (no lane of a wavefront waits for another), then the
-// rest by decreasing row total; -1 pads the last quad.
-std::vector<int16_t> quad_order(const std::vector<int>& rowptr, int nc) {
-  std::map<std::array<int, 8>, std::vector<int>> byprof;
+// Cube slots of one kind in wavefront order: quads of 4 slots whose segments
+// have the same lengths first (no lane of a wavefront waits for another),
+// then the rest by decreasing total; -1 pads the last quad.
+std::vector<int16_t> quad_order(const std::vector<int>& segptr, int nc) {
+  constexpr int kSeg = 8 * kNumMono;  // segments per cube slot
+  std::map<std::vector<int>, std::vector<int>> byprof;
   for (int j = 0; j < nc; ++j) {
-    std::array<int, 8> pr{};
-    for (int f = 0; f < 8; ++f) pr[f] = rowptr[j * 8 + f + 1] - rowptr[j * 8 + f];
+    std::vector<int> pr(kSeg);
+    for (int k = 0; k < kSeg; ++k) pr[k] = segptr[j * kSeg + k + 1] - segptr[j * kSeg + k];
     byprof[pr].push_back(j);
   }
   std::vector<int16_t> out;
@@ -1534,8 +1572,9 @@ std::vector<int16_t> quad_order(const std::vector<int>& rowptr, int nc) {
 }
 
 // Templates and representatives of node size nl on device dev (cached; the
-// caller holds the cache lock).  FCC_ERR_UNSUPPORTED if a kind does not fit
-// the kernels' LDS arrays.
+// caller holds the cache lock).  Rows are split by monomial with integer
+// coefficients (see DevOrbitLevel).  FCC_ERR_UNSUPPORTED if a kind does not
+// fit the kernels' LDS arrays or a coefficient is not a 16-bit multiple of 1/144.
 fcc_status device_orbit_level(int dev, int nl, DevOrbitLevel* out) {
   static std::map<std::array<int, 2>, DevOrbitLevel> levels;
   const std::array<int, 2> key{dev, nl};
@@ -1546,10 +1585,10 @@ fcc_status device_orbit_level(int dev, int nl, DevOrbitLevel* out) {
   }
   const OrbitBlocks* ob = orbit_blocks(nl);
   if (!ob) return FCC_ERR_UNSUPPORTED;
-  if (ob->npoly > kMaxPoly) return FCC_ERR_UNSUPPORTED;
   std::vector<DevOrbitKind> kinds;
   std::vector<int16_t> perm;
-  std::vector<uint16_t> rowptr, ent;
+  std::vector<uint16_t> rowptr;
+  std::vector<uint32_t> ent;
   std::vector<int8_t> wmat;
   std::vector<uint32_t> reps;
   std::vector<int4> chunks;
@@ -1562,22 +1601,40 @@ fcc_status device_orbit_level(int dev, int nl, DevOrbitLevel* out) {
     k.off_w = int(wmat.size());
     for (int j = 0; j < T.nc; ++j)
       for (int i = 0; i < 9; ++i) wmat.push_back(int8_t(G[T.w[j]][i]));
+    while (wmat.size() % 16) wmat.push_back(0);
     for (int side = 0; side < 2; ++side) {
       const std::vector<int>& rp = side ? T.c_rowptr : T.b_rowptr;
       const std::vector<uint16_t>& en = side ? T.c_ent : T.b_ent;
-      if (en.size() > size_t(kOrbitMaxEnt)) return FCC_ERR_UNSUPPORTED;
+      std::vector<int> seg(1, 0);
+      std::vector<uint32_t> se;
+      for (int r = 0; r < 8 * T.nc; ++r)
+        for (int q = 0; q < kNumMono; ++q) {
+          for (int e = rp[r]; e < rp[r + 1]; ++e) {
+            const double c = ob->poly[size_t(en[e] & 255u) * kNumMono + q] * 144.0;
+            const long long kc = std::llround(c);
+            if (kc == 0) continue;
+            if (std::fabs(c - double(kc)) > 1e-9 || kc < -32768 || kc > 32767) return FCC_ERR_UNSUPPORTED;
+            se.push_back((uint32_t(en[e] >> 8) << 16) | (uint32_t(kc) & 0xffffu));
+          }
+          seg.push_back(int(se.size()));
+        }
+      if (se.size() > size_t(kOrbitMaxEnt)) return FCC_ERR_UNSUPPORTED;
       k.off_rowptr[side] = int(rowptr.size());
-      for (int v : rp) rowptr.push_back(uint16_t(v));
+      for (int v : seg) rowptr.push_back(uint16_t(v));
+      while (rowptr.size() % 8) rowptr.push_back(0);
       k.off_ent[side] = int(ent.size());
-      ent.insert(ent.end(), en.begin(), en.end());
+      k.nent[side] = int(se.size());
+      ent.insert(ent.end(), se.begin(), se.end());
+      while (ent.size() % 4) ent.push_back(0);
       k.off_perm[side] = int(perm.size());
-      const std::vector<int16_t> q = quad_order(rp, T.nc);
+      const std::vector<int16_t> q = quad_order(seg, T.nc);
       perm.insert(perm.end(), q.begin(), q.end());
+      while (perm.size() % 8) perm.push_back(-1);
     }
     kinds.push_back(k);
     const std::vector<uint32_t>& r = ob->reps[t];
-    for (size_t r0 = 0; r0 < r.size(); r0 += kOrbitUnits)
-      chunks.push_back(make_int4(int(t), int(reps.size() + r0), int(std::min<size_t>(kOrbitUnits, r.size() - r0)), 0));
+    for (size_t r0 = 0; r0 < r.size(); r0 += kOrbitChunk)
+      chunks.push_back(make_int4(int(t), int(reps.size() + r0), int(std::min<size_t>(kOrbitChunk, r.size() - r0)), 0));
     reps.insert(reps.end(), r.begin(), r.end());
   }
   DevOrbitLevel lv{};
@@ -1589,11 +1646,8 @@ fcc_status device_orbit_level(int dev, int nl, DevOrbitLevel* out) {
   if (s == FCC_OK) s = upload(wmat, &lv.wmat);
   if (s == FCC_OK) s = upload(reps, &lv.reps);
   if (s == FCC_OK) s = upload(chunks, &lv.chunks);
-  if (s == FCC_OK) s = upload(ob->poly, &lv.poly);
   if (s != FCC_OK) return s;
   lv.nchunk = int(chunks.size());
-  lv.npoly = ob->npoly;
-  lv.nconst = ob->nconst;
   lv.lgm = 0;
   while ((1 << lv.lgm) < ob->m) ++lv.lgm;
   levels.emplace(key, lv);
@@ -1794,8 +1848,8 @@ void fwd_level_dispatch(const fcc_plan_s* p, int L, DT ti, DT to, const VolSet& 
 // launch (orbit_level.hpp): the schedule asks for it, the node size is at
 // least 16, the level is above the fused tail and its templates are on the GPU.
 bool orbit_at(const fcc_plan_s* p, int d, int L) {
-  return L < 10 && (p->tune.map[d][L] & FCC_MAP_ORBIT) && (p->n >> L) >= 16 && L < p->tail_Lt[d] &&
-         L < int(p->olv.size()) && p->olv[L].kinds != nullptr;
+  return L < 10 && (p->tune.map[d][L] & FCC_MAP_ORBIT) && (p->n >> L) >= 8 && L < p->tail_Lt[d] &&
+         L < int(p->olv.size()) && p->olv[L].kinds != nullptr && p->onodes && p->onode_off[L] >= 0;
 }
 bool fwd_split(const fcc_plan_s* p, int L) { return !orbit_at(p, 0, L) && (p->tune.map[0][L] & FCC_MAP_SPLIT) != 0; }
 // The DCT_2 pass of level D - 2 and the last level run as one launch: the
@@ -1807,8 +1861,9 @@ bool fwd_last2(const fcc_plan_s* p) {
 }
 // The inverse counterpart: the last level alone, then the DCT_2^{-1} pass of
 // level D - 2, as one launch.
+bool orbit_at(const fcc_plan_s* p, int d, int L);
 bool inv_last2(const fcc_plan_s* p) {
-  return p->D >= 3 && p->tail_Lt[1] == p->D - 1 && buf_type(p, p->D - 1) == stage_type(p) &&
+  return p->D >= 3 && p->tail_Lt[1] == p->D - 1 && buf_type(p, p->D - 1) == stage_type(p) && !orbit_at(p, 1, p->D - 2) &&
          arith64(p, p->D - 2) == arith64(p, p->D - 1);
 }
 // number of launch slots of one transform in direction d (0 forward, 1 inverse)
@@ -1894,13 +1949,16 @@ std::vector<SlotDesc> describe_slots(const fcc_plan_s* p, int d) {
 
 // ---- orbit-block level launches -------------------------------------------
 dim3 orbit_grid(const fcc_plan_s* p, int L, int nvol) {
-  const long long total = (long long)p->olv[L].nchunk * (1LL << (3 * L)) * nvol;
+  const long long total = orbit_blocks_total(p->olv[L].nchunk, L, nvol);
   return dim3(unsigned(((total + 7) >> 3) << 3));
+}
+const OrbitNode* onodes_of(const fcc_plan_s* p, int L) {
+  return static_cast<const OrbitNode*>(p->onodes) + p->onode_off[L];
 }
 template <typename R, typename TI, typename TO>
 void fwd_orbit_launch(const fcc_plan_s* p, int L, const VolSet& vs, int nvol, hipStream_t st) {
   launch((k_fwd_orbit<R, TI, TO>), orbit_grid(p, L, nvol), dim3(kOrbitThreads), 0, st, vs, nvol, p->n, L, p->olv[L],
-         phases(p, L), nodes_of(p, L));
+         phases(p, L), onodes_of(p, L));
 }
 void fwd_orbit_dispatch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, int nvol, hipStream_t st) {
   if (arith64(p, L)) {
@@ -1921,7 +1979,7 @@ void fwd_orbit_dispatch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, int
 template <typename R, typename TI, typename TO>
 void inv_orbit_launch(const fcc_plan_s* p, int L, const VolSet& vs, int nvol, hipStream_t st) {
   launch((k_inv_orbit<R, TI, TO>), orbit_grid(p, L, nvol), dim3(kOrbitThreads), 0, st, vs, nvol, p->n, L, p->olv[L],
-         phases(p, L), nodes_of(p, L));
+         phases(p, L), onodes_of(p, L));
 }
 void inv_orbit_dispatch(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int nvol, hipStream_t st) {
   if (arith64(p, L)) {
@@ -2724,7 +2782,7 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
   // coordinates in 8 bits (node size <= 256).
   bool tables[16] = {};
   for (int L = 0; L < p->D; ++L) {
-    const bool orb = (n >> L) >= 16 && L < 10 && (p->tune.map[0][L] & FCC_MAP_ORBIT) &&
+    const bool orb = (n >> L) >= 8 && L < 10 && (p->tune.map[0][L] & FCC_MAP_ORBIT) &&
                      (p->tune.map[1][L] & FCC_MAP_ORBIT);
     tables[L] = !orb;
     if (tables[L] && (n >> L) > 256) {
@@ -2736,7 +2794,7 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
     std::lock_guard<std::mutex> lock(cache().mu);
     p->olv.assign(p->D, DevOrbitLevel{});
     for (int L = 0; s == FCC_OK && L < p->D && L < 10; ++L)
-      if ((n >> L) >= 16 && ((p->tune.map[0][L] | p->tune.map[1][L]) & FCC_MAP_ORBIT))
+      if ((n >> L) >= 8 && ((p->tune.map[0][L] | p->tune.map[1][L]) & FCC_MAP_ORBIT))
         s = device_orbit_level(p->device, n >> L, &p->olv[L]);
     for (int L = 0; s == FCC_OK && L < p->D; ++L) {
       DevLevel lv{};
@@ -2807,6 +2865,26 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
       }
   }
   if (s == FCC_OK && p->D > 0) {
+    // dense DCT_2 and inverse of every node of the orbit-block levels
+    long long total = 0;
+    for (int L = 0; L < p->D; ++L) {
+      p->onode_off[L] = -1;
+      if (L < int(p->olv.size()) && p->olv[L].kinds) {
+        p->onode_off[L] = total;
+        total += 1LL << (3 * L);
+      }
+    }
+    hipError_t e = total > 0 ? hipMalloc(&p->onodes, sizeof(OrbitNode) * total) : hipSuccess;
+    if (e != hipSuccess) s = hip_fail(e, "hipMalloc(orbit node table)", __LINE__);
+    for (int L = 0; s == FCC_OK && L < p->D; ++L)
+      if (p->onode_off[L] >= 0) {
+        const long long cnt = 1LL << (3 * L);
+        hipLaunchKernelGGL(k_orbit_nodes, dim3(unsigned((cnt + 63) / 64)), dim3(64), 0, st,
+                           static_cast<OrbitNode*>(p->onodes) + p->onode_off[L], L, phases(p, L));
+        s = launch_status("orbit node table launch");
+      }
+  }
+  if (s == FCC_OK && p->D > 0) {
     size_t N = size_t(n) * n * n;
     p->ws_bytes = N * (p->stages64 ? sizeof(double2) : sizeof(float2));
     for (int b = 0; b < 2 && s == FCC_OK; ++b) {
@@ -2850,6 +2928,7 @@ fcc_status fcc_dct_destroy(fcc_plan_t p) {
   dense_free(p);
   if (p->resid) (void)hipFree(p->resid);
   if (p->nodes) (void)hipFree(p->nodes);
+  if (p->onodes) (void)hipFree(p->onodes);
   if (p->hph) (void)hipFree(p->hph);
   for (void* w : p->ws)
     if (w) (void)hipFree(w);

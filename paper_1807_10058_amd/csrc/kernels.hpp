@@ -161,25 +161,31 @@ struct GatherMap {
 
 // Orbit-block form of the basis change (orbit_level.hpp).
 // One orbit kind on the device.
+// Every array offset below is a multiple of 16 bytes, and every array is
+// padded to a multiple of 16 bytes, so blocks copy them with 16-byte loads.
 struct DevOrbitKind {
   int nc;             // cubes of the orbit
   int off_w;          // wmat: 9 nc entries, the matrices G[w_j] of the cube slots (row-major)
-  int off_perm[2];    // i16: 4 ceil(nc/4) cube slots in wavefront order (-1: idle lane), [0] B, [1] C
-  int off_rowptr[2];  // u16: 8 nc + 1 row starts of B (C), relative to off_ent
-  int off_ent[2];     // u16: entries (slot << 8) | polynomial id
+  int off_perm[2];    // i16: 8 ceil(nc/8) cube slots in wavefront order (-1: idle lane), [0] B, [1] C
+  int off_rowptr[2];  // u16: 40 nc + 1 segment starts of B (C), relative to off_ent
+  int off_ent[2];     // u32: entries (slot << 16) | (k & 0xffff), coefficient k / 144
+  int nent[2];        // entries of B (C)
 };
-// Templates and representatives of one node size.
+// Templates and representatives of one node size.  Each row of B (C) is split
+// by the monomials {1, c3, c1, c2, c1 c3} of the node's coefficient
+// polynomials: segment (row, q) lists the sources whose coefficient has a
+// nonzero q-th monomial coefficient k / 144 (k a 16-bit integer: every
+// coefficient is a multiple of 1/144), so a row is
+// (1/144) sum_q mono_q(node) * (sum over segment q of k_e x_e).
 struct DevOrbitLevel {
   const DevOrbitKind* kinds;
   const int16_t* perm;
   const uint16_t* rowptr;
-  const uint16_t* ent;
+  const uint32_t* ent;
   const int8_t* wmat;
   const uint32_t* reps;  // representatives p0 packed (x << 20) | (y << 10) | z
   const int4* chunks;    // {kind, first representative, count <= 16, 0}
   int nchunk;
-  const double* poly;    // npoly * kNumMono, ids below nconst are constants
-  int npoly, nconst;
   int lgm;               // log2 m
 };
 

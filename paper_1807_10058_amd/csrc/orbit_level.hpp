@@ -13,25 +13,38 @@
 //             DCT_2(phi)^{-1} (per-cube solves), then form every output
 //             x(q' + m o) from the orbit's 8|O| cube values (C_nl's block).
 //
-// A block takes 16 orbits of one kind ("units") of one node J.  Their sources
-// (or cube values) sit in LDS as [slot][unit], slot = cube slot * 8 + o (or
-// def).  The rows are summed by wavefronts of 64 lanes = 4 cube slots x 16
-// units; the template orders the cube slots so that the 4 slots of a wavefront
-// have identical row lengths (generic orbits: groups of 4 cubes with the same
-// profile), so the lanes of a wavefront run the same trip counts.  Blocks are
-// numbered so that each XCD works through one contiguous range (consecutive
-// nodes, then consecutive chunks of orbits in Morton order of their
-// representatives), which keeps the cache lines that neighbouring blocks share
-// in one L2.
+// A block takes 16 "units" = K orbits of one kind x G nodes (G = 1 at level
+// 0, 8 at level 1, 16 below; the nodes are consecutive in J, so for one
+// source slot the units of one orbit read consecutive addresses).  Their
+// sources (or cube values) sit in LDS as [slot][unit], slot = cube slot * 8
+// + o (or def).  The rows are summed by wavefronts of 64 lanes = 4 cube slots
+// x 16 units; a template row is split by monomial of the node's coefficient
+// polynomials into 5 segments of real coefficients, and the cube slots are
+// ordered so that the 4 slots of a wavefront have identical segment lengths
+// (generic orbits: groups of 4 cubes with the same profile), so the lanes of a
+// wavefront run the same trip counts.  Each lane forms its unit's monomials.
+// Blocks are numbered so that each XCD works through one contiguous range
+// (consecutive node groups, then consecutive orbits in Morton order of their
+// representatives), which keeps cache lines that neighbouring blocks share in
+// one L2.
 #pragma once
 
 namespace fcc {
 
-constexpr int kOrbitUnits = 16;                   // orbits per block
-constexpr int kOrbitThreads = 384;                // 6 wavefronts: 24 cube slots x 16 units
+constexpr int kOrbitUnits = 8;                      // units per block
+constexpr int kOrbitChunk = 16;                     // representatives per chunk
+constexpr int kOrbitThreads = 192;                  // 3 wavefronts: 24 cube slots x 8 units
 constexpr int kOrbitMaxCubes = 24;
 constexpr int kOrbitMaxSlots = 8 * kOrbitMaxCubes;  // 192
-constexpr int kOrbitMaxEnt = 2560;                // entries of one kind's B (C) block
+constexpr int kOrbitSeg = 8 * kNumMono;             // segments per cube slot
+constexpr int kOrbitMaxEnt = 2560;                  // entries of one kind's B (C) block
+constexpr int kOrbitMaxNodes = 8;
+
+// Blocks of an orbit launch: per chunk of 16 representatives and group of
+// G = min(8^L, 8) nodes, 16 / K blocks of K = 8 / G orbits.
+__host__ __device__ __forceinline__ long long orbit_blocks_total(int nchunk, int L, int nvol) {
+  return (long long)nchunk * 2 * (1LL << (3 * L)) * nvol;
+}
 
 // Logical block of an orbit launch: blocks i, i+8, i+16, ... run on one XCD,
 // which gets one contiguous range of the total.  Returns -1 past the end.
@@ -41,164 +54,267 @@ __device__ __forceinline__ long long orbit_block(long long total) {
   return b < total ? b : -1;
 }
 
-// Cube q_j = (G[w_j] p0) mod m of unit representative p0.
+// Cube q_j = (G[w_j] p0) mod m of representative p0.
 __device__ __forceinline__ void orbit_cube(const int8_t* g, uint32_t pr, int mask, int q[3]) {
   const int p0[3] = {int(pr >> 20), int((pr >> 10) & 1023u), int(pr & 1023u)};
 #pragma unroll
   for (int d = 0; d < 3; ++d) q[d] = (g[3 * d] * p0[0] + g[3 * d + 1] * p0[1] + g[3 * d + 2] * p0[2]) & mask;
 }
 
-// Block set-up shared by both directions: decode (volume, chunk, node), copy
-// the kind's side `sd` of the template to LDS and form the node's coefficient
-// values.  Returns false for padding blocks (the whole block leaves).
+// LDS state of a block.
 template <typename R>
+struct OrbitShared {
+  cx<R> val[kOrbitMaxSlots * kOrbitUnits];  // sources (forward) or cube values (inverse)
+  alignas(16) cx<R> mono[kOrbitMaxNodes][kNumMono];  // monomials / 144, per node
+  alignas(16) uint32_t ent[kOrbitMaxEnt];
+  alignas(16) uint16_t seg[kOrbitMaxCubes * kOrbitSeg + 8];
+  alignas(16) int16_t perm[kOrbitMaxCubes];
+  alignas(16) int8_t wm[9 * kOrbitMaxCubes + 8];
+  uint32_t rep[kOrbitUnits];
+};
+
 struct OrbitBlock {
   long long vol;
-  int J[3];
-  int kind, first, cnt, nc;
+  long long node0;  // first node of the block's group of G
+  int G, K;         // nodes and orbits of the block
+  int nc, nact;     // cubes of the kind; active units (orbit index < chunk count)
 };
+
+// Node J (flat index) -> coordinates.
+__device__ __forceinline__ void node_coords(long long node, int L, int J[3]) {
+  const int mask = (1 << L) - 1;
+  J[0] = int(node >> (2 * L));
+  J[1] = int((node >> L) & mask);
+  J[2] = int(node & mask);
+}
+
+// Block set-up shared by both directions: decode (volume, chunk, orbit
+// sub-range, node group), then copy the kind's side `sd` of the template and
+// the orbits' representatives to LDS and form each node's monomials.  Every
+// copy is a 16-byte load issued before the first wait (one memory round
+// trip).  Returns false for blocks with nothing to do (the whole block leaves).
+constexpr int kOrbitPieces = 5;  // 16-byte pieces per thread
 template <typename R>
-__device__ __forceinline__ bool orbit_setup(const DevOrbitLevel& ol, int n, int L, int nvol, int sd,
-                                            const double2* __restrict__ hph, OrbitBlock<R>& ob, cx<R>* coef,
-                                            uint16_t* ent, uint16_t* rowptr, int16_t* perm, int8_t* wm) {
+__device__ __forceinline__ bool orbit_setup(const DevOrbitLevel& ol, int L, int nvol, int sd,
+                                            const double2* __restrict__ hph, OrbitBlock& ob, OrbitShared<R>& sh) {
   const long long nnode = 1LL << (3 * L);
-  const long long b = orbit_block((long long)ol.nchunk * nnode * nvol);
+  ob.G = int(nnode < kOrbitMaxNodes ? nnode : kOrbitMaxNodes);
+  ob.K = kOrbitUnits / ob.G;
+  const long long b = orbit_block(orbit_blocks_total(ol.nchunk, L, nvol));
   if (b < 0) return false;
-  const long long node = b % nnode, rest = b / nnode;
+  const int nsub = kOrbitChunk / ob.K;
+  const long long ngroups = nnode / ob.G;
+  const long long ng = b % ngroups;
+  long long rest = b / ngroups;
+  const int sub = int(rest % nsub);
+  rest /= nsub;
   const int chunk = int(rest % ol.nchunk);
   ob.vol = rest / ol.nchunk;
-  const int mask = (1 << L) - 1;
-  ob.J[0] = int(node >> (2 * L));
-  ob.J[1] = int((node >> L) & mask);
-  ob.J[2] = int(node & mask);
+  ob.node0 = ng * ob.G;
   const int4 ch = ol.chunks[chunk];
-  ob.kind = ch.x;
-  ob.first = ch.y;
-  ob.cnt = ch.z;
-  const DevOrbitKind kd = ol.kinds[ob.kind];
+  const int first = ch.y + sub * ob.K;
+  const int norb = min(ob.K, ch.z - sub * ob.K);
+  if (norb <= 0) return false;
+  ob.nact = norb * ob.G;
+  const DevOrbitKind kd = ol.kinds[ch.x];
   ob.nc = kd.nc;
-  const int rows = 8 * kd.nc;
   const int tid = threadIdx.x;
-  for (int i = tid; i <= rows; i += blockDim.x) rowptr[i] = ol.rowptr[kd.off_rowptr[sd] + i];
-  const int nent = ol.rowptr[kd.off_rowptr[sd] + rows];
-  for (int i = tid; i < nent; i += blockDim.x) ent[i] = ol.ent[kd.off_ent[sd] + i];
-  const int np = 4 * ((kd.nc + 3) >> 2);
-  for (int i = tid; i < np; i += blockDim.x) perm[i] = ol.perm[kd.off_perm[sd] + i];
-  for (int i = tid; i < 9 * kd.nc; i += blockDim.x) wm[i] = ol.wmat[kd.off_w + i];
-  if (tid < ol.npoly) {
-    cx<R> mono[kNumMono];
-    node_mono(hph, L, ob.J, mono);
-    coef[tid] = poly_value(ol.poly, ol.nconst, tid, mono);
+  // pieces: segment starts, entries, slot order, slot matrices
+  const int o1 = (kOrbitSeg * kd.nc + 1 + 7) >> 3;
+  const int o2 = o1 + ((kd.nent[sd] + 3) >> 2);
+  const int o3 = o2 + ((kd.nc + 7) >> 3);
+  const int total = o3 + ((9 * kd.nc + 15) >> 4);
+  const uint4* g_seg = reinterpret_cast<const uint4*>(ol.rowptr + kd.off_rowptr[sd]);
+  const uint4* g_ent = reinterpret_cast<const uint4*>(ol.ent + kd.off_ent[sd]);
+  const uint4* g_perm = reinterpret_cast<const uint4*>(ol.perm + kd.off_perm[sd]);
+  const uint4* g_wm = reinterpret_cast<const uint4*>(ol.wmat + kd.off_w);
+  // (pieces past the total re-read the first one, so every load is unconditional)
+  uint4 t[kOrbitPieces];
+#pragma unroll
+  for (int c = 0; c < kOrbitPieces; ++c) {
+    const int k = tid + c * kOrbitThreads;
+    const uint4* src = k >= total ? g_seg
+                       : k < o1   ? g_seg + k
+                       : k < o2   ? g_ent + (k - o1)
+                       : k < o3   ? g_perm + (k - o2)
+                                  : g_wm + (k - o3);
+    t[c] = *src;
   }
+  uint32_t r = 0;
+  if (tid < norb) r = ol.reps[first + tid];
+  if (tid < ob.G) {
+    int J[3];
+    node_coords(ob.node0 + tid, L, J);
+    cx<R> mono[kNumMono];
+    node_mono(hph, L, J, mono);
+#pragma unroll
+    for (int q = 0; q < kNumMono; ++q) sh.mono[tid][q] = R(1.0 / 144.0) * mono[q];
+  }
+#pragma unroll
+  for (int c = 0; c < kOrbitPieces; ++c) {
+    const int k = tid + c * kOrbitThreads;
+    if (k < total) {
+      uint4* dst = k < o1   ? reinterpret_cast<uint4*>(sh.seg) + k
+                   : k < o2 ? reinterpret_cast<uint4*>(sh.ent) + (k - o1)
+                   : k < o3 ? reinterpret_cast<uint4*>(sh.perm) + (k - o2)
+                            : reinterpret_cast<uint4*>(sh.wm) + (k - o3);
+      *dst = t[c];
+    }
+  }
+  if (tid < norb) sh.rep[tid] = r;
   return true;
 }
 
-// Forward level L: y = B_nl(c) x on the orbits of one chunk, then
+// One row of B (C) for unit u: sum_q (mono_q / 144) * sum_{segment q} k_e val[slot_e][u].
+template <typename R>
+__device__ __forceinline__ cx<R> orbit_row(const OrbitShared<R>& sh, int s0, int u, const cx<R>* mono) {
+  cx<R> y{R(0), R(0)};
+  const char* vbase = reinterpret_cast<const char*>(sh.val) + u * sizeof(cx<R>);
+#pragma unroll
+  for (int q = 0; q < kNumMono; ++q) {
+    cx<R> a{R(0), R(0)};
+    const int e1 = sh.seg[s0 + q + 1];
+#pragma unroll 2
+    for (int e = sh.seg[s0 + q]; e < e1; ++e) {
+      const uint32_t v = sh.ent[e];
+      const cx<R> x = *reinterpret_cast<const cx<R>*>(vbase + (v >> 16) * (kOrbitUnits * sizeof(cx<R>)));
+      const R c = R(int(int16_t(v & 0xffffu)));
+      a.x = a.x + c * x.x;
+      a.y = a.y + c * x.y;
+    }
+    y = y + mono[q] * a;
+  }
+  return y;
+}
+
+// Forward level L: y = B_nl(c) x on the block's orbits and nodes, then
 // z = DCT_2(phi) y per cube, stored at the cube's 8 positions.
 template <typename R, typename TI, typename TO>
 __global__ __launch_bounds__(kOrbitThreads) void k_fwd_orbit(VolSet vs, int nvol, int n, int L, DevOrbitLevel ol,
                                                              const double2* __restrict__ hph,
-                                                             const NodeConst* nodes) {
-  __shared__ cx<R> src[kOrbitMaxSlots * kOrbitUnits];
-  __shared__ cx<R> coef[kMaxPoly];
-  __shared__ uint16_t ent[kOrbitMaxEnt];
-  __shared__ uint16_t rowptr[kOrbitMaxSlots + 1];
-  __shared__ int16_t perm[kOrbitMaxCubes];
-  __shared__ int8_t wm[9 * kOrbitMaxCubes];
-  OrbitBlock<R> ob;
-  if (!orbit_setup<R>(ol, n, L, nvol, 0, hph, ob, coef, ent, rowptr, perm, wm)) return;
+                                                             const OrbitNode* __restrict__ onodes) {
+  __shared__ OrbitShared<R> sh;
+  OrbitBlock ob;
+  if (!orbit_setup<R>(ol, L, nvol, 0, hph, ob, sh)) return;
   __syncthreads();
   const int mask = (1 << ol.lgm) - 1;
   const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, ob.vol));
-  // sources: slot s = j * 8 + o of unit u is q_j(u) + m o
-  for (int it = threadIdx.x; it < ob.nc * 8 * kOrbitUnits; it += kOrbitThreads) {
-    const int u = it & (kOrbitUnits - 1), s = it >> 4;
-    if (u < ob.cnt) {
-      int q[3];
-      orbit_cube(wm + 9 * (s >> 3), ol.reps[ob.first + u], mask, q);
+  // sources: slot s = j * 8 + o of unit u = k * G + g is q_j(orbit k) + m o in
+  // node node0 + g; every load of a thread is issued before the first wait
+  constexpr int kPer = kOrbitMaxSlots * kOrbitUnits / kOrbitThreads;
+  cx<R> v[kPer];
+#pragma unroll
+  for (int c = 0; c < kPer; ++c) {
+    const int it = threadIdx.x + c * kOrbitThreads, u = it & (kOrbitUnits - 1), s = it >> 3;
+    if (it < ob.nc * 8 * kOrbitUnits && u < ob.nact) {
+      int q[3], J[3];
+      orbit_cube(sh.wm + 9 * (s >> 3), sh.rep[u / ob.G], mask, q);
+      node_coords(ob.node0 + u % ob.G, L, J);
       const int o = s & 7;
-      src[it] = IO<TI, R>::ld(in, gpos(n, L, ob.J, q[0] + (((o >> 2) & 1) << ol.lgm),
-                                        q[1] + (((o >> 1) & 1) << ol.lgm), q[2] + ((o & 1) << ol.lgm)));
+      v[c] = IO<TI, R>::ld(in, gpos(n, L, J, q[0] + (((o >> 2) & 1) << ol.lgm), q[1] + (((o >> 1) & 1) << ol.lgm),
+                                    q[2] + ((o & 1) << ol.lgm)));
     }
+  }
+#pragma unroll
+  for (int c = 0; c < kPer; ++c) {
+    const int it = threadIdx.x + c * kOrbitThreads;
+    if (it < ob.nc * 8 * kOrbitUnits && (it & (kOrbitUnits - 1)) < ob.nact) sh.val[it] = v[c];
   }
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, u = lane & (kOrbitUnits - 1);
-  if (w >= ((ob.nc + 3) >> 2) || u >= ob.cnt) return;
-  const int j = perm[4 * w + (lane >> 4)];
+  if (w >= ((ob.nc + 7) >> 3) || u >= ob.nact) return;
+  const int j = sh.perm[8 * w + (lane >> 3)];
   if (j < 0) return;
+  int J[3];
+  node_coords(ob.node0 + u % ob.G, L, J);
+  const cx<R>* mono = sh.mono[u % ob.G];
+  // z = DCT_2(phi) y, one column per row of B as the rows complete (column
+  // f + 1 is loaded while row f is summed)
+  const OrbitNode& on = onodes[ob.node0 + u % ob.G];
   cx<R> y[8];
+  double2 dcol[8];
 #pragma unroll
-  for (int f = 0; f < 8; ++f) {
-    cx<R> acc{R(0), R(0)};
-    const int e1 = rowptr[j * 8 + f + 1];
-    for (int e = rowptr[j * 8 + f]; e < e1; ++e) {
-      const uint16_t v = ent[e];
-      acc = acc + coef[v & 255u] * src[(v >> 8) * kOrbitUnits + u];
-    }
-    y[f] = acc;
+  for (int i = 0; i < 8; ++i) {
+    y[i] = {R(0), R(0)};
+    dcol[i] = on.D[i];
   }
-  dct2_apply(nodes, hph, L, ob.J, y);
+#pragma unroll 1
+  for (int f = 0; f < 8; ++f) {
+    double2 cur[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) cur[i] = dcol[i];
+    if (f < 7) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) dcol[i] = on.D[(f + 1) * 8 + i];
+    }
+    const cx<R> yf = orbit_row(sh, (j * 8 + f) * kNumMono, u, mono);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) y[i] = y[i] + ldc<R>(cur[i]) * yf;
+  }
   int q[3];
-  orbit_cube(wm + 9 * j, ol.reps[ob.first + u], mask, q);
+  orbit_cube(sh.wm + 9 * j, sh.rep[u / ob.G], mask, q);
   TO* __restrict__ out = static_cast<TO*>(vol_ptr(vs.out, ob.vol));
 #pragma unroll
   for (int i = 0; i < 8; ++i)
-    IO<TO, R>::st(out, gpos(n, L, ob.J, 2 * q[0] + ((i >> 2) & 1), 2 * q[1] + ((i >> 1) & 1), 2 * q[2] + (i & 1)),
+    IO<TO, R>::st(out, gpos(n, L, J, 2 * q[0] + ((i >> 2) & 1), 2 * q[1] + ((i >> 1) & 1), 2 * q[2] + (i & 1)),
                   y[i]);
 }
 
-// Inverse level L: y = DCT_2(phi)^{-1} z per cube of the chunk's orbits, then
-// x(q' + m o) = row (q', o) of C_nl(c) applied to the orbit's cube values.
+// Inverse level L: y = DCT_2(phi)^{-1} z per cube of the block's orbits and
+// nodes, then x(q' + m o) = row (q', o) of C_nl(c) applied to the orbit's cube
+// values.
 template <typename R, typename TI, typename TO>
 __global__ __launch_bounds__(kOrbitThreads) void k_inv_orbit(VolSet vs, int nvol, int n, int L, DevOrbitLevel ol,
                                                              const double2* __restrict__ hph,
-                                                             const NodeConst* nodes) {
-  __shared__ cx<R> ys[kOrbitMaxSlots * kOrbitUnits];
-  __shared__ cx<R> coef[kMaxPoly];
-  __shared__ uint16_t ent[kOrbitMaxEnt];
-  __shared__ uint16_t rowptr[kOrbitMaxSlots + 1];
-  __shared__ int16_t perm[kOrbitMaxCubes];
-  __shared__ int8_t wm[9 * kOrbitMaxCubes];
-  OrbitBlock<R> ob;
-  if (!orbit_setup<R>(ol, n, L, nvol, 1, hph, ob, coef, ent, rowptr, perm, wm)) return;
+                                                             const OrbitNode* __restrict__ onodes) {
+  __shared__ OrbitShared<R> sh;
+  OrbitBlock ob;
+  if (!orbit_setup<R>(ol, L, nvol, 1, hph, ob, sh)) return;
   __syncthreads();
   const int mask = (1 << ol.lgm) - 1;
   const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, ob.vol));
-  // cube values: slot s = j * 8 + def of unit u, from position def + 2 q_j(u)
+  // cube values: slot s = j * 8 + def of unit u, from position def + 2 q_j
   for (int it = threadIdx.x; it < ob.nc * kOrbitUnits; it += kOrbitThreads) {
-    const int u = it & (kOrbitUnits - 1), j = it >> 4;
-    if (u < ob.cnt) {
-      int q[3];
-      orbit_cube(wm + 9 * j, ol.reps[ob.first + u], mask, q);
+    const int u = it & (kOrbitUnits - 1), j = it >> 3;
+    if (u < ob.nact) {
+      int q[3], J[3];
+      orbit_cube(sh.wm + 9 * j, sh.rep[u / ob.G], mask, q);
+      node_coords(ob.node0 + u % ob.G, L, J);
       cx<R> z[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i)
-        z[i] = IO<TI, R>::ld(in, gpos(n, L, ob.J, 2 * q[0] + ((i >> 2) & 1), 2 * q[1] + ((i >> 1) & 1),
+        z[i] = IO<TI, R>::ld(in, gpos(n, L, J, 2 * q[0] + ((i >> 2) & 1), 2 * q[1] + ((i >> 1) & 1),
                                        2 * q[2] + (i & 1)));
-      idct2_apply(nodes, hph, L, ob.J, z);
+      // y = DCT_2(phi)^{-1} z
+      const OrbitNode& on = onodes[ob.node0 + u % ob.G];
+      cx<R> y[8];
 #pragma unroll
-      for (int f = 0; f < 8; ++f) ys[(j * 8 + f) * kOrbitUnits + u] = z[f];
+      for (int f = 0; f < 8; ++f) y[f] = {R(0), R(0)};
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int f = 0; f < 8; ++f) y[f] = y[f] + ldc<R>(on.Dinv[i * 8 + f]) * z[i];
+#pragma unroll
+      for (int f = 0; f < 8; ++f) sh.val[(j * 8 + f) * kOrbitUnits + u] = y[f];
     }
   }
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, u = lane & (kOrbitUnits - 1);
-  if (w >= ((ob.nc + 3) >> 2) || u >= ob.cnt) return;
-  const int j = perm[4 * w + (lane >> 4)];
+  if (w >= ((ob.nc + 7) >> 3) || u >= ob.nact) return;
+  const int j = sh.perm[8 * w + (lane >> 3)];
   if (j < 0) return;
+  int J[3];
+  node_coords(ob.node0 + u % ob.G, L, J);
+  const cx<R>* mono = sh.mono[u % ob.G];
   int q[3];
-  orbit_cube(wm + 9 * j, ol.reps[ob.first + u], mask, q);
+  orbit_cube(sh.wm + 9 * j, sh.rep[u / ob.G], mask, q);
   TO* __restrict__ out = static_cast<TO*>(vol_ptr(vs.out, ob.vol));
 #pragma unroll
   for (int o = 0; o < 8; ++o) {
-    cx<R> acc{R(0), R(0)};
-    const int e1 = rowptr[j * 8 + o + 1];
-    for (int e = rowptr[j * 8 + o]; e < e1; ++e) {
-      const uint16_t v = ent[e];
-      acc = acc + coef[v & 255u] * ys[(v >> 8) * kOrbitUnits + u];
-    }
-    IO<TO, R>::st(out, gpos(n, L, ob.J, q[0] + (((o >> 2) & 1) << ol.lgm), q[1] + (((o >> 1) & 1) << ol.lgm),
+    const cx<R> x = orbit_row(sh, (j * 8 + o) * kNumMono, u, mono);
+    IO<TO, R>::st(out, gpos(n, L, J, q[0] + (((o >> 2) & 1) << ol.lgm), q[1] + (((o >> 1) & 1) << ol.lgm),
                             q[2] + ((o & 1) << ol.lgm)),
-                  acc);
+                  x);
   }
 }
 

@@ -39,7 +39,8 @@ struct fcc_plan_s {
   int tail_Lt[2] = {0, 0};              // first level of the fused LDS tail: [0] forward, [1] inverse
   std::vector<fcc::DevLevel> tlv;
   std::vector<fcc::DevOrbitLevel> olv;  // per level L: orbit templates of nl = n >> L (orbit levels only)
-  bool orbit[2][16] = {};               // level L of direction d runs as one orbit-block launch       // per level from min(tail_Lt) on: plain-order tables, S = 1
+  void* onodes = nullptr;               // dense DCT_2 and inverse per node of the orbit-block levels
+  long long onode_off[16] = {};         // per level offset into onodes, -1 if none       // per level from min(tail_Lt) on: plain-order tables, S = 1
   unsigned char kf[2][16][8] = {};      // balanced map: log2 lanes per row, per side, level and f
 };
 

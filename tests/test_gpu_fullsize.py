@@ -8,6 +8,7 @@ import torch
 import oracle
 import paper_1807_10058_amd as fcc
 import workloads
+from oracle import fold_ref
 
 pytestmark = pytest.mark.gpu
 gu = pytest.importorskip("tests.gpu_util")
@@ -23,11 +24,18 @@ def test_residual_entry_point_matches_host():
     ref = (x.double() - y.double()).abs().max().item() / x.double().abs().max().item()
     assert abs(r - ref) <= 1e-12 * max(1.0, ref)
     assert fcc.fcc_dct_roundtrip_residual(plan, x, x) == 0.0
+    # a NaN in the round trip must not pass as a small residual
+    y[77] = float("nan")
+    r = fcc.fcc_dct_roundtrip_residual(plan, x, y)
+    assert not (r <= 1e-5)
 
 
 @pytest.mark.parametrize("n", [128, 256])
 def test_large_single_volume_forward_inverse(n):
-    """Trilinear-upsampled smooth field (the n = 256 workload's recipe), FP32 data."""
+    """Trilinear-upsampled smooth field (the n = 256 workload's recipe), FP32
+    data: the whole forward volume against the independent fold reference,
+    sampled rows against the direct oracle, the inverse of the exact spectrum
+    against the fold inverse on sampled points, and the FP64 round trip."""
     x_np = workloads.upsampled_field(n, seed=3)
     plan = fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT)
     x = torch.from_numpy(x_np).to(gu.DEV)
@@ -36,14 +44,28 @@ def test_large_single_volume_forward_inverse(n):
     fcc.fcc_dct_forward(plan, x, X)
     fcc.fcc_dct_inverse(plan, X, y)
     torch.cuda.synchronize()
+    Xh = X.cpu().numpy()
+    full = fold_ref.fold_forward(x_np.astype(np.float64), n)
+    assert gu.maxrel(Xh, full) <= 1e-5
     rows = gu.sample_rows(n, 12, n)
     ref = oracle.forward_rows(x_np.astype(np.float64), n, rows)
-    assert gu.maxrel(X.cpu().numpy()[rows], ref) <= 1e-5
+    assert gu.maxrel(Xh[rows], ref) <= 1e-5
     assert fcc.fcc_dct_roundtrip_residual(plan, x, y) <= 1e-5
+    # the inverse alone: GPU inverse of the exact FP64 spectrum (rounded to the
+    # complex64 input) against the fold inverse of the same values
+    Xin = torch.from_numpy(full.astype(np.complex64)).to(gu.DEV)
+    fcc.fcc_dct_inverse(plan, Xin, y)
+    torch.cuda.synchronize()
+    pts = np.random.default_rng(n).choice(n ** 3, 2000, replace=False)
+    want = fold_ref.fold_inverse(Xin.cpu().numpy().astype(np.complex128), n, points=pts)
+    assert np.abs(y.cpu().numpy()[pts] - want.real).max() <= 1e-5 * np.abs(x_np).max()
 
 
 def test_ragged_batch_full_size():
-    """All 512 volumes of the ragged workload, forward then inverse in one call."""
+    """All 512 volumes of the ragged workload, forward then inverse in one call:
+    one volume per size class checked on 64 direct oracle rows and, for
+    n >= 32, over the whole volume against the fold reference; the round trip
+    of every volume by the FP64 residual."""
     ns, xs_np = workloads.ragged_batch(512, seed=4)
     plans = {n: fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT) for n in set(ns)}
     xs = [torch.from_numpy(x).to(gu.DEV) for x in xs_np]
@@ -55,9 +77,12 @@ def test_ragged_batch_full_size():
         if n in seen:
             continue
         seen.add(n)
-        rows = gu.sample_rows(n, 8, i)
+        got = outs[i].cpu().numpy()
+        rows = gu.sample_rows(n, 64, i)
         ref = oracle.forward_rows(xs_np[i].astype(np.float64), n, rows)
-        assert gu.maxrel(outs[i].cpu().numpy()[rows], ref) <= 1e-5, n
+        assert gu.maxrel(got[rows], ref) <= 1e-5, n
+        if n >= 32:
+            assert gu.maxrel(got, fold_ref.fold_forward(xs_np[i].astype(np.float64), n)) <= 1e-5, n
     for i in range(len(ns)):
         x0 = torch.from_numpy(xs_np[i]).to(gu.DEV)
         assert fcc.fcc_dct_roundtrip_residual(plans[ns[i]], x0, xs[i]) <= 1e-5, (i, ns[i])

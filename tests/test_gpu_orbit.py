@@ -130,3 +130,18 @@ def test_n512_forward_rows_and_roundtrip():
     ref = oracle.forward_rows(x_np.astype(np.float64), n, rows)
     assert gu.maxrel(X.cpu().numpy()[rows], ref) <= 1e-5
     assert fcc.fcc_dct_roundtrip_residual(plan, xt, y) <= 1e-5
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_orbit_down_to_node_size_8(n):
+    """Orbit-block launches at every level with node size >= 8 (the n = 8
+    templates are a family of their own): same transform as the default schedule."""
+    x = RNG.standard_normal(n ** 3)
+    base = fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP64, flags=fcc.FCC_REAL_INPUT)
+    t = fcc.fcc_dct_get_tuning(base)
+    t["map"] = [[m | (fcc.FCC_MAP_ORBIT if (n >> L) >= 8 else 0) for L, m in enumerate(row)] for row in t["map"]]
+    plan = fcc.fcc_dct_plan_tuned(n, prec=fcc.FCC_PREC_FP64, flags=fcc.FCC_REAL_INPUT, tuning=t)
+    assert sum("orbit" in s["name"] for s in fcc.fcc_dct_describe_launches(plan, 1)) == n.bit_length() - 3
+    _, X, y = _run(plan, x, fcc.FCC_PREC_FP64, True)
+    assert gu.maxrel(X.cpu().numpy(), fold_ref.fold_forward(x, n)) <= FP64_TOL[n]
+    assert gu.maxrel(y.cpu().numpy(), x) <= 10 * FP64_TOL[n]
