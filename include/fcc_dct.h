@@ -71,7 +71,23 @@ enum {
   /* FCC_PREC_FP32 with FP64 stages: run the top level (and the inverse's last
    * level) in FP32 arithmetic with a complex64 intermediate.  Faster top level;
    * round-trip error ~4e-6 instead of ~5e-8 at n = 32..128.                    */
-  FCC_LEVEL0_FP32 = 1u << 3
+  FCC_LEVEL0_FP32 = 1u << 3,
+  /* The transposed transform, the literal reading of the row/column labels
+   * after eq. SU4ChebyshevTransformExplicitForm: forward X[k] =
+   * sum_j T_k(theta_j) x[j] (input indexed by the zeros, output by the
+   * basis), inverse its exact inverse.  Runs the factors of eq. FastAlgorithm
+   * transposed, in reverse order (orbit-block launches at every level with
+   * node size >= 4, then DCT_2^T per cube).  FP64 or FP32 data, n <= 256;
+   * not with FCC_LEVEL0_FP32, FCC_HERMITIAN_PACKED or the split precisions. */
+  FCC_TRANSPOSED = 1u << 4,
+  /* With FCC_REAL_INPUT: the spectrum of real input in Hermitian-packed form.
+   * The zeros pair up as j' = (c - g^T j) mod n with X[j'] = conj X[j] (g in W
+   * and c fixed by the skew; Sec. III, x-bar = z, y-bar = y); the forward
+   * writes one value per pair (the member with the smaller flat index) and
+   * the self-paired zeros, in increasing flat index: fcc_dct_packed_size
+   * values.  The inverse reads that form.  Skews without such a pairing return
+   * FCC_ERR_UNSUPPORTED; fcc_dct_batched does not take these plans. */
+  FCC_HERMITIAN_PACKED = 1u << 5
 };
 
 /* Build a plan for DCT_{n x n x n}(r,s,t) (Definition 2).
@@ -139,6 +155,10 @@ fcc_status fcc_dct_inverse(fcc_plan_t plan, const void* X, void* x, void* hip_st
 fcc_status fcc_dct_batched(const fcc_plan_t* plans, int count, const void* const* in,
                            void* const* out, int direction, void* hip_stream);
 
+/* Number of complex values in the forward output of a plan: n^3, or the
+ * packed count with FCC_HERMITIAN_PACKED.  Errors: FCC_ERR_INVALID_ARG. */
+fcc_status fcc_dct_packed_size(fcc_plan_t plan, long long* count);
+
 /* Free every graph (and its scratch) that fcc_dct_batched has recorded.  At
  * most 4 are kept anyway (the least recently used is freed when a new one is
  * recorded); this releases them at once.  Waits for the device first.
@@ -198,7 +218,7 @@ const char* fcc_status_string(fcc_status s);
  *                    FCC_MAP_XCD16 those sources are fetched into one XCD's
  *                    L2 once.  It takes precedence over FCC_MAP_F_INNER and
  *                    FCC_MAP_BALANCE and changes no result bit.
- *                    FCC_MAP_ORBIT (node sizes n / 2^L >= 16) runs the
+ *                    FCC_MAP_ORBIT (node sizes n / 2^L >= 8) runs the
  *                    level as one launch over the orbits of W on the node's
  *                    cube grid: a block loads the sources of 16 orbits of one
  *                    kind once, forms their rows from the kind's template (the
@@ -302,10 +322,29 @@ fcc_status fcc_dct_batched_time_launches(const fcc_plan_t* plans, int count, con
 /* FP64 round-trip residual on the GPU: *result = max_k |x_k - y_k| / max_k |x_k|
  * over the plan's n^3 elements, x and y laid out like the forward input
  * (real with FCC_REAL_INPUT, else complex; float or double per precision).
- * Typically y = inverse(forward(x)).  Waits for `hip_stream` (the result is a
- * host value).  Errors: FCC_ERR_INVALID_ARG, FCC_ERR_HIP. */
+ * Typically y = inverse(forward(x)).  A NaN in x - y counts as an infinite
+ * difference, so a round trip that produced NaN never reports a small
+ * residual.  Waits for `hip_stream` (the result is a host value).  Errors: FCC_ERR_INVALID_ARG, FCC_ERR_HIP. */
 fcc_status fcc_dct_roundtrip_residual(fcc_plan_t plan, const void* x, const void* y, double* result,
                                       void* hip_stream);
+
+/* ---- block-wise coding ------------------------------------------------- */
+
+/* Threshold and quantise FCC spectra for block-wise volumetric coding (the
+ * application motivating the transform, Sec. I and Sec. V): for each of
+ * `count` complex64 coefficients X[k] (device, interleaved float2),
+ *   keep_k = re^2 + im^2 >= threshold^2,
+ *   codes[k] = keep_k ? (rint(re / step), rint(im / step)) : (0, 0)  (int16 pairs, saturated),
+ *   Xq[k] = step * codes[k]  (the dequantised spectrum, float2),
+ * every operation a single FP32 rounding (no fused multiply-add), so the
+ * integer decisions are reproducible in any IEEE FP32 arithmetic.  *kept
+ * (a device counter, set to zero first) receives the number of kept
+ * coefficients.  codes or Xq may be NULL.  Asynchronous on hip_stream.
+ * Errors: FCC_ERR_INVALID_ARG (null X or kept, step <= 0, negative or
+ * non-finite threshold, misaligned pointers), FCC_ERR_UNSUPPORTED (Xq == X),
+ * FCC_ERR_HIP. */
+fcc_status fcc_spectrum_quantise(const void* X, long long count, float threshold, float step, void* codes,
+                                 void* Xq, unsigned long long* kept, void* hip_stream);
 
 /* ---- introspection (host logic; no GPU needed) ------------------------- */
 

@@ -116,5 +116,20 @@ def inverse(X, n, rst=DEFAULT_RST):
     return np.linalg.solve(matrix(n, rst), np.asarray(X, dtype=np.complex128).reshape(-1))
 
 
+def transposed_rows(x, n, kappas, rst=DEFAULT_RST):
+    """Entries kappas of the transposed transform (the literal row/column
+    reading of eq. SU4ChebyshevTransformExplicitForm): X_T[k] = sum_j T_k(theta_j) x[j],
+    each an O(24 N) sum in numpy (T_k written out as the orbit sum of Definition 1)."""
+    G = group()
+    th = sample_points(n, rst)
+    x = np.asarray(x, dtype=np.complex128).reshape(-1)
+    out = []
+    for k in np.asarray(kappas).reshape(-1):
+        kv = np.array([k // (n * n), (k // n) % n, k % n])
+        Tk = np.exp(2j * np.pi * (th @ (G @ kv).T)).mean(axis=1)
+        out.append(Tk @ x)
+    return np.array(out)
+
+
 def num_threads():
     return int(lib().fcco_num_threads())

@@ -12,6 +12,7 @@ _LIB_PATH = os.path.join(_HERE, "libfccdct.so")
 FCC_OK = 0
 FCC_PREC_FP64, FCC_PREC_FP32, FCC_PREC_SPLIT_BF16, FCC_PREC_SPLIT_FP16 = 0, 1, 2, 3
 FCC_REAL_INPUT, FCC_STAGES_FP32, FCC_STAGES_FP64, FCC_LEVEL0_FP32 = 1, 2, 4, 8
+FCC_TRANSPOSED, FCC_HERMITIAN_PACKED = 16, 32
 (FCC_MAP_XCD, FCC_MAP_F_INNER, FCC_MAP_NODES8, FCC_MAP_NODES64, FCC_MAP_SPLIT, FCC_MAP_BALANCE, FCC_MAP_XCD16,
  FCC_MAP_CLUSTER, FCC_MAP_ORBIT) = 1, 2, 4, 8, 16, 32, 64, 128, 256
 _MAX_LEVELS = 10
@@ -93,6 +94,8 @@ _lib.fcc_dct_batched.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINT
                                  ctypes.c_int, _vp]
 _lib.fcc_dct_destroy.argtypes = [_vp]
 _lib.fcc_dct_batched_release.argtypes = []
+_lib.fcc_dct_packed_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_longlong)]
+_lib.fcc_spectrum_quantise.argtypes = [_vp, ctypes.c_longlong, ctypes.c_float, ctypes.c_float, _vp, _vp, _vp, _vp]
 _lib.fcc_dct_describe_launches.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_LaunchInfo), ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_int)]
 _lib.fcc_dct_batched_time_launches.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp),
@@ -107,7 +110,7 @@ _lib.fcc_status_string.restype = ctypes.c_char_p
 _lib.fcc_asp_tables.argtypes = [ctypes.c_int, ctypes.POINTER(_LevelTables)]
 _lib.fcc_asp_orbit_blocks.argtypes = [ctypes.c_int, ctypes.POINTER(_OrbitBlocks)]
 for _f in ("fcc_dct_plan", "fcc_dct_plan_tuned", "fcc_dct_get_tuning", "fcc_dct_autotune", "fcc_dct_forward", "fcc_dct_forward_static", "fcc_dct_inverse", "fcc_dct_batched", "fcc_dct_destroy", "fcc_dct_batched_release",
-           "fcc_dct_describe_launches", "fcc_dct_batched_time_launches",
+           "fcc_dct_describe_launches", "fcc_dct_batched_time_launches", "fcc_spectrum_quantise", "fcc_dct_packed_size",
            "fcc_asp_tables", "fcc_asp_orbit_blocks", "fcc_dct_time_launches", "fcc_dct_roundtrip_residual"):
     getattr(_lib, _f).restype = ctypes.c_int
 
@@ -237,6 +240,26 @@ class BatchedCall:
 
 def fcc_dct_batched(plans, ins, outs, direction, stream=None):
     BatchedCall(plans, ins, outs, direction)(stream)
+
+
+def fcc_spectrum_quantise(X, threshold, step, codes=None, Xq=None, kept=None, stream=None):
+    """Threshold and quantise a complex64 spectrum on the GPU (block-wise coding).
+    X: complex64 tensor; codes: int16 tensor of 2*len(X) (or None); Xq: complex64
+    tensor (or None); kept: int64 device tensor of one element (or None).
+    Returns the kept tensor (the count is read after synchronisation)."""
+    import torch
+    if kept is None:
+        kept = torch.zeros(1, dtype=torch.int64, device=X.device)
+    _check(_lib.fcc_spectrum_quantise(_ptr(X), int(X.numel()), float(threshold), float(step), _ptr(codes), _ptr(Xq),
+                                      _ptr(kept), _stream(stream)), "fcc_spectrum_quantise")
+    return kept
+
+
+def fcc_dct_packed_size(plan):
+    """Complex values of the plan's forward output (n^3, or the Hermitian-packed count)."""
+    c = ctypes.c_longlong(0)
+    _check(_lib.fcc_dct_packed_size(plan.handle, ctypes.byref(c)), "fcc_dct_packed_size")
+    return int(c.value)
 
 
 def fcc_dct_batched_release():

@@ -807,6 +807,98 @@ __global__ void k_orbit_nodes(OrbitNode* out, int L, const double2* __restrict__
   }
 }
 
+// The last level of the transposed transform (node size 2, B_2 = C_2 = I),
+// one thread per node J at level L = D - 1 (its 8 points J + 2^L i):
+//   forward (kInv false): y = DCT_2(phi)^T z = A(phi)^T H_8 z,
+//   inverse (kInv true) : y = DCT_2(phi)^{-T} z = H_8 A(phi)^{-T} z / 8 (solves with A^T).
+template <typename R, typename TI, typename TO, bool kInv>
+__global__ __launch_bounds__(256) void k_tr_last(VolSet vs, int nvol, int n, int L, const double2* __restrict__ hph) {
+  const long long nodes = 1LL << (3 * L);
+  const long long tg = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tg >= nodes * nvol) return;
+  const long long vol = tg / nodes, node = tg - vol * nodes;
+  const int mask = (1 << L) - 1;
+  const int J[3] = {int(node >> (2 * L)), int((node >> L) & mask), int(node & mask)};
+  const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, vol));
+  TO* __restrict__ out = static_cast<TO*>(vol_ptr(vs.out, vol));
+  cx<R> z[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) z[i] = IO<TI, R>::ld(in, gpos(n, L, J, (i >> 2) & 1, (i >> 1) & 1, i & 1));
+  cx<R> Q[3][3], a4[4][4], a3[3][3];
+  node_pos_powers(hph, L, J, Q);
+  build_A(Q, a4, a3);
+  const int c4[4] = {1, 3, 4, 6}, c3[3] = {2, 5, 7};
+  cx<R> y[8];
+  if constexpr (!kInv) {
+    hadamard8(z);
+    y[0] = z[0];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      cx<R> acc{R(0), R(0)};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc = acc + a4[i][j] * z[c4[i]];
+      y[c4[j]] = acc;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      cx<R> acc{R(0), R(0)};
+#pragma unroll
+      for (int i = 0; i < 3; ++i) acc = acc + a3[i][j] * z[c3[i]];
+      y[c3[j]] = acc;
+    }
+  } else {
+    cx<R> t4[4][4], t3[3][3], b4[4], b3[3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      b4[i] = z[c4[i]];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) t4[i][j] = a4[j][i];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      b3[i] = z[c3[i]];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) t3[i][j] = a3[j][i];
+    }
+    solve_small<R, 4>(t4, b4);
+    solve_small<R, 3>(t3, b3);
+    y[0] = z[0];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) y[c4[i]] = b4[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) y[c3[i]] = b3[i];
+    hadamard8(y);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) y[i] = R(0.125) * y[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) IO<TO, R>::st(out, gpos(n, L, J, (i >> 2) & 1, (i >> 1) & 1, i & 1), y[i]);
+}
+
+// Hermitian packing of the spectrum of real input: the sample points pair up
+// as iota' = (c - g^T iota) mod n with X[iota'] = conj X[iota] (g in W fixed
+// by the skew, Sec. III realness of T); slot[iota] = k >= 0 for the k-th
+// representative (iota <= iota' in flat order), -(k + 1) for the partner of
+// representative k.
+template <typename T>
+__global__ __launch_bounds__(256) void k_hpack(const T* __restrict__ full, T* __restrict__ packed,
+                                               const int* __restrict__ slot, long long N) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int k = slot[i];
+  if (k >= 0) packed[k] = full[i];
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_hunpack(const T* __restrict__ packed, T* __restrict__ full,
+                                                 const int* __restrict__ slot, long long N) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int k = slot[i];
+  T v = packed[k >= 0 ? k : -k - 1];
+  if (k < 0) v.y = -v.y;
+  full[i] = v;
+}
+
 // Inverse level L, first pass: y = DCT_2(phi)^{-1} z = A(phi)^{-1} H_8 z / 8 on every cube.
 template <typename R, typename TI>
 __global__ __launch_bounds__(256) void k_inv_dct2(VolSet vs, int nvol, int n, int L, const double2* __restrict__ hph,
@@ -1602,9 +1694,28 @@ fcc_status device_orbit_level(int dev, int nl, DevOrbitLevel* out) {
     for (int j = 0; j < T.nc; ++j)
       for (int i = 0; i < 9; ++i) wmat.push_back(int8_t(G[T.w[j]][i]));
     while (wmat.size() % 16) wmat.push_back(0);
-    for (int side = 0; side < 2; ++side) {
-      const std::vector<int>& rp = side ? T.c_rowptr : T.b_rowptr;
-      const std::vector<uint16_t>& en = side ? T.c_ent : T.b_ent;
+    // transposed sides: row s of B^T lists the rows r of B that read slot s
+    // (with B's coefficient), and likewise for C^T
+    auto transpose = [&](const std::vector<int>& rp, const std::vector<uint16_t>& en, std::vector<int>* trp,
+                         std::vector<uint16_t>* ten) {
+      const int rows = 8 * T.nc;
+      std::vector<std::vector<uint16_t>> byrow(rows);
+      for (int r = 0; r < rows; ++r)
+        for (int e = rp[r]; e < rp[r + 1]; ++e) byrow[en[e] >> 8].push_back(uint16_t((r << 8) | (en[e] & 255u)));
+      trp->assign(1, 0);
+      ten->clear();
+      for (int r = 0; r < rows; ++r) {
+        ten->insert(ten->end(), byrow[r].begin(), byrow[r].end());
+        trp->push_back(int(ten->size()));
+      }
+    };
+    std::vector<int> bt_rp, ct_rp;
+    std::vector<uint16_t> bt_en, ct_en;
+    transpose(T.b_rowptr, T.b_ent, &bt_rp, &bt_en);
+    transpose(T.c_rowptr, T.c_ent, &ct_rp, &ct_en);
+    for (int side = 0; side < 4; ++side) {
+      const std::vector<int>& rp = side == 0 ? T.b_rowptr : side == 1 ? T.c_rowptr : side == 2 ? bt_rp : ct_rp;
+      const std::vector<uint16_t>& en = side == 0 ? T.b_ent : side == 1 ? T.c_ent : side == 2 ? bt_en : ct_en;
       std::vector<int> seg(1, 0);
       std::vector<uint32_t> se;
       for (int r = 0; r < 8 * T.nc; ++r)
@@ -1867,9 +1978,13 @@ bool inv_last2(const fcc_plan_s* p) {
          arith64(p, p->D - 2) == arith64(p, p->D - 1);
 }
 // number of launch slots of one transform in direction d (0 forward, 1 inverse)
+// (Hermitian-packed plans add the pack launch after the forward and the
+// unpack launch before the inverse.)
 int slot_count(const fcc_plan_s* p, int d) {
-  if (p->n == 1 || p->dense) return 1;
-  int k = 1;
+  const int extra = p->hslot ? 1 : 0;
+  if (p->n == 1 || p->dense) return 1 + extra;
+  if (p->transposed) return p->D;
+  int k = 1 + extra;
   if (d == 1) {
     for (int L = 0; L < p->tail_Lt[1]; ++L) k += orbit_at(p, 1, L) ? 1 : 2;
     return inv_last2(p) ? k - 1 : k;
@@ -1903,10 +2018,32 @@ std::vector<SlotDesc> describe_slots(const fcc_plan_s* p, int d) {
   const int rin = (p->flags & FCC_REAL_INPUT) ? r : c;
   std::vector<SlotDesc> v;
   auto L_ = [](int L) { return " L" + std::to_string(L); };
+  if (p->hslot) {
+    // the plain transform's slots, then the pack launch (forward), or the
+    // unpack launch, then the plain slots (inverse): full spectrum <-> packed
+    fcc_plan_s q = *p;
+    q.hslot = nullptr;
+    std::vector<SlotDesc> b = describe_slots(&q, d);
+    if (d == 0)
+      b.push_back({"k_hpack", c, c});
+    else
+      b.insert(b.begin(), {"k_hunpack", c, c});
+    return b;
+  }
   if (p->n == 1) return {{d == 0 ? "k_copy1" : "k_copy1", d == 0 ? rin : c, d == 0 ? c : rin}};
   if (p->dense) return {{std::string("k_split_gemm") + (p->prec == FCC_PREC_SPLIT_FP16 ? "<f16>" : "<bf16>"),
                          d == 0 ? rin : c, d == 0 ? c : rin}};
   const int D = p->D;
+  if (p->transposed) {
+    if (d == 0) {
+      v.push_back({"k_tr_last" + L_(D - 1), rin, c});
+      for (int L = D - 2; L >= 0; --L) v.push_back({"k_tr_orbit" + L_(L), c, c});
+    } else {
+      for (int L = 0; L <= D - 2; ++L) v.push_back({"k_tr_inv_orbit" + L_(L), c, c});
+      v.push_back({"k_tr_inv_last" + L_(D - 1), c, rin});
+    }
+    return v;
+  }
   if (d == 0) {
     for (int L = 0; L < p->tail_Lt[0]; ++L) {
       const int bi = L == 0 ? rin : c;
@@ -1955,10 +2092,10 @@ dim3 orbit_grid(const fcc_plan_s* p, int L, int nvol) {
 const OrbitNode* onodes_of(const fcc_plan_s* p, int L) {
   return static_cast<const OrbitNode*>(p->onodes) + p->onode_off[L];
 }
-template <typename R, typename TI, typename TO>
+template <typename R, typename TI, typename TO, bool kT = false>
 void fwd_orbit_launch(const fcc_plan_s* p, int L, const VolSet& vs, int nvol, hipStream_t st) {
-  launch((k_fwd_orbit<R, TI, TO>), orbit_grid(p, L, nvol), dim3(kOrbitThreads), 0, st, vs, nvol, p->n, L, p->olv[L],
-         phases(p, L), onodes_of(p, L));
+  launch((k_fwd_orbit<R, TI, TO, kT>), orbit_grid(p, L, nvol), dim3(kOrbitThreads), 0, st, vs, nvol, p->n, L,
+         p->olv[L], phases(p, L), onodes_of(p, L));
 }
 void fwd_orbit_dispatch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, int nvol, hipStream_t st) {
   if (arith64(p, L)) {
@@ -1976,10 +2113,10 @@ void fwd_orbit_dispatch(const fcc_plan_s* p, int L, DT ti, const VolSet& vs, int
       fwd_orbit_launch<float, float2, float2>(p, L, vs, nvol, st);
   }
 }
-template <typename R, typename TI, typename TO>
+template <typename R, typename TI, typename TO, bool kT = false>
 void inv_orbit_launch(const fcc_plan_s* p, int L, const VolSet& vs, int nvol, hipStream_t st) {
-  launch((k_inv_orbit<R, TI, TO>), orbit_grid(p, L, nvol), dim3(kOrbitThreads), 0, st, vs, nvol, p->n, L, p->olv[L],
-         phases(p, L), onodes_of(p, L));
+  launch((k_inv_orbit<R, TI, TO, kT>), orbit_grid(p, L, nvol), dim3(kOrbitThreads), 0, st, vs, nvol, p->n, L,
+         p->olv[L], phases(p, L), onodes_of(p, L));
 }
 void inv_orbit_dispatch(const fcc_plan_s* p, int L, DT to, const VolSet& vs, int nvol, hipStream_t st) {
   if (arith64(p, L)) {
@@ -2174,8 +2311,60 @@ void copy1_dispatch(DT ti, DT to, const VolSet& vs, int nvol, hipStream_t st) {
 // after every launch, so slot k's duration is ev[k+1] - ev[k].
 // Enqueue the forward transform of nvol volumes that share plan p.
 // ws0/ws1: two scratch arrays of n^3 stage-precision complex per volume.
+fcc_status enqueue_transposed(const fcc_plan_s* p, int dir, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0,
+                              VolPtrs ws1, hipStream_t st);
+fcc_status enqueue_forward_plain(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0, VolPtrs ws1,
+                                 hipStream_t st);
+fcc_status enqueue_inverse_plain(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0, VolPtrs ws1,
+                                 hipStream_t st);
+void hpack_launch(const fcc_plan_s* p, bool unpack, const void* src, void* dst, hipStream_t st) {
+  const long long N = (long long)p->n * p->n * p->n;
+  const dim3 g(unsigned((N + 255) / 256)), b(256);
+  if (p->prec == FCC_PREC_FP64) {
+    if (unpack)
+      launch(k_hunpack<double2>, g, b, 0, st, static_cast<const double2*>(src), static_cast<double2*>(dst),
+             static_cast<const int*>(p->hslot), N);
+    else
+      launch(k_hpack<double2>, g, b, 0, st, static_cast<const double2*>(src), static_cast<double2*>(dst),
+             static_cast<const int*>(p->hslot), N);
+  } else {
+    if (unpack)
+      launch(k_hunpack<float2>, g, b, 0, st, static_cast<const float2*>(src), static_cast<float2*>(dst),
+             static_cast<const int*>(p->hslot), N);
+    else
+      launch(k_hpack<float2>, g, b, 0, st, static_cast<const float2*>(src), static_cast<float2*>(dst),
+             static_cast<const int*>(p->hslot), N);
+  }
+}
+// Enqueue the forward transform of nvol volumes that share plan p (the
+// transposed transform for FCC_TRANSPOSED plans; FCC_HERMITIAN_PACKED plans
+// serve one volume: the full spectrum goes to the plan's buffer, then packed).
 fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0, VolPtrs ws1,
                            hipStream_t st) {
+  if (p->transposed) return enqueue_transposed(p, 1, nvol, in, out, ws0, ws1, st);
+  if (p->hslot) {
+    if (nvol != 1 || out.arr) return FCC_ERR_UNSUPPORTED;
+    fcc_status s = enqueue_forward_plain(p, 1, in, VolPtrs{nullptr, p->hfull}, ws0, ws1, st);
+    if (s != FCC_OK) return s;
+    hpack_launch(p, false, p->hfull, out.one, st);
+    return launch_status("pack launch");
+  }
+  return enqueue_forward_plain(p, nvol, in, out, ws0, ws1, st);
+}
+fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0, VolPtrs ws1,
+                           hipStream_t st) {
+  if (p->transposed) return enqueue_transposed(p, -1, nvol, in, out, ws0, ws1, st);
+  if (p->hslot) {
+    if (nvol != 1 || in.arr) return FCC_ERR_UNSUPPORTED;
+    hpack_launch(p, true, in.one, p->hfull, st);
+    fcc_status s = launch_status("unpack launch");
+    if (s != FCC_OK) return s;
+    return enqueue_inverse_plain(p, 1, VolPtrs{nullptr, p->hfull}, out, ws0, ws1, st);
+  }
+  return enqueue_inverse_plain(p, nvol, in, out, ws0, ws1, st);
+}
+fcc_status enqueue_forward_plain(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0, VolPtrs ws1,
+                                 hipStream_t st) {
   if (p->n == 1) {
     copy1_dispatch(in_type(p), cplx_type(p), VolSet{in, out}, nvol, st);
     return launch_status("forward n=1 launch");
@@ -2235,8 +2424,8 @@ fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
   return launch_status("forward level launch");
 }
 
-fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0, VolPtrs ws1,
-                           hipStream_t st) {
+fcc_status enqueue_inverse_plain(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0, VolPtrs ws1,
+                                 hipStream_t st) {
   DT real_or_cplx = (p->flags & FCC_REAL_INPUT) ? in_type(p) : cplx_type(p);
   if (p->n == 1) {
     copy1_dispatch(cplx_type(p), real_or_cplx, VolSet{in, out}, nvol, st);
@@ -2304,6 +2493,97 @@ fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
     which ^= 1;
   }
   return launch_status("inverse level launch");
+}
+
+// The transposed transform (FCC_TRANSPOSED): forward X = F^T x runs the
+// factors of eq. FastAlgorithm transposed, deepest level first (DCT_2^T per
+// cube, then per level DCT_2^T and B^T over the orbits); the inverse
+// x = F^{-T} X runs C^T and DCT_2^{-T} from the top level down.
+template <typename R>
+void tr_last_dispatch(const fcc_plan_s* p, bool inv, DT ti, DT to, const VolSet& vs, int nvol, hipStream_t st) {
+  const int L = p->D - 1;
+  const long long nodes = (1LL << (3 * L)) * nvol;
+  const dim3 g(unsigned((nodes + 255) / 256)), b(256);
+  const double2* h = phases(p, L);
+  using RC = cx<R>;
+  (void)sizeof(RC);
+  auto go = [&](auto tin, auto tout) {
+    using TI = decltype(tin);
+    using TO = decltype(tout);
+    if (inv)
+      launch((k_tr_last<R, TI, TO, true>), g, b, 0, st, vs, nvol, p->n, L, h);
+    else
+      launch((k_tr_last<R, TI, TO, false>), g, b, 0, st, vs, nvol, p->n, L, h);
+  };
+  auto out_of = [&](auto tin) {
+    switch (to) {
+      case DT::F32R: go(tin, float{}); break;
+      case DT::F64R: go(tin, double{}); break;
+      case DT::F32C: go(tin, float2{}); break;
+      case DT::F64C: go(tin, double2{}); break;
+    }
+  };
+  switch (ti) {
+    case DT::F32R: out_of(float{}); break;
+    case DT::F64R: out_of(double{}); break;
+    case DT::F32C: out_of(float2{}); break;
+    case DT::F64C: out_of(double2{}); break;
+  }
+}
+fcc_status enqueue_transposed(const fcc_plan_s* p, int dir, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0,
+                              VolPtrs ws1, hipStream_t st) {
+  const DT real_or_cplx = (p->flags & FCC_REAL_INPUT) ? in_type(p) : cplx_type(p);
+  if (p->n == 1) {
+    copy1_dispatch(dir > 0 ? in_type(p) : cplx_type(p), dir > 0 ? cplx_type(p) : real_or_cplx, VolSet{in, out}, nvol,
+                   st);
+    return launch_status("transposed n=1 launch");
+  }
+  const int D = p->D;
+  const DT stg = stage_type(p);
+  if (dir > 0) {
+    VolPtrs dst = D == 1 ? out : ws0;
+    if (p->stages64)
+      tr_last_dispatch<double>(p, false, in_type(p), D == 1 ? cplx_type(p) : stg, VolSet{in, dst}, nvol, st);
+    else
+      tr_last_dispatch<float>(p, false, in_type(p), D == 1 ? cplx_type(p) : stg, VolSet{in, dst}, nvol, st);
+    VolPtrs cur = ws0;
+    int which = 1;
+    for (int L = D - 2; L >= 0; --L) {
+      VolPtrs d2 = L == 0 ? out : (which ? ws1 : ws0);
+      const DT to = L == 0 ? cplx_type(p) : stg;
+      if (p->stages64) {
+        if (to == DT::F32C)
+          inv_orbit_launch<double, double2, float2, true>(p, L, VolSet{cur, d2}, nvol, st);
+        else
+          inv_orbit_launch<double, double2, double2, true>(p, L, VolSet{cur, d2}, nvol, st);
+      } else {
+        inv_orbit_launch<float, float2, float2, true>(p, L, VolSet{cur, d2}, nvol, st);
+      }
+      cur = d2;
+      which ^= 1;
+    }
+    return launch_status("transposed forward launch");
+  }
+  VolPtrs src = in;
+  DT src_t = cplx_type(p);
+  for (int L = 0; L <= D - 2; ++L) {
+    VolPtrs d2 = (L & 1) ? ws1 : ws0;
+    if (p->stages64) {
+      if (src_t == DT::F32C)
+        fwd_orbit_launch<double, float2, double2, true>(p, L, VolSet{src, d2}, nvol, st);
+      else
+        fwd_orbit_launch<double, double2, double2, true>(p, L, VolSet{src, d2}, nvol, st);
+    } else {
+      fwd_orbit_launch<float, float2, float2, true>(p, L, VolSet{src, d2}, nvol, st);
+    }
+    src = d2;
+    src_t = stg;
+  }
+  if (p->stages64)
+    tr_last_dispatch<double>(p, true, src_t, real_or_cplx, VolSet{src, out}, nvol, st);
+  else
+    tr_last_dispatch<float>(p, true, src_t, real_or_cplx, VolSet{src, out}, nvol, st);
+  return launch_status("transposed inverse launch");
 }
 
 VolPtrs one_vol(const void* p) { return VolPtrs{nullptr, const_cast<void*>(p)}; }
@@ -2717,8 +2997,15 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
   if (!is_pow2(n)) return FCC_ERR_NOT_POW2;
   if (prec < FCC_PREC_FP64 || prec > FCC_PREC_SPLIT_FP16) return FCC_ERR_INVALID_ARG;
   if ((flags & FCC_STAGES_FP32) && (flags & FCC_STAGES_FP64)) return FCC_ERR_INVALID_ARG;
-  if (flags & ~(unsigned)(FCC_REAL_INPUT | FCC_STAGES_FP32 | FCC_STAGES_FP64 | FCC_LEVEL0_FP32))
+  if (flags & ~(unsigned)(FCC_REAL_INPUT | FCC_STAGES_FP32 | FCC_STAGES_FP64 | FCC_LEVEL0_FP32 | FCC_TRANSPOSED |
+                          FCC_HERMITIAN_PACKED))
     return FCC_ERR_INVALID_ARG;
+  const bool split_prec = prec == FCC_PREC_SPLIT_BF16 || prec == FCC_PREC_SPLIT_FP16;
+  if ((flags & FCC_TRANSPOSED) &&
+      (split_prec || (flags & (FCC_LEVEL0_FP32 | FCC_HERMITIAN_PACKED)) || n > 256))
+    return FCC_ERR_UNSUPPORTED;
+  if ((flags & FCC_HERMITIAN_PACKED) && !(flags & FCC_REAL_INPUT)) return FCC_ERR_INVALID_ARG;
+  if ((flags & FCC_HERMITIAN_PACKED) && split_prec) return FCC_ERR_UNSUPPORTED;
   if (tuning && !valid_tuning(*tuning)) return FCC_ERR_INVALID_ARG;
   // per-row tables pack node-local coordinates in 8 bits: node sizes above 256
   // need orbit-block launches in both directions
@@ -2780,11 +3067,14 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
   // Levels that run as orbit-block launches in both directions read no
   // per-row table; the others need one, and its packed entries hold node-local
   // coordinates in 8 bits (node size <= 256).
+  // (The transposed transform runs orbit-block launches at every level with
+  // node size >= 4 and a per-cube pass at the last: no table anywhere.)
+  p->transposed = (flags & FCC_TRANSPOSED) != 0;
   bool tables[16] = {};
   for (int L = 0; L < p->D; ++L) {
     const bool orb = (n >> L) >= 8 && L < 10 && (p->tune.map[0][L] & FCC_MAP_ORBIT) &&
                      (p->tune.map[1][L] & FCC_MAP_ORBIT);
-    tables[L] = !orb;
+    tables[L] = !orb && !p->transposed;
     if (tables[L] && (n >> L) > 256) {
       delete p;
       return FCC_ERR_UNSUPPORTED;
@@ -2794,7 +3084,8 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
     std::lock_guard<std::mutex> lock(cache().mu);
     p->olv.assign(p->D, DevOrbitLevel{});
     for (int L = 0; s == FCC_OK && L < p->D && L < 10; ++L)
-      if ((n >> L) >= 8 && ((p->tune.map[0][L] | p->tune.map[1][L]) & FCC_MAP_ORBIT))
+      if (p->transposed ? (n >> L) >= 4
+                        : ((n >> L) >= 8 && ((p->tune.map[0][L] | p->tune.map[1][L]) & FCC_MAP_ORBIT)))
         s = device_orbit_level(p->device, n >> L, &p->olv[L]);
     for (int L = 0; s == FCC_OK && L < p->D; ++L) {
       DevLevel lv{};
@@ -2824,7 +3115,7 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
     // plain-order tables with one cube per slice for every level a fused
     // tail may cover (node sizes <= 16); levels >= 2 have them already
     p->tlv.resize(p->D);
-    for (int L = std::max(0, p->D - 4); s == FCC_OK && L < p->D; ++L) {
+    for (int L = std::max(0, p->D - 4); s == FCC_OK && !p->transposed && L < p->D; ++L) {
       if (L >= 2 && tables[L])
         p->tlv[L] = p->lv[L];
       else
@@ -2892,6 +3183,63 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
       if (e != hipSuccess) s = hip_fail(e, "hipMalloc(scratch)", __LINE__);
     }
   }
+  if (s == FCC_OK && (flags & FCC_HERMITIAN_PACKED)) {
+    // the pairing j' = (c - g^T j) mod n: g in W with c = -g^T rst - rst integral
+    const auto& G = weyl_group();
+    int gsel = -1;
+    long long cv[3] = {0, 0, 0};
+    for (int w = 0; w < 24 && gsel < 0; ++w) {
+      bool ok = true;
+      long long c[3];
+      for (int i = 0; i < 3 && ok; ++i) {
+        double v = -r[i];
+        for (int k = 0; k < 3; ++k) v -= double(G[w][3 * k + i]) * r[k];  // (g^T rst)_i = sum_k g[k][i] rst_k
+        ok = std::fabs(v - std::nearbyint(v)) < 1e-12;
+        c[i] = (long long)std::nearbyint(v);
+      }
+      if (ok) {
+        gsel = w;
+        for (int i = 0; i < 3; ++i) cv[i] = c[i];
+      }
+    }
+    if (gsel < 0) {
+      s = FCC_ERR_UNSUPPORTED;
+    } else {
+      const long long N = (long long)n * n * n;
+      std::vector<int> slot;
+      try {
+        slot.assign(size_t(N), 0);
+      } catch (const std::bad_alloc&) {
+        s = FCC_ERR_OOM;
+      }
+      if (s == FCC_OK) {
+        const auto& g = G[gsel];
+        auto partner = [&](long long j) {
+          const long long v[3] = {j / ((long long)n * n), (j / n) % n, j % n};
+          long long q[3];
+          for (int i = 0; i < 3; ++i) {
+            long long t = cv[i];
+            for (int k = 0; k < 3; ++k) t -= (long long)g[3 * k + i] * v[k];
+            q[i] = ((t % n) + n) % n;
+          }
+          return (q[0] * n + q[1]) * n + q[2];
+        };
+        long long k = 0;
+        for (long long j = 0; j < N; ++j)
+          if (j <= partner(j)) slot[size_t(j)] = int(k++);
+        for (long long j = 0; j < N; ++j) {
+          const long long q = partner(j);
+          if (j > q) slot[size_t(j)] = -slot[size_t(q)] - 1;
+        }
+        p->hpacked = k;
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->hslot), sizeof(int) * size_t(N));
+        if (e == hipSuccess) e = hipMemcpy(p->hslot, slot.data(), sizeof(int) * size_t(N), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+          e = hipMalloc(&p->hfull, size_t(N) * (prec == FCC_PREC_FP64 ? sizeof(double2) : sizeof(float2)));
+        if (e != hipSuccess) s = hip_fail(e, "hermitian packing tables", __LINE__);
+      }
+    }
+  }
   if (s == FCC_OK) {
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) s = hip_fail(e, "hipStreamSynchronize", __LINE__);
@@ -2929,6 +3277,8 @@ fcc_status fcc_dct_destroy(fcc_plan_t p) {
   if (p->resid) (void)hipFree(p->resid);
   if (p->nodes) (void)hipFree(p->nodes);
   if (p->onodes) (void)hipFree(p->onodes);
+  if (p->hslot) (void)hipFree(p->hslot);
+  if (p->hfull) (void)hipFree(p->hfull);
   if (p->hph) (void)hipFree(p->hph);
   for (void* w : p->ws)
     if (w) (void)hipFree(w);
@@ -3333,6 +3683,8 @@ fcc_status fcc_dct_batched(const fcc_plan_t* plans, int count, const void* const
   for (int i = 0; i < count; ++i)
     if (!plans[i] || !in[i] || !out[i] || !aligned16(in[i]) || !aligned16(out[i]) || in[i] == out[i])
       return FCC_ERR_INVALID_ARG;
+  for (int i = 0; i < count; ++i)
+    if (plans[i]->hslot) return FCC_ERR_UNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   (void)hipGetLastError();
   std::vector<uintptr_t> key;
@@ -3373,6 +3725,12 @@ fcc_status fcc_dct_batched(const fcc_plan_t* plans, int count, const void* const
   }
   hipError_t e = hipGraphLaunch(bx->exec, st);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch", __LINE__);
+  return FCC_OK;
+}
+
+fcc_status fcc_dct_packed_size(fcc_plan_t p, long long* count) {
+  if (!p || !count) return FCC_ERR_INVALID_ARG;
+  *count = p->hslot ? p->hpacked : (long long)p->n * p->n * p->n;
   return FCC_OK;
 }
 

@@ -166,10 +166,12 @@ struct GatherMap {
 struct DevOrbitKind {
   int nc;             // cubes of the orbit
   int off_w;          // wmat: 9 nc entries, the matrices G[w_j] of the cube slots (row-major)
-  int off_perm[2];    // i16: 8 ceil(nc/8) cube slots in wavefront order (-1: idle lane), [0] B, [1] C
-  int off_rowptr[2];  // u16: 40 nc + 1 segment starts of B (C), relative to off_ent
-  int off_ent[2];     // u32: entries (slot << 16) | (k & 0xffff), coefficient k / 144
-  int nent[2];        // entries of B (C)
+  // sides: [0] B, [1] C, [2] B^T, [3] C^T (the transposed transform's factors;
+  // B^T has C's layout and C^T has B's: rows are indexed by the other side's slots)
+  int off_perm[4];    // i16: 8 ceil(nc/8) cube slots in wavefront order (-1: idle lane)
+  int off_rowptr[4];  // u16: 40 nc + 1 segment starts, relative to off_ent
+  int off_ent[4];     // u32: entries (slot << 16) | (k & 0xffff), coefficient k / 144
+  int nent[4];
 };
 // Templates and representatives of one node size.  Each row of B (C) is split
 // by the monomials {1, c3, c1, c2, c1 c3} of the node's coefficient

@@ -189,13 +189,15 @@ __device__ __forceinline__ cx<R> orbit_row(const OrbitShared<R>& sh, int s0, int
 
 // Forward level L: y = B_nl(c) x on the block's orbits and nodes, then
 // z = DCT_2(phi) y per cube, stored at the cube's 8 positions.
-template <typename R, typename TI, typename TO>
+// kT: the transposed transform's inverse level instead: rows of C^T (side 3),
+// then DCT_2(phi)^{-T} per cube.
+template <typename R, typename TI, typename TO, bool kT>
 __global__ __launch_bounds__(kOrbitThreads) void k_fwd_orbit(VolSet vs, int nvol, int n, int L, DevOrbitLevel ol,
                                                              const double2* __restrict__ hph,
                                                              const OrbitNode* __restrict__ onodes) {
   __shared__ OrbitShared<R> sh;
   OrbitBlock ob;
-  if (!orbit_setup<R>(ol, L, nvol, 0, hph, ob, sh)) return;
+  if (!orbit_setup<R>(ol, L, nvol, kT ? 3 : 0, hph, ob, sh)) return;
   __syncthreads();
   const int mask = (1 << ol.lgm) - 1;
   const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, ob.vol));
@@ -232,11 +234,14 @@ __global__ __launch_bounds__(kOrbitThreads) void k_fwd_orbit(VolSet vs, int nvol
   // f + 1 is loaded while row f is summed)
   const OrbitNode& on = onodes[ob.node0 + u % ob.G];
   cx<R> y[8];
+  // column f of the matrix: D[f * 8 + i] (forward), or row f of DCT_2^{-1},
+  // Dinv[i * 8 + f] (transposed inverse)
+  auto col = [&](int f, int i) { return kT ? on.Dinv[i * 8 + f] : on.D[f * 8 + i]; };
   double2 dcol[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     y[i] = {R(0), R(0)};
-    dcol[i] = on.D[i];
+    dcol[i] = col(0, i);
   }
 #pragma unroll 1
   for (int f = 0; f < 8; ++f) {
@@ -245,7 +250,7 @@ __global__ __launch_bounds__(kOrbitThreads) void k_fwd_orbit(VolSet vs, int nvol
     for (int i = 0; i < 8; ++i) cur[i] = dcol[i];
     if (f < 7) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) dcol[i] = on.D[(f + 1) * 8 + i];
+      for (int i = 0; i < 8; ++i) dcol[i] = col(f + 1, i);
     }
     const cx<R> yf = orbit_row(sh, (j * 8 + f) * kNumMono, u, mono);
 #pragma unroll
@@ -263,13 +268,15 @@ __global__ __launch_bounds__(kOrbitThreads) void k_fwd_orbit(VolSet vs, int nvol
 // Inverse level L: y = DCT_2(phi)^{-1} z per cube of the block's orbits and
 // nodes, then x(q' + m o) = row (q', o) of C_nl(c) applied to the orbit's cube
 // values.
-template <typename R, typename TI, typename TO>
+// kT: the transposed transform's level instead: DCT_2(phi)^T per cube, then
+// the rows of B^T (side 2).
+template <typename R, typename TI, typename TO, bool kT>
 __global__ __launch_bounds__(kOrbitThreads) void k_inv_orbit(VolSet vs, int nvol, int n, int L, DevOrbitLevel ol,
                                                              const double2* __restrict__ hph,
                                                              const OrbitNode* __restrict__ onodes) {
   __shared__ OrbitShared<R> sh;
   OrbitBlock ob;
-  if (!orbit_setup<R>(ol, L, nvol, 1, hph, ob, sh)) return;
+  if (!orbit_setup<R>(ol, L, nvol, kT ? 2 : 1, hph, ob, sh)) return;
   __syncthreads();
   const int mask = (1 << ol.lgm) - 1;
   const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, ob.vol));
@@ -285,7 +292,7 @@ __global__ __launch_bounds__(kOrbitThreads) void k_inv_orbit(VolSet vs, int nvol
       for (int i = 0; i < 8; ++i)
         z[i] = IO<TI, R>::ld(in, gpos(n, L, J, 2 * q[0] + ((i >> 2) & 1), 2 * q[1] + ((i >> 1) & 1),
                                        2 * q[2] + (i & 1)));
-      // y = DCT_2(phi)^{-1} z
+      // y = DCT_2(phi)^{-1} z (transposed transform: DCT_2(phi)^T z)
       const OrbitNode& on = onodes[ob.node0 + u % ob.G];
       cx<R> y[8];
 #pragma unroll
@@ -293,7 +300,7 @@ __global__ __launch_bounds__(kOrbitThreads) void k_inv_orbit(VolSet vs, int nvol
 #pragma unroll
       for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int f = 0; f < 8; ++f) y[f] = y[f] + ldc<R>(on.Dinv[i * 8 + f]) * z[i];
+        for (int f = 0; f < 8; ++f) y[f] = y[f] + ldc<R>(kT ? on.D[f * 8 + i] : on.Dinv[i * 8 + f]) * z[i];
 #pragma unroll
       for (int f = 0; f < 8; ++f) sh.val[(j * 8 + f) * kOrbitUnits + u] = y[f];
     }

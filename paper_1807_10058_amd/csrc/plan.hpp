@@ -39,6 +39,10 @@ struct fcc_plan_s {
   int tail_Lt[2] = {0, 0};              // first level of the fused LDS tail: [0] forward, [1] inverse
   std::vector<fcc::DevLevel> tlv;
   std::vector<fcc::DevOrbitLevel> olv;  // per level L: orbit templates of nl = n >> L (orbit levels only)
+  bool transposed = false;              // FCC_TRANSPOSED: the transform's transpose (and its inverse)
+  int* hslot = nullptr;                 // FCC_HERMITIAN_PACKED: per point, packed slot (see k_hpack)
+  void* hfull = nullptr;                // FCC_HERMITIAN_PACKED: the full spectrum
+  long long hpacked = 0;                // FCC_HERMITIAN_PACKED: complex values of the packed spectrum
   void* onodes = nullptr;               // dense DCT_2 and inverse per node of the orbit-block levels
   long long onode_off[16] = {};         // per level offset into onodes, -1 if none       // per level from min(tail_Lt) on: plain-order tables, S = 1
   unsigned char kf[2][16][8] = {};      // balanced map: log2 lanes per row, per side, level and f

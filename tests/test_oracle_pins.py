@@ -257,3 +257,35 @@ def test_fold_inverse_undoes_the_direct_forward(n):
     assert np.abs(y - x).max() <= 1e-12 * np.abs(x).max()
     pts = RNG.choice(n ** 3, 40, replace=False)
     assert np.array_equal(fold_ref.fold_inverse(X, n, points=pts), y[pts])
+
+
+@pytest.mark.parametrize("n", [2, 4, 8])
+def test_transposed_rows_are_the_matrix_transpose(n):
+    """The transposed reading X_T = F^T x (the literal row/column labels after
+    eq. SU4ChebyshevTransformExplicitForm), entry by entry from the orbit sum,
+    equals the transpose of the direct matrix."""
+    F = oracle.matrix(n)
+    x = RNG.standard_normal(n ** 3) + 1j * RNG.standard_normal(n ** 3)
+    ks = RNG.choice(n ** 3, min(16, n ** 3), replace=False)
+    assert np.abs(oracle.transposed_rows(x, n, ks) - (F.T @ x)[ks]).max() <= 1e-12 * np.abs(F.T @ x).max()
+
+
+@pytest.mark.parametrize("n", [2, 4, 8])
+def test_hermitian_pairing_of_real_spectra(n):
+    """For real input, X[j'] = conj X[j] with j' = -g^T j mod n for the one g of W
+    with g^T rst = -rst mod 1 (realness of T, Sec. III: conj T_(j,k,p) = T_(p,k,j));
+    the pairing is an involution with n^2 fixed points."""
+    G = oracle.group()
+    rst = np.array(oracle.DEFAULT_RST)
+    gs = [g for g in G if np.allclose(np.mod(-g.T @ rst - rst + 0.5, 1.0), 0.5)]
+    assert len(gs) == 1
+    g = gs[0]
+    c = np.rint(-g.T @ rst - rst).astype(int)
+    j = np.stack(np.unravel_index(np.arange(n ** 3), (n, n, n)), -1)
+    q = np.mod(-(j @ g) + c, n)
+    jp = (q[:, 0] * n + q[:, 1]) * n + q[:, 2]
+    assert np.array_equal(jp[jp], np.arange(n ** 3))
+    assert (jp == np.arange(n ** 3)).sum() == n * n
+    x = RNG.standard_normal(n ** 3)
+    X = oracle.forward(x, n)
+    assert np.abs(X[jp] - np.conj(X)).max() <= 1e-12 * np.abs(X).max()
