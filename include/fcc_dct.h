@@ -87,7 +87,17 @@ enum {
    * the self-paired zeros, in increasing flat index: fcc_dct_packed_size
    * values.  The inverse reads that form.  Skews without such a pairing return
    * FCC_ERR_UNSUPPORTED; fcc_dct_batched does not take these plans. */
-  FCC_HERMITIAN_PACKED = 1u << 5
+  FCC_HERMITIAN_PACKED = 1u << 5,
+  /* A variant, not the paper's factorisation: the same transform through the
+   * fold+FFT form that follows from the explicit matrix (Sec. IV-A, eq.
+   * SU4ChebyshevTransformExplicitForm, with the two sums exchanged):
+   * X = N IDFT_3(Fh), Fh[mu] = (1/24) sum_{g kappa = mu mod n} x[kappa]
+   * exp(2 pi i (g kappa).rst / n); the inverse takes Fh = DFT_3(X) / N and
+   * undoes the fold orbit by orbit (the Gram blocks of the fold).  All
+   * arithmetic in the data precision (FCC_PREC_FP32 runs FP32 throughout).
+   * Needs 8 rst integral (the default skew is); FP64 or FP32; n <= 512; not
+   * with the other flags except FCC_REAL_INPUT. */
+  FCC_FOLD_FFT = 1u << 6
 };
 
 /* Build a plan for DCT_{n x n x n}(r,s,t) (Definition 2).
@@ -158,6 +168,19 @@ fcc_status fcc_dct_batched(const fcc_plan_t* plans, int count, const void* const
 /* Number of complex values in the forward output of a plan: n^3, or the
  * packed count with FCC_HERMITIAN_PACKED.  Errors: FCC_ERR_INVALID_ARG. */
 fcc_status fcc_dct_packed_size(fcc_plan_t plan, long long* count);
+
+/* Host-only (no device call): the unfold tables of the FCC_FOLD_FFT inverse
+ * for size n and skew rst (8 rst integral).  Point k (flat index) has the row
+ * K[pid[k]] of 24 complex values, one per element u of W (in the closure order
+ * of the generators of eq. GeneratorMatricesS4, identity first), and
+ *   x[k] = sum_u K[pid[k]][u] exp(-2 pi i (u k).rst / n) Fh[u k mod n],
+ *   Fh = DFT_3(X) / n^3,
+ * inverts the transform.  pid: n^3 bytes; K: 256 * 24 * 2 doubles
+ * (interleaved complex), caller-owned; *npat receives the number of rows.
+ * Errors: FCC_ERR_INVALID_ARG (null pointers, n not a power of two <= 1024),
+ * FCC_ERR_UNSUPPORTED (8 rst not integral, more than 256 distinct rows),
+ * FCC_ERR_SINGULAR_SKEW (a singular block), FCC_ERR_OOM. */
+fcc_status fcc_fold_unfold_tables(int n, const double rst[3], unsigned char* pid, double* K, int* npat);
 
 /* Free every graph (and its scratch) that fcc_dct_batched has recorded.  At
  * most 4 are kept anyway (the least recently used is freed when a new one is

@@ -12,7 +12,7 @@ _LIB_PATH = os.path.join(_HERE, "libfccdct.so")
 FCC_OK = 0
 FCC_PREC_FP64, FCC_PREC_FP32, FCC_PREC_SPLIT_BF16, FCC_PREC_SPLIT_FP16 = 0, 1, 2, 3
 FCC_REAL_INPUT, FCC_STAGES_FP32, FCC_STAGES_FP64, FCC_LEVEL0_FP32 = 1, 2, 4, 8
-FCC_TRANSPOSED, FCC_HERMITIAN_PACKED = 16, 32
+FCC_TRANSPOSED, FCC_HERMITIAN_PACKED, FCC_FOLD_FFT = 16, 32, 64
 (FCC_MAP_XCD, FCC_MAP_F_INNER, FCC_MAP_NODES8, FCC_MAP_NODES64, FCC_MAP_SPLIT, FCC_MAP_BALANCE, FCC_MAP_XCD16,
  FCC_MAP_CLUSTER, FCC_MAP_ORBIT) = 1, 2, 4, 8, 16, 32, 64, 128, 256
 _MAX_LEVELS = 10
@@ -95,6 +95,8 @@ _lib.fcc_dct_batched.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINT
 _lib.fcc_dct_destroy.argtypes = [_vp]
 _lib.fcc_dct_batched_release.argtypes = []
 _lib.fcc_dct_packed_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_longlong)]
+_lib.fcc_fold_unfold_tables.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), _vp, _vp,
+                                        ctypes.POINTER(ctypes.c_int)]
 _lib.fcc_spectrum_quantise.argtypes = [_vp, ctypes.c_longlong, ctypes.c_float, ctypes.c_float, _vp, _vp, _vp, _vp]
 _lib.fcc_dct_describe_launches.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_LaunchInfo), ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_int)]
@@ -110,7 +112,7 @@ _lib.fcc_status_string.restype = ctypes.c_char_p
 _lib.fcc_asp_tables.argtypes = [ctypes.c_int, ctypes.POINTER(_LevelTables)]
 _lib.fcc_asp_orbit_blocks.argtypes = [ctypes.c_int, ctypes.POINTER(_OrbitBlocks)]
 for _f in ("fcc_dct_plan", "fcc_dct_plan_tuned", "fcc_dct_get_tuning", "fcc_dct_autotune", "fcc_dct_forward", "fcc_dct_forward_static", "fcc_dct_inverse", "fcc_dct_batched", "fcc_dct_destroy", "fcc_dct_batched_release",
-           "fcc_dct_describe_launches", "fcc_dct_batched_time_launches", "fcc_spectrum_quantise", "fcc_dct_packed_size",
+           "fcc_dct_describe_launches", "fcc_dct_batched_time_launches", "fcc_spectrum_quantise", "fcc_dct_packed_size", "fcc_fold_unfold_tables",
            "fcc_asp_tables", "fcc_asp_orbit_blocks", "fcc_dct_time_launches", "fcc_dct_roundtrip_residual"):
     getattr(_lib, _f).restype = ctypes.c_int
 
@@ -260,6 +262,18 @@ def fcc_dct_packed_size(plan):
     c = ctypes.c_longlong(0)
     _check(_lib.fcc_dct_packed_size(plan.handle, ctypes.byref(c)), "fcc_dct_packed_size")
     return int(c.value)
+
+
+def fcc_fold_unfold_tables(n, rst=None):
+    """Host-only unfold tables of the fold+FFT inverse: (pid uint8[n^3], K complex[npat, 24])."""
+    import numpy as np
+    r = (ctypes.c_double * 3)(*([0.125, 0.0, 0.375] if rst is None else [float(v) for v in rst]))
+    pid = np.zeros(n ** 3, dtype=np.uint8)
+    K = np.zeros((256, 24), dtype=np.complex128)
+    npat = ctypes.c_int(0)
+    _check(_lib.fcc_fold_unfold_tables(int(n), r, pid.ctypes.data, K.ctypes.data, ctypes.byref(npat)),
+           "fcc_fold_unfold_tables")
+    return pid, K[:npat.value].copy()
 
 
 def fcc_dct_batched_release():

@@ -7,7 +7,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfccdct.so")
-SOURCES = ["fcc_dct.hip", "dense.hip", "coding.hip", "asp_tables.cpp", "orbit_blocks.cpp"]
+SOURCES = ["fcc_dct.hip", "dense.hip", "coding.hip", "asp_tables.cpp", "orbit_blocks.cpp", "fold_plan.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -20,6 +20,7 @@
 
 #include "asp_tables.hpp"
 #include "fcc_dct.h"
+#include "fold_plan.hpp"
 #include "kernels.hpp"
 #include "orbit_blocks.hpp"
 #include "orbits.inc"
@@ -1375,6 +1376,7 @@ __global__ void k_phase_table(double2* out, int D, double r0, double r1, double 
 }  // namespace fcc
 
 #include "orbit_level.hpp"
+#include "fold_fft.hpp"
 
 
 // ===========================================================================
@@ -1982,6 +1984,7 @@ bool inv_last2(const fcc_plan_s* p) {
 // unpack launch before the inverse.)
 int slot_count(const fcc_plan_s* p, int d) {
   const int extra = p->hslot ? 1 : 0;
+  if (p->fold) return p->n == 1 ? 1 : 4;
   if (p->n == 1 || p->dense) return 1 + extra;
   if (p->transposed) return p->D;
   int k = 1 + extra;
@@ -2029,6 +2032,19 @@ std::vector<SlotDesc> describe_slots(const fcc_plan_s* p, int d) {
     else
       b.insert(b.begin(), {"k_hunpack", c, c});
     return b;
+  }
+  if (p->fold) {
+    // priced like the other launches: each DFT pass reads and writes the volume once
+    if (d == 0) {
+      v.push_back({"k_fold", rin, c});
+      if (p->n > 1)
+        for (const char* a : {"k_dft c", "k_dft b", "k_dft a"}) v.push_back({a, c, c});
+    } else {
+      if (p->n > 1)
+        for (const char* a : {"k_dft a", "k_dft b", "k_dft c"}) v.push_back({a, c, c});
+      v.push_back({"k_unfold", c, rin});
+    }
+    return v;
   }
   if (p->n == 1) return {{d == 0 ? "k_copy1" : "k_copy1", d == 0 ? rin : c, d == 0 ? c : rin}};
   if (p->dense) return {{std::string("k_split_gemm") + (p->prec == FCC_PREC_SPLIT_FP16 ? "<f16>" : "<bf16>"),
@@ -2317,6 +2333,76 @@ fcc_status enqueue_forward_plain(const fcc_plan_s* p, int nvol, VolPtrs in, VolP
                                  hipStream_t st);
 fcc_status enqueue_inverse_plain(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0, VolPtrs ws1,
                                  hipStream_t st);
+// ---- FCC_FOLD_FFT: fold, three DFT passes; DFT passes, unfold ---------------
+template <typename R, int N>
+void dft_launch(int ax, int sgn, const VolSet& vs, int nvol, const cx<R>* w8n, int post_r8, hipStream_t st) {
+  const dim3 g(unsigned(nvol * (N * N / dft_lines<R, N>()))), b(256);
+  if (sgn > 0) {
+    if (ax == 0) launch((k_dft<R, N, 0, 1>), g, b, 0, st, vs, nvol, w8n, post_r8);
+    else if (ax == 1) launch((k_dft<R, N, 1, 1>), g, b, 0, st, vs, nvol, w8n, post_r8);
+    else launch((k_dft<R, N, 2, 1>), g, b, 0, st, vs, nvol, w8n, post_r8);
+  } else {
+    if (ax == 0) launch((k_dft<R, N, 0, -1>), g, b, 0, st, vs, nvol, w8n, post_r8);
+    else if (ax == 1) launch((k_dft<R, N, 1, -1>), g, b, 0, st, vs, nvol, w8n, post_r8);
+    else launch((k_dft<R, N, 2, -1>), g, b, 0, st, vs, nvol, w8n, post_r8);
+  }
+}
+template <typename R>
+void dft_dispatch(int n, int ax, int sgn, const VolSet& vs, int nvol, const cx<R>* w8n, int post_r8, hipStream_t st) {
+  switch (n) {
+    case 2: dft_launch<R, 2>(ax, sgn, vs, nvol, w8n, post_r8, st); break;
+    case 4: dft_launch<R, 4>(ax, sgn, vs, nvol, w8n, post_r8, st); break;
+    case 8: dft_launch<R, 8>(ax, sgn, vs, nvol, w8n, post_r8, st); break;
+    case 16: dft_launch<R, 16>(ax, sgn, vs, nvol, w8n, post_r8, st); break;
+    case 32: dft_launch<R, 32>(ax, sgn, vs, nvol, w8n, post_r8, st); break;
+    case 64: dft_launch<R, 64>(ax, sgn, vs, nvol, w8n, post_r8, st); break;
+    case 128: dft_launch<R, 128>(ax, sgn, vs, nvol, w8n, post_r8, st); break;
+    case 256: dft_launch<R, 256>(ax, sgn, vs, nvol, w8n, post_r8, st); break;
+    case 512: dft_launch<R, 512>(ax, sgn, vs, nvol, w8n, post_r8, st); break;
+    default: break;
+  }
+}
+// Forward: k_fold (x -> out), then the DFT passes along c, b, a in place on
+// out.  Inverse: the DFT passes along a (in -> ws0), b, c (in place, each with
+// its axis phase), then k_unfold (ws0 -> out).
+template <typename R>
+fcc_status fold_run(const fcc_plan_s* p, int dir, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0, hipStream_t st) {
+  const int n = p->n, lg = p->D;
+  const cx<R>* w = static_cast<const cx<R>*>(p->fw8n);
+  const int nrep = p->fnrep;
+  const dim3 gp(unsigned(nvol * ((nrep + kFoldReps - 1) / kFoldReps))), b(256);
+  const bool real = (p->flags & FCC_REAL_INPUT) != 0;
+  const int* r8 = p->r8;
+  const int* reps = static_cast<const int*>(p->freps);
+  if (dir > 0) {
+    if (real)
+      launch((k_fold<R, R>), gp, b, 0, st, VolSet{in, out}, nvol, lg, r8[0], r8[1], r8[2], w, reps, nrep);
+    else
+      launch((k_fold<R, cx<R>>), gp, b, 0, st, VolSet{in, out}, nvol, lg, r8[0], r8[1], r8[2], w, reps, nrep);
+    for (int ax = 2; n > 1 && ax >= 0; --ax) dft_dispatch<R>(n, ax, 1, VolSet{out, out}, nvol, w, 0, st);
+    return launch_status("fold forward launch");
+  }
+  VolPtrs src = in;
+  if (n > 1) {
+    dft_dispatch<R>(n, 0, -1, VolSet{in, ws0}, nvol, w, r8[0], st);
+    dft_dispatch<R>(n, 1, -1, VolSet{ws0, ws0}, nvol, w, r8[1], st);
+    dft_dispatch<R>(n, 2, -1, VolSet{ws0, ws0}, nvol, w, r8[2], st);
+    src = ws0;
+  }
+  const cx<R>* kt = static_cast<const cx<R>*>(p->fkt);
+  if (real)
+    launch((k_unfold<R, R>), gp, b, 0, st, VolSet{src, out}, nvol, lg, r8[0], r8[1], r8[2], kt, p->fnpat, reps,
+           p->fpid, nrep);
+  else
+    launch((k_unfold<R, cx<R>>), gp, b, 0, st, VolSet{src, out}, nvol, lg, r8[0], r8[1], r8[2], kt, p->fnpat, reps,
+           p->fpid, nrep);
+  return launch_status("fold inverse launch");
+}
+fcc_status fold_enqueue(const fcc_plan_s* p, int dir, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0, hipStream_t st) {
+  return p->prec == FCC_PREC_FP64 ? fold_run<double>(p, dir, nvol, in, out, ws0, st)
+                                  : fold_run<float>(p, dir, nvol, in, out, ws0, st);
+}
+
 void hpack_launch(const fcc_plan_s* p, bool unpack, const void* src, void* dst, hipStream_t st) {
   const long long N = (long long)p->n * p->n * p->n;
   const dim3 g(unsigned((N + 255) / 256)), b(256);
@@ -2341,6 +2427,7 @@ void hpack_launch(const fcc_plan_s* p, bool unpack, const void* src, void* dst, 
 // serve one volume: the full spectrum goes to the plan's buffer, then packed).
 fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0, VolPtrs ws1,
                            hipStream_t st) {
+  if (p->fold) return fold_enqueue(p, 1, nvol, in, out, ws0, st);
   if (p->transposed) return enqueue_transposed(p, 1, nvol, in, out, ws0, ws1, st);
   if (p->hslot) {
     if (nvol != 1 || out.arr) return FCC_ERR_UNSUPPORTED;
@@ -2353,6 +2440,7 @@ fcc_status enqueue_forward(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs ou
 }
 fcc_status enqueue_inverse(const fcc_plan_s* p, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0, VolPtrs ws1,
                            hipStream_t st) {
+  if (p->fold) return fold_enqueue(p, -1, nvol, in, out, ws0, st);
   if (p->transposed) return enqueue_transposed(p, -1, nvol, in, out, ws0, ws1, st);
   if (p->hslot) {
     if (nvol != 1 || in.arr) return FCC_ERR_UNSUPPORTED;
@@ -2979,6 +3067,61 @@ std::map<std::array<int, 4>, fcc_tuning>& tuned() {
 
 extern "C" {
 
+}  // extern "C"
+namespace {
+// Tables of an FCC_FOLD_FFT plan: the phases exp(2 pi i m / (8n)), the unfold
+// rows (scaled by 1/n^3) and the per-point row index, all in the data
+// precision; one n^3 complex scratch buffer for the inverse.
+template <typename C>
+fcc_status fold_upload(fcc_plan_s* p, const fcc::FoldTables& t) {
+  const int n = p->n;
+  std::vector<C> w(size_t(8) * n), k(t.K.size());
+  for (int m = 0; m < 8 * n; ++m) {
+    // exact at the multiples of pi/4, else the FP64 sine and cosine of the reduced angle
+    const double a = 2.0 * M_PI * double(m) / (8.0 * n);
+    w[m] = {decltype(C{}.x)(std::cos(a)), decltype(C{}.x)(std::sin(a))};
+    if ((m * 8) % (8 * n) == 0) {
+      static const double h = std::sqrt(0.5);
+      const double cs[8][2] = {{1, 0}, {h, h}, {0, 1}, {-h, h}, {-1, 0}, {-h, -h}, {0, -1}, {h, -h}};
+      const int q = (m * 8) / (8 * n);
+      w[m] = {decltype(C{}.x)(cs[q][0]), decltype(C{}.x)(cs[q][1])};
+    }
+  }
+  const double inv = 1.0 / (double(n) * n * n);
+  for (size_t i = 0; i < t.K.size(); ++i) k[i] = {decltype(C{}.x)(t.K[i].real() * inv), decltype(C{}.x)(t.K[i].imag() * inv)};
+  hipError_t e = hipMalloc(&p->fw8n, w.size() * sizeof(C));
+  if (e == hipSuccess) e = hipMemcpy(p->fw8n, w.data(), w.size() * sizeof(C), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&p->fkt, k.size() * sizeof(C));
+  if (e == hipSuccess) e = hipMemcpy(p->fkt, k.data(), k.size() * sizeof(C), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->fpid), t.prid.size());
+  if (e == hipSuccess) e = hipMemcpy(p->fpid, t.prid.data(), t.prid.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&p->freps, t.reps.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemcpy(p->freps, t.reps.data(), t.reps.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  p->fnrep = int(t.reps.size());
+  if (e == hipSuccess) {
+    p->ws_bytes = size_t(n) * n * n * sizeof(C);
+    e = hipMalloc(&p->ws[0], p->ws_bytes);
+  }
+  return e == hipSuccess ? FCC_OK : hip_fail(e, "fold tables", __LINE__);
+}
+fcc_status fold_prepare(fcc_plan_s* p, const double r[3], hipStream_t) {
+  p->fold = true;
+  p->stages64 = p->prec == FCC_PREC_FP64;
+  for (int i = 0; i < 3; ++i) {
+    const double v = 8.0 * r[i];
+    if (std::fabs(v - std::nearbyint(v)) > 1e-12) return FCC_ERR_UNSUPPORTED;
+    p->r8[i] = int(std::nearbyint(v));
+  }
+  fcc::FoldTables t;
+  const fcc_status s = fcc::fold_tables(p->n, p->r8, &t, true);
+  if (s != FCC_OK) return s;
+  if (t.npat > kFoldMaxPat) return FCC_ERR_UNSUPPORTED;
+  p->fnpat = t.npat;
+  return p->prec == FCC_PREC_FP64 ? fold_upload<double2>(p, t) : fold_upload<float2>(p, t);
+}
+}  // namespace
+extern "C" {
+
 fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precision prec, unsigned flags,
                         void* hip_stream) {
   return fcc_dct_plan_tuned(plan, n, rst, prec, flags, nullptr, hip_stream);
@@ -2998,8 +3141,11 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
   if (prec < FCC_PREC_FP64 || prec > FCC_PREC_SPLIT_FP16) return FCC_ERR_INVALID_ARG;
   if ((flags & FCC_STAGES_FP32) && (flags & FCC_STAGES_FP64)) return FCC_ERR_INVALID_ARG;
   if (flags & ~(unsigned)(FCC_REAL_INPUT | FCC_STAGES_FP32 | FCC_STAGES_FP64 | FCC_LEVEL0_FP32 | FCC_TRANSPOSED |
-                          FCC_HERMITIAN_PACKED))
+                          FCC_HERMITIAN_PACKED | FCC_FOLD_FFT))
     return FCC_ERR_INVALID_ARG;
+  if ((flags & FCC_FOLD_FFT) && ((flags & ~(unsigned)(FCC_FOLD_FFT | FCC_REAL_INPUT)) ||
+                                 (prec != FCC_PREC_FP32 && prec != FCC_PREC_FP64) || n > 512))
+    return FCC_ERR_UNSUPPORTED;
   const bool split_prec = prec == FCC_PREC_SPLIT_BF16 || prec == FCC_PREC_SPLIT_FP16;
   if ((flags & FCC_TRANSPOSED) &&
       (split_prec || (flags & (FCC_LEVEL0_FP32 | FCC_HERMITIAN_PACKED)) || n > 256))
@@ -3064,6 +3210,15 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   fcc_status s = FCC_OK;
   (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
+  if (flags & FCC_FOLD_FFT) {
+    s = fold_prepare(p, r, st);
+    if (s != FCC_OK) {
+      fcc_dct_destroy(p);
+      return s;
+    }
+    *plan = p;
+    return FCC_OK;
+  }
   // Levels that run as orbit-block launches in both directions read no
   // per-row table; the others need one, and its packed entries hold node-local
   // coordinates in 8 bits (node size <= 256).
@@ -3280,6 +3435,10 @@ fcc_status fcc_dct_destroy(fcc_plan_t p) {
   if (p->hslot) (void)hipFree(p->hslot);
   if (p->hfull) (void)hipFree(p->hfull);
   if (p->hph) (void)hipFree(p->hph);
+  if (p->fw8n) (void)hipFree(p->fw8n);
+  if (p->fkt) (void)hipFree(p->fkt);
+  if (p->fpid) (void)hipFree(p->fpid);
+  if (p->freps) (void)hipFree(p->freps);
   for (void* w : p->ws)
     if (w) (void)hipFree(w);
   delete p;
@@ -3440,7 +3599,7 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
   fcc_plan_t p = nullptr;
   fcc_status s = fcc_dct_plan_tuned(&p, n, rst, prec, flags, nullptr, hip_stream);
   if (s != FCC_OK) return s;
-  if (!p->dense && p->D >= 2) {
+  if (!p->dense && !p->fold && p->D >= 2) {
     // synthetic operands: the forward input and a complex array for the
     // forward output / inverse input
     const long long N = (long long)n * n * n;

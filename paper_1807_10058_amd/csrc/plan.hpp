@@ -46,6 +46,14 @@ struct fcc_plan_s {
   void* onodes = nullptr;               // dense DCT_2 and inverse per node of the orbit-block levels
   long long onode_off[16] = {};         // per level offset into onodes, -1 if none       // per level from min(tail_Lt) on: plain-order tables, S = 1
   unsigned char kf[2][16][8] = {};      // balanced map: log2 lanes per row, per side, level and f
+  // FCC_FOLD_FFT (the fold+FFT variant): tables in the data precision
+  bool fold = false;
+  int r8[3] = {1, 0, 3};                // 8 rst
+  void* fw8n = nullptr;                 // exp(2 pi i m / (8n)), m < 8n
+  void* fkt = nullptr;                  // unfold rows, fnpat x 24, scaled by 1/n^3
+  unsigned char* fpid = nullptr;        // unfold row per image of each orbit representative (24 x fnrep)
+  void* freps = nullptr;                // orbit representatives (flat index), by 8^3 box
+  int fnpat = 0, fnrep = 0;
 };
 
 namespace fcc {
