@@ -27,7 +27,8 @@ precision) and the CPU oracle timed on a bounded sample.
 --pmc-pass runs only the workload's launch slots once, eagerly, in slot order
 (for rocprofv3 counter runs) and writes their list to gpurun_out/slots_<w>.json;
 --summarize DIR turns a counter run's CSV output in DIR into the traffic table
-of profiles/traffic_<w>.md.
+of profiles/traffic_<w>.md; with --fold both cover the fold+FFT variant's
+launches (c4, c5), which the c5 line reports beside the paper's factorisation.
 """
 import argparse
 import glob
@@ -43,9 +44,11 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
 MFMA_BF16_PEAK_TFS = 2500.0  # dense BF16 MFMA
 KERNEL_SOURCES = ("paper_1807_10058_amd/csrc/fcc_dct.hip", "paper_1807_10058_amd/csrc/kernels.hpp",
                   "paper_1807_10058_amd/csrc/orbit_level.hpp", "paper_1807_10058_amd/csrc/dense.hip",
-                  "paper_1807_10058_amd/csrc/orbits.inc")
+                  "paper_1807_10058_amd/csrc/orbits.inc", "paper_1807_10058_amd/csrc/fold_fft.hpp")
 TRAFFIC_PROFILE = {"c2": "traffic_c2_n64_forward.md", "c4": "traffic_c4_n256_forward_inverse.md",
-                   "c5": "traffic_c5_ragged512_forward_inverse.md"}
+                   "c5": "traffic_c5_ragged512_forward_inverse.md",
+                   "c4_fold": "traffic_fold_c4_n256_forward_inverse.md",
+                   "c5_fold": "traffic_fold_c5_ragged512_forward_inverse.md"}
 
 
 def parse():
@@ -64,6 +67,8 @@ def parse():
                     help="search the schedule before planning (setup, untimed) instead of the built-in one")
     ap.add_argument("--pmc-pass", action="store_true", help="one eager pass of the launch slots only")
     ap.add_argument("--summarize", metavar="DIR", help="write the traffic table of a counter run in DIR")
+    ap.add_argument("--fold", action="store_true",
+                    help="with --pmc-pass / --summarize: the launches of the fold+FFT variant (c4, c5)")
     return ap.parse_args()
 
 
@@ -182,14 +187,15 @@ def single_volume(args, name):
         fcc.fcc_dct_autotune(n, prec=prec, flags=fcc.FCC_REAL_INPUT, reps=5)
     tune_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    plan = fcc.fcc_dct_plan(n, prec=prec, flags=fcc.FCC_REAL_INPUT)
+    fold = args.fold and args.pmc_pass and name == "c4"
+    plan = fcc.fcc_dct_plan(n, prec=prec, flags=fcc.FCC_REAL_INPUT | (fcc.FCC_FOLD_FFT if fold else 0))
     plan_s = time.perf_counter() - t0
     x = torch.from_numpy(np.ascontiguousarray(x_np)).to(dev, rdt)
     X = torch.empty(n ** 3, dtype=cdt, device=dev)
     y = torch.empty(n ** 3, dtype=rdt, device=dev)
     pairs = [(1, x, X)] + ([(-1, X, y)] if direction == 0 else [])
     if args.pmc_pass:
-        return pmc_pass(name, lambda: single_slots(plan, pairs, 1))
+        return pmc_pass(name + ("_fold" if fold else ""), lambda: single_slots(plan, pairs, 1))
 
     def step():
         fcc.fcc_dct_forward(plan, x, X)
@@ -239,8 +245,10 @@ def c4_beside(args):
     import numpy as np
     import torch
 
+    import oracle
     import paper_1807_10058_amd as fcc
     import workloads
+    from tests.gpu_util import sample_rows
     n = 256
     dev = torch.device("cuda:0")
     x_np = workloads.upsampled_field(n, 3)
@@ -261,10 +269,35 @@ def c4_beside(args):
         dirs[s["direction"]] = round(dirs.get(s["direction"], 0.0) + s["ms"], 5)
     step()
     torch.cuda.synchronize()
-    return {"workload": "c4: n=256 forward+inverse, trilinear-upsampled field, FP32 data, FP64 stages",
-            "ms_per_step": ms, "points_per_s": n ** 3 / (ms * 1e-3), "direction_kernel_ms": dirs,
-            "roofline": roof, "roundtrip_max_rel_fp64_gpu": fcc.fcc_dct_roundtrip_residual(plan, x, y),
-            "step_frac_of_hbm_floor": (n ** 3 * 28) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    out = {"workload": "c4: n=256 forward+inverse, trilinear-upsampled field, FP32 data, FP64 stages",
+           "ms_per_step": ms, "points_per_s": n ** 3 / (ms * 1e-3), "direction_kernel_ms": dirs,
+           "roofline": roof, "roundtrip_max_rel_fp64_gpu": fcc.fcc_dct_roundtrip_residual(plan, x, y),
+           "step_frac_of_hbm_floor": (n ** 3 * 28) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    # the fold+FFT variant on the same input (FP32 arithmetic throughout)
+    fplan = fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT | fcc.FCC_FOLD_FFT)
+
+    def fstep():
+        fcc.fcc_dct_forward(fplan, x, X)
+        fcc.fcc_dct_inverse(fplan, X, y)
+
+    fms, _ = time_steps(fstep, max(5, args.steps // 2), 2)
+    fslots = single_slots(fplan, [(1, x, X), (-1, X, y)], 10)
+    fdirs = {}
+    for s in fslots:
+        fdirs[s["direction"]] = round(fdirs.get(s["direction"], 0.0) + s["ms"], 5)
+    fstep()
+    torch.cuda.synchronize()
+    rows = sample_rows(n, 16, 3)
+    ref = oracle.forward_rows(np.asarray(x_np, dtype=np.float64), n, rows)
+    got = X.cpu().numpy().astype(np.complex128)[rows]
+    out["fold_fft_variant"] = {
+        "what": "fold+FFT formulation (from the explicit matrix; not the paper's factorisation), FP32 arithmetic",
+        "ms_per_step": fms, "points_per_s": n ** 3 / (fms * 1e-3), "direction_kernel_ms": fdirs,
+        "roofline": roofline("c4_fold", fslots), "forward_max_rel_sampled": float(np.abs(got - ref).max()
+                                                                               / np.abs(ref).max()),
+        "roundtrip_max_rel_fp64_gpu": fcc.fcc_dct_roundtrip_residual(fplan, x, y),
+        "step_frac_of_hbm_floor": (n ** 3 * 28) / (fms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
 
 
 def batched(args, name):
@@ -316,17 +349,21 @@ def batched(args, name):
             return plan_for(n, fcc.FCC_PREC_SPLIT_BF16)
         if variant == "mixed":
             return plan_for(n, fcc.FCC_PREC_FP32, fcc.FCC_REAL_INPUT | fcc.FCC_LEVEL0_FP32)
+        if variant == "fold":
+            return plan_for(n, fcc.FCC_PREC_FP32, fcc.FCC_REAL_INPUT | fcc.FCC_FOLD_FFT)
         return plan_for(n, fcc.FCC_PREC_FP32)
 
     main_variant = "split" if name == "c3" else "mixed"
     if args.pmc_pass:
-        plans = [plan_for_variant(n, main_variant) for n in ns]
-        return pmc_pass(name, lambda: fcc.fcc_dct_batched_time_launches(plans, xs, outs, direction, reps=1))
+        fold = args.fold and name == "c5"
+        plans = [plan_for_variant(n, "fold" if fold else main_variant) for n in ns]
+        return pmc_pass(name + ("_fold" if fold else ""),
+                        lambda: fcc.fcc_dct_batched_time_launches(plans, xs, outs, direction, reps=1))
 
     originals = [x.clone() for x in xs] if direction == 0 else None
     res = {}
     slots_main = None
-    variants = ("split", "fp32") if name == "c3" else ("mixed", "split", "fp32")
+    variants = ("split", "fp32") if name == "c3" else ("mixed", "split", "fp32", "fold")
     for variant in variants:
         if direction == 0:
             for x, o in zip(xs, originals):
@@ -340,6 +377,8 @@ def batched(args, name):
         ms, wall = time_steps(step, args.steps, args.warmup)
         if variant == main_variant:
             slots_main = fcc.fcc_dct_batched_time_launches(plans, xs, outs, direction, reps=3)
+        if variant == "fold":
+            slots_fold = fcc.fcc_dct_batched_time_launches(plans, xs, outs, direction, reps=3)
         # accuracy: forward outputs vs oracle (sampled), round trip vs input
         if direction == 0:
             for x, o in zip(xs, originals):
@@ -362,6 +401,8 @@ def batched(args, name):
             acc["roundtrip_max_rel"] = worst_rt
         res[variant] = {"ms_per_step": ms, "points_per_s": points / (ms * 1e-3), "accuracy": acc,
                         "graph_build_s": round(build_s, 3), "wall_seconds_timed": round(wall, 4)}
+        if variant == "fold":
+            res[variant]["roofline"] = roofline(name + "_fold", slots_fold)
         fcc.fcc_dct_batched_release()
     main = res[main_variant]
     if name == "c3":
@@ -380,7 +421,9 @@ def batched(args, name):
            "sizes": {str(k): ns.count(k) for k in sorted(set(ns))}, "autotune_seconds": round(tune_s, 3),
            "variants": {"mixed": "split-BF16 MFMA for n = 8; FP32 top level, FP64 stages below for n >= 16",
                         "split": "split-BF16 MFMA for n = 8; FP64 stages for n >= 16",
-                        "fp32": "FP32 data, FP64 stages for every n (plain fast path)"}}
+                        "fp32": "FP32 data, FP64 stages for every n (plain fast path)",
+                        "fold": "fold+FFT formulation from the explicit matrix (a variant, not the paper's "
+                                "factorisation), FP32 arithmetic throughout"}}
     slot_ms = {}
     for s in slots_main:
         slot_ms[s["name"]] = round(slot_ms.get(s["name"], 0.0) + s["ms"], 5)
@@ -474,7 +517,7 @@ def main():
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.summarize:
-        summarize(args.summarize, args.workload)
+        summarize(args.summarize, args.workload + ("_fold" if args.fold else ""))
         return
     if args.workload in ("c1", "c2", "c4"):
         r = single_volume(args, args.workload)

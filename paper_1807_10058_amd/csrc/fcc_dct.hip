@@ -2370,15 +2370,25 @@ fcc_status fold_run(const fcc_plan_s* p, int dir, int nvol, VolPtrs in, VolPtrs 
   const int n = p->n, lg = p->D;
   const cx<R>* w = static_cast<const cx<R>*>(p->fw8n);
   const int nrep = p->fnrep;
-  const dim3 gp(unsigned(nvol * ((nrep + kFoldReps - 1) / kFoldReps))), b(256);
+  // blocks of 64 lanes where 256 would leave CUs idle
+  const int lanes = (long long)nrep * nvol >= 1024LL * kFoldLanes ? kFoldLanes : 64;
+  const long long nblk = (long long)nvol * ((nrep + lanes - 1) / lanes);
+  const dim3 gp(unsigned(((nblk + 7) >> 3) << 3)), b(lanes);
   const bool real = (p->flags & FCC_REAL_INPUT) != 0;
   const int* r8 = p->r8;
   const int* reps = static_cast<const int*>(p->freps);
+  // the default skew's phases at compile time (only r8 mod 8 matters)
+  const bool def = (r8[0] & 7) == 1 && (r8[1] & 7) == 0 && (r8[2] & 7) == 3;
+  auto fold = [&](auto tin, auto dflt) {
+    using TI = decltype(tin);
+    launch((k_fold<R, TI, decltype(dflt)::value>), gp, b, 0, st, VolSet{in, out}, nvol, lg, r8[0], r8[1], r8[2], w,
+           reps, nrep);
+  };
   if (dir > 0) {
     if (real)
-      launch((k_fold<R, R>), gp, b, 0, st, VolSet{in, out}, nvol, lg, r8[0], r8[1], r8[2], w, reps, nrep);
+      def ? fold(R{}, std::true_type{}) : fold(R{}, std::false_type{});
     else
-      launch((k_fold<R, cx<R>>), gp, b, 0, st, VolSet{in, out}, nvol, lg, r8[0], r8[1], r8[2], w, reps, nrep);
+      def ? fold(cx<R>{}, std::true_type{}) : fold(cx<R>{}, std::false_type{});
     for (int ax = 2; n > 1 && ax >= 0; --ax) dft_dispatch<R>(n, ax, 1, VolSet{out, out}, nvol, w, 0, st);
     return launch_status("fold forward launch");
   }
@@ -2390,12 +2400,15 @@ fcc_status fold_run(const fcc_plan_s* p, int dir, int nvol, VolPtrs in, VolPtrs 
     src = ws0;
   }
   const cx<R>* kt = static_cast<const cx<R>*>(p->fkt);
+  auto unfold = [&](auto tout, auto dflt) {
+    using TO = decltype(tout);
+    launch((k_unfold<R, TO, decltype(dflt)::value>), gp, b, 0, st, VolSet{src, out}, nvol, lg, r8[0], r8[1], r8[2],
+           kt, p->fnpat, reps, p->fpid, nrep);
+  };
   if (real)
-    launch((k_unfold<R, R>), gp, b, 0, st, VolSet{src, out}, nvol, lg, r8[0], r8[1], r8[2], kt, p->fnpat, reps,
-           p->fpid, nrep);
+    def ? unfold(R{}, std::true_type{}) : unfold(R{}, std::false_type{});
   else
-    launch((k_unfold<R, cx<R>>), gp, b, 0, st, VolSet{src, out}, nvol, lg, r8[0], r8[1], r8[2], kt, p->fnpat, reps,
-           p->fpid, nrep);
+    def ? unfold(cx<R>{}, std::true_type{}) : unfold(cx<R>{}, std::false_type{});
   return launch_status("fold inverse launch");
 }
 fcc_status fold_enqueue(const fcc_plan_s* p, int dir, int nvol, VolPtrs in, VolPtrs out, VolPtrs ws0, hipStream_t st) {

@@ -228,31 +228,33 @@ __global__ __launch_bounds__(256) void k_dft(VolSet vs, int nvol, const cx<R>* _
   });
 }
 
-// Orbit blocks.  A block takes kFoldReps orbits of W on the torus (by their
-// representatives, ordered by 8^3 box so that a block's orbits are close)
-// and all 24 images h r of each: it loads the input at every image once into
-// LDS, forms each output from the 24 members of its orbit there, and stores
-// it.  Lane (h, i) owns image h of orbit i; a wave holds one h, so the LDS
-// slot of a source (an element of W fixed by g and h) is the same for the
-// whole wave.  Images that coincide (orbits with a stabiliser) are loaded and
-// stored more than once, with equal values.
-constexpr int kFoldReps = 64;
-constexpr int kFoldItems = 24 * kFoldReps / 256;
+// Orbit lanes.  Each lane owns one orbit of W on the torus, by its
+// representative rep (ordered by box, so a wave's orbits are close), and all
+// 24 images u rep mod n = u rep - n W_u (W_u = floor(u rep / n)): it loads the
+// input at every image once, forms the 24 outputs from them in registers and
+// stores them.  With the image index in the unrolled loops a compile-time
+// constant, the phase of each (output h, source u) pair costs a few integer
+// operations:
+//   forward  Fh[h rep] = (1/24) e(h rep) sum_u w8^{-(Z_u . h^T r8 - W_h . r8)} x[u rep],
+//            Z_u = u^{-1} W_u,
+//   inverse  x[h rep] = sum_u K[pid][u] w8^{-(W_{uh} . r8 - W_h . u^T r8)} Fh'[(u h) rep],
+// (e(mu) = exp(2 pi i mu.rst / n); w8^{-j} from an 8-entry table in LDS).
+// Images that coincide (orbits with a stabiliser) are stored once per image
+// by the same lane, last one kept.
+constexpr int kFoldLanes = 256;  // lanes per block (64 for small launches)
 
 struct FoldMul {
   unsigned char m[24][24];
 };
-// m[a][b] = index of W[a]^{inv ? -1 : 1} W[b]
-constexpr FoldMul fold_mul(bool inv) {
+// m[a][b] = index of W[a] W[b]
+constexpr FoldMul fold_mul() {
   FoldMul t{};
   for (int a = 0; a < 24; ++a)
     for (int b = 0; b < 24; ++b) {
-      const int* A = kFoldW[inv ? kFoldWinv[a] : a].g;
-      const int* B = kFoldW[b].g;
       int P[9] = {};
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
-          for (int k = 0; k < 3; ++k) P[3 * i + j] += A[3 * i + k] * B[3 * k + j];
+          for (int k = 0; k < 3; ++k) P[3 * i + j] += kFoldW[a].g[3 * i + k] * kFoldW[b].g[3 * k + j];
       for (int c = 0; c < 24; ++c) {
         bool eq = true;
         for (int q = 0; q < 9; ++q) eq = eq && kFoldW[c].g[q] == P[q];
@@ -261,117 +263,178 @@ constexpr FoldMul fold_mul(bool inv) {
     }
   return t;
 }
-constexpr FoldMul kFoldMulInv = fold_mul(true);   // g^{-1} h
-constexpr FoldMul kFoldMul = fold_mul(false);     // u h
-#define FCC_FOLD_GC(u, a0, a1, a2, a3, a4, a5, a6, a7, a8, ui) {a0, a1, a2, a3, a4, a5, a6, a7, a8},
-__constant__ int kFoldWc[24][9] = {FCC_GROUP(FCC_FOLD_GC)};
-#undef FCC_FOLD_GC
+constexpr FoldMul kFoldMul = fold_mul();
 
-// Image h of representative rep (flat index), reduced mod n.
-__device__ __forceinline__ void fold_image(int h, int rep, int lg, int mu[3]) {
-  const int n = 1 << lg;
-  const int k[3] = {rep >> (2 * lg), (rep >> lg) & (n - 1), rep & (n - 1)};
+// Logical block: launches have a multiple of 8 blocks, blocks i, i+8, ...
+// run on one XCD and take one contiguous range of orbits, so that the
+// neighbouring orbits that share cache lines meet in one L2.
+__device__ __forceinline__ long long fold_block(long long total) {
+  const long long per = (total + 7) >> 3;
+  const long long b = (long long)(blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+  return b < total ? b : -1;
+}
+
+__device__ __forceinline__ void fold_act(int u, const int k[3], int v[3]) {
 #pragma unroll
   for (int i = 0; i < 3; ++i)
-    mu[i] = (kFoldWc[h][3 * i] * k[0] + kFoldWc[h][3 * i + 1] * k[1] + kFoldWc[h][3 * i + 2] * k[2]) & (n - 1);
+    v[i] = kFoldW[u].g[3 * i] * k[0] + kFoldW[u].g[3 * i + 1] * k[1] + kFoldW[u].g[3 * i + 2] * k[2];
+}
+// z . (g^T r8) with g = W[u]: the default skew r8 = (1, 0, 3) folds to constants
+template <bool DEF>
+__device__ __forceinline__ int fold_qdot(int u, const int z[3], const int r8[3]) {
+  const int* g = kFoldW[u].g;
+  if constexpr (DEF) {
+    return (g[0] + 3 * g[6]) * z[0] + (g[1] + 3 * g[7]) * z[1] + (g[2] + 3 * g[8]) * z[2];
+  } else {
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) s += (g[i] * r8[0] + g[3 + i] * r8[1] + g[6 + i] * r8[2]) * z[i];
+    return s;
+  }
+}
+template <bool DEF>
+__device__ __forceinline__ int fold_rdot(const int w[3], const int r8[3]) {
+  if constexpr (DEF) return w[0] + 3 * w[2];
+  return w[0] * r8[0] + w[1] * r8[1] + w[2] * r8[2];
+}
+// A copy of k the compiler cannot see through, so that the images a later
+// loop needs are recomputed there instead of being held from an earlier one.
+__device__ __forceinline__ void fold_launder(const int k[3], int o[3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    int t = k[i];
+    asm volatile("" : "+v"(t));
+    o[i] = t;
+  }
+}
+template <typename R>
+__device__ __forceinline__ void fold_rot_table(cx<R>* t) {
+  if (threadIdx.x < 8) {
+    constexpr R h = R(0.70710678118654752440);
+    const R c[8] = {1, h, 0, -h, -1, -h, 0, h};
+    t[threadIdx.x] = {c[threadIdx.x], -c[(threadIdx.x + 6) & 7]};  // exp(-i pi j / 4)
+  }
 }
 
 // Forward fold of nvol volumes (out is complex R).
-template <typename R, typename TI>
-__global__ __launch_bounds__(256) void k_fold(VolSet vs, int nvol, int lg, int r80, int r81, int r82,
-                                              const cx<R>* __restrict__ w8n, const int* __restrict__ reps,
-                                              int nrep) {
-  __shared__ cx<R> xs[24][kFoldReps];
-  __shared__ unsigned char tab[24 * 24];
-  const int bpv = (nrep + kFoldReps - 1) / kFoldReps;
-  const int vol = blockIdx.x / bpv, r0 = (blockIdx.x - vol * bpv) * kFoldReps;
-  if (vol >= nvol) return;
-  const int n = 1 << lg;
+template <typename R, typename TI, bool DEF>
+__global__ __launch_bounds__(kFoldLanes) void k_fold(VolSet vs, int nvol, int lg, int r80, int r81, int r82,
+                                                     const cx<R>* __restrict__ w8n, const int* __restrict__ reps,
+                                                     int nrep) {
+  __shared__ cx<R> rot[8];
+  fold_rot_table(rot);
+  __syncthreads();
+  const int lanes = blockDim.x, bpv = (nrep + lanes - 1) / lanes;
+  const long long blk = fold_block((long long)bpv * nvol);
+  if (blk < 0) return;
+  const int vol = int(blk / bpv);
+  const int r = int(blk - (long long)vol * bpv) * lanes + threadIdx.x;
+  const int n = 1 << lg, mask = n - 1;
   const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, vol));
   cx<R>* __restrict__ out = static_cast<cx<R>*>(vol_ptr(vs.out, vol));
-  for (int q = threadIdx.x; q < 24 * 24; q += 256) tab[q] = kFoldMulInv.m[q / 24][q % 24];
-  int mu[kFoldItems][3];
-#pragma unroll
-  for (int it = 0; it < kFoldItems; ++it) {
-    const int item = threadIdx.x + it * 256;
-    const int h = __builtin_amdgcn_readfirstlane(item / kFoldReps), i = item % kFoldReps;
-    const int r = min(r0 + i, nrep - 1);
-    fold_image(h, reps[r], lg, mu[it]);
-    xs[h][i] = IO<TI, R>::ld(in, ((long long)mu[it][0] * n + mu[it][1]) * n + mu[it][2]);
-  }
-  __syncthreads();
   const int r8[3] = {r80, r81, r82};
-#pragma unroll 1
-  for (int it = 0; it < kFoldItems; ++it) {
-    const int item = threadIdx.x + it * 256;
-    const int h = __builtin_amdgcn_readfirstlane(item / kFoldReps), i = item % kFoldReps;
-    cx<R> acc{R(0), R(0)};
-    static_for<0, 24>([&](auto G) {
-      constexpr int g = decltype(G)::value;
-      constexpr FoldW gi = kFoldW[kFoldWinv[g]];
-      constexpr FoldW gg = kFoldW[g];
-      int w[3];
+  const int rep = reps[min(r, nrep - 1)];
+  const int k[3] = {rep >> (2 * lg), (rep >> lg) & mask, rep & mask};
+  // real input stays real: each term is then two multiply-adds
+  constexpr bool kReal = std::is_same<TI, float>::value || std::is_same<TI, double>::value;
+  using V = typename std::conditional<kReal, R, cx<R>>::type;
+  V xv[24];
+  int A8[3] = {0, 0, 0};  // W_u . r8 mod 8, eight 4-bit fields per word
 #pragma unroll
-      for (int d = 0; d < 3; ++d)
-        w[d] = (gi.g[3 * d] * mu[it][0] + gi.g[3 * d + 1] * mu[it][1] + gi.g[3 * d + 2] * mu[it][2]) >> lg;
-      int m = 0;  // (g w) . r8
+  for (int u = 0; u < 24; ++u) {
+    int v[3];
+    fold_act(u, k, v);
+    const cx<R> t = IO<TI, R>::ld(in, ((long long)(v[0] & mask) * n + (v[1] & mask)) * n + (v[2] & mask));
+    if constexpr (kReal)
+      xv[u] = t.x;
+    else
+      xv[u] = t;
+    const int w[3] = {v[0] >> lg, v[1] >> lg, v[2] >> lg};
+    A8[u >> 3] |= (fold_rdot<DEF>(w, r8) & 7) << (4 * (u & 7));
+  }
+  cx<R> acc[24];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) m += (gg.g[3 * d] * w[0] + gg.g[3 * d + 1] * w[1] + gg.g[3 * d + 2] * w[2]) * r8[d];
-      acc = acc + rot8m(xs[tab[g * 24 + h]][i], m & 7);
-    });
-    if (r0 + i < nrep) {
-      const int e = (mu[it][0] * r8[0] + mu[it][1] * r8[1] + mu[it][2] * r8[2]) & (8 * n - 1);
-      out[((long long)mu[it][0] * n + mu[it][1]) * n + mu[it][2]] = (R(1) / R(24)) * (w8n[e] * acc);
+  for (int h = 0; h < 24; ++h) acc[h] = {R(0), R(0)};
+  int k1[3], k2[3];
+  fold_launder(k, k1);
+#pragma unroll
+  for (int u = 0; u < 24; ++u) {
+    int v[3];
+    fold_act(u, k1, v);
+    const int w[3] = {v[0] >> lg, v[1] >> lg, v[2] >> lg};
+    int z[3];  // u^{-1} W_u
+    fold_act(kFoldWinv[u], w, z);
+#pragma unroll
+    for (int h = 0; h < 24; ++h) {
+      const cx<R> c = rot[(fold_qdot<DEF>(h, z, r8) - (A8[h >> 3] >> (4 * (h & 7)))) & 7];
+      if constexpr (kReal)
+        acc[h] = {acc[h].x + c.x * xv[u], acc[h].y + c.y * xv[u]};
+      else
+        acc[h] = acc[h] + c * xv[u];
     }
+  }
+  if (r >= nrep) return;
+  fold_launder(k, k2);
+#pragma unroll
+  for (int h = 0; h < 24; ++h) {
+    int v[3];
+    fold_act(h, k2, v);
+    const int mu[3] = {v[0] & mask, v[1] & mask, v[2] & mask};
+    const int e = (mu[0] * r8[0] + mu[1] * r8[1] + mu[2] * r8[2]) & (8 * n - 1);
+    out[((long long)mu[0] * n + mu[1]) * n + mu[2]] = (R(1) / R(24)) * (w8n[e] * acc[h]);
   }
 }
 
 // Inverse unfold: x[k] from Fh' (complex R) with the unfold rows K.
-template <typename R, typename TO>
-__global__ __launch_bounds__(256) void k_unfold(VolSet vs, int nvol, int lg, int r80, int r81, int r82,
-                                                const cx<R>* __restrict__ kt, int npat,
-                                                const int* __restrict__ reps, const unsigned char* __restrict__ prid,
-                                                int nrep) {
-  __shared__ cx<R> fs[24][kFoldReps];
+template <typename R, typename TO, bool DEF>
+__global__ __launch_bounds__(kFoldLanes) void k_unfold(VolSet vs, int nvol, int lg, int r80, int r81, int r82,
+                                                       const cx<R>* __restrict__ kt, int npat,
+                                                       const int* __restrict__ reps,
+                                                       const unsigned char* __restrict__ prid, int nrep) {
   __shared__ cx<R> ks[kFoldMaxPat * 24];
-  __shared__ unsigned char tab[24 * 24];
-  const int bpv = (nrep + kFoldReps - 1) / kFoldReps;
-  const int vol = blockIdx.x / bpv, r0 = (blockIdx.x - vol * bpv) * kFoldReps;
-  if (vol >= nvol) return;
-  const int n = 1 << lg;
+  __shared__ cx<R> rot[8];
+  for (int q = threadIdx.x; q < npat * 24; q += blockDim.x) ks[q] = kt[q];
+  fold_rot_table(rot);
+  __syncthreads();
+  const int lanes = blockDim.x, bpv = (nrep + lanes - 1) / lanes;
+  const long long blk = fold_block((long long)bpv * nvol);
+  if (blk < 0) return;
+  const int vol = int(blk / bpv);
+  const int r = int(blk - (long long)vol * bpv) * lanes + threadIdx.x;
+  const int rc = min(r, nrep - 1);
+  const int n = 1 << lg, mask = n - 1;
   const cx<R>* __restrict__ in = static_cast<const cx<R>*>(vol_ptr(vs.in, vol));
   TO* __restrict__ out = static_cast<TO*>(vol_ptr(vs.out, vol));
-  for (int q = threadIdx.x; q < npat * 24; q += 256) ks[q] = kt[q];
-  for (int q = threadIdx.x; q < 24 * 24; q += 256) tab[q] = kFoldMul.m[q / 24][q % 24];
-  int kk[kFoldItems][3];
-  int pr[kFoldItems];
-#pragma unroll
-  for (int it = 0; it < kFoldItems; ++it) {
-    const int item = threadIdx.x + it * 256;
-    const int h = __builtin_amdgcn_readfirstlane(item / kFoldReps), i = item % kFoldReps;
-    const int r = min(r0 + i, nrep - 1);
-    fold_image(h, reps[r], lg, kk[it]);
-    pr[it] = prid[(long long)h * nrep + r];
-    fs[h][i] = in[((long long)kk[it][0] * n + kk[it][1]) * n + kk[it][2]];
-  }
-  __syncthreads();
   const int r8[3] = {r80, r81, r82};
-#pragma unroll 1
-  for (int it = 0; it < kFoldItems; ++it) {
-    const int item = threadIdx.x + it * 256;
-    const int h = __builtin_amdgcn_readfirstlane(item / kFoldReps), i = item % kFoldReps;
-    const cx<R>* krow = ks + 24 * pr[it];
-    cx<R> acc{R(0), R(0)};
-    static_for<0, 24>([&](auto U) {
-      constexpr int u = decltype(U)::value;
-      constexpr FoldW g = kFoldW[u];
-      int m = 0;  // floor(u k / n) . r8
+  const int rep = reps[rc];
+  const int k[3] = {rep >> (2 * lg), (rep >> lg) & mask, rep & mask};
+  cx<R> y[24];
+  int B8[3] = {0, 0, 0}, pr4[6] = {0, 0, 0, 0, 0, 0};  // W_v . r8 mod 8 (4-bit fields); row indices (bytes)
 #pragma unroll
-      for (int d = 0; d < 3; ++d)
-        m += ((g.g[3 * d] * kk[it][0] + g.g[3 * d + 1] * kk[it][1] + g.g[3 * d + 2] * kk[it][2]) >> lg) * r8[d];
-      acc = acc + krow[u] * rot8m(fs[tab[u * 24 + h]][i], m & 7);
-    });
-    if (r0 + i < nrep) IO<TO, R>::st(out, ((long long)kk[it][0] * n + kk[it][1]) * n + kk[it][2], acc);
+  for (int v = 0; v < 24; ++v) {
+    int t[3];
+    fold_act(v, k, t);
+    y[v] = in[((long long)(t[0] & mask) * n + (t[1] & mask)) * n + (t[2] & mask)];
+    const int w[3] = {t[0] >> lg, t[1] >> lg, t[2] >> lg};
+    B8[v >> 3] |= (fold_rdot<DEF>(w, r8) & 7) << (4 * (v & 7));
+    pr4[v >> 2] |= int(prid[(long long)v * nrep + rc]) << (8 * (v & 3));
+  }
+  int k1[3];
+  fold_launder(k, k1);
+#pragma unroll
+  for (int h = 0; h < 24; ++h) {
+    int t[3];
+    fold_act(h, k1, t);
+    const int w[3] = {t[0] >> lg, t[1] >> lg, t[2] >> lg};
+    const cx<R>* krow = ks + 24 * ((pr4[h >> 2] >> (8 * (h & 3))) & 255);
+    cx<R> acc{R(0), R(0)};
+#pragma unroll
+    for (int u = 0; u < 24; ++u) {
+      const int v = kFoldMul.m[u][h];
+      const cx<R> c = krow[u] * rot[(((B8[v >> 3] >> (4 * (v & 7))) & 7) - fold_qdot<DEF>(u, w, r8)) & 7];
+      acc = acc + c * y[v];
+    }
+    if (r < nrep) IO<TO, R>::st(out, ((long long)(t[0] & mask) * n + (t[1] & mask)) * n + (t[2] & mask), acc);
   }
 }
 

@@ -293,14 +293,15 @@ fcc_status fold_tables(int n, const int r8[3], FoldTables* out, bool orbits) {
   out->K = std::move(b.K);
   out->npat = int(b.rows.size());
   if (orbits) {
-    const int bs = std::min(n, 8), nb = n / bs;
+    const int sa = std::min(n, kFoldBox[0]), sb = std::min(n, kFoldBox[1]), sc = std::min(n, kFoldBox[2]);
+    const long long na = n / sa, nb = n / sb, nc = n / sc;
     out->reps.clear();
-    for (long long B = 0; B < (long long)nb * nb * nb; ++B) {
-      const int ba = int(B / ((long long)nb * nb)), bb = int((B / nb) % nb), bc = int(B % nb);
-      for (int i = 0; i < bs; ++i)
-        for (int j = 0; j < bs; ++j)
-          for (int l = 0; l < bs; ++l) {
-            const long long f = ((long long)(ba * bs + i) * n + (bb * bs + j)) * n + (bc * bs + l);
+    for (long long B = 0; B < na * nb * nc; ++B) {
+      const long long ba = B / (nb * nc), bb = (B / nc) % nb, bc = B % nc;
+      for (int i = 0; i < sa; ++i)
+        for (int j = 0; j < sb; ++j)
+          for (int l = 0; l < sc; ++l) {
+            const long long f = ((ba * sa + i) * n + (bb * sb + j)) * n + (bc * sc + l);
             if (isrep[size_t(f)]) out->reps.push_back(int32_t(f));
           }
     }

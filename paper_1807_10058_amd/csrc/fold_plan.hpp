@@ -34,9 +34,10 @@ namespace fcc {
 // row K[pid * 24 + u] of eq. (2), u in the order of the FCC_GROUP table.
 //
 // For the orbit-block kernels: one representative per orbit of W on the
-// torus (its smallest flat index), ordered by the 8 x 8 x 8 box that holds it
+// torus (its smallest flat index), ordered by the kFoldBox box that holds it
 // (boxes and points within a box in lexicographic order), and per image h of
 // representative r the row index prid[h * nrep + r] = pid[h r mod n].
+constexpr int kFoldBox[3] = {4, 4, 8};
 struct FoldTables {
   std::vector<uint8_t> pid;
   std::vector<std::complex<double>> K;
