@@ -114,149 +114,177 @@ struct Vec8<_Float16> {
   }
 };
 
-constexpr int BM = 64, BN = 128, BK = 64, LDSK = BK + 8;
+constexpr int BM = 128, BN = 128, BK = 32, LDSK = BK + 8;
+constexpr int KP_ALIGN = 2 * BK;  // padded K of the stored operands: an even number of K tiles
 
-// One K tile of the split GEMM's operands in registers: 16 floats of an A row
-// (from k0 + akc) and 32 entries of a W row, hi and lo (from k0).  Named
-// members, no arrays, so that nothing is addressed through scratch.
-struct GemmTile {
-  float4 a0, a1, a2, a3;
-  uint4 h0, h1, h2, h3, l0, l1, l2, l3;
-};
-template <bool kVec>
-__device__ __forceinline__ float4 gemm_a4(const float* arp, int K, int kk) {
-  if constexpr (kVec) {
-    // K % 4 == 0: a float4 is wholly in range or wholly out
-    return (arp && kk < K) ? *reinterpret_cast<const float4*>(arp + kk) : make_float4(0.f, 0.f, 0.f, 0.f);
-  } else {
-    float4 v;
-    v.x = (arp && kk < K) ? arp[kk] : 0.f;
-    v.y = (arp && kk + 1 < K) ? arp[kk + 1] : 0.f;
-    v.z = (arp && kk + 2 < K) ? arp[kk + 2] : 0.f;
-    v.w = (arp && kk + 3 < K) ? arp[kk + 3] : 0.f;
-    return v;
-  }
-}
-template <bool kVec, typename T16>
-__device__ __forceinline__ void gemm_load(const float* arp, int K, int k0, int akc, const T16* bhp, const T16* blp,
-                                          GemmTile& t) {
-  const int kk = k0 + akc;
-  t.a0 = gemm_a4<kVec>(arp, K, kk);
-  t.a1 = gemm_a4<kVec>(arp, K, kk + 4);
-  t.a2 = gemm_a4<kVec>(arp, K, kk + 8);
-  t.a3 = gemm_a4<kVec>(arp, K, kk + 12);
-  const uint4* hp = reinterpret_cast<const uint4*>(bhp + k0);
-  const uint4* lp = reinterpret_cast<const uint4*>(blp + k0);
-  t.h0 = hp[0], t.h1 = hp[1], t.h2 = hp[2], t.h3 = hp[3];
-  t.l0 = lp[0], t.l1 = lp[1], t.l2 = lp[2], t.l3 = lp[3];
-}
-// 8 floats, scaled, as hi and lo 16-bit vectors
-template <typename T16>
-__device__ __forceinline__ void gemm_split8(float4 x, float4 y, float s, typename Vec8<T16>::type& hi,
-                                            typename Vec8<T16>::type& lo) {
-  const float v[8] = {x.x * s, x.y * s, x.z * s, x.w * s, y.x * s, y.y * s, y.z * s, y.w * s};
+// The input rows split once into 16-bit hi and lo parts (scaled by the row's
+// power of two for FP16), M rounded up to BM with zero rows and K to Kp with
+// zeros, so the GEMM reads both operands the same way and masks nothing.
+// One block per row, 4 values per thread.
+template <typename T16, bool kRows>
+__global__ __launch_bounds__(128) void k_split_rows(const float* const* a_rows, const float* a_base, long long lda,
+                                                    int M, int K, int Kp, const float* __restrict__ rowscale,
+                                                    T16* __restrict__ a_hi, T16* __restrict__ a_lo) {
+  const int r = blockIdx.x;
+  const bool ok = r < M;
+  const float* ap = ok ? (kRows ? a_rows[r] : a_base + (long long)r * lda) : nullptr;
+  const float s = (ok && rowscale) ? rowscale[r] : 1.0f;
+  for (int k = threadIdx.x * 4; k < Kp; k += 128 * 4) {
+    T16 h[4], l[4];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const T16 t = T16(v[i]);
-    hi[i] = t;
-    lo[i] = T16(v[i] - float(t));
+    for (int i = 0; i < 4; ++i) {
+      const float v = (ok && k + i < K) ? ap[k + i] * s : 0.f;
+      h[i] = T16(v);
+      l[i] = T16(v - float(h[i]));
+    }
+    T16* hp = a_hi + (long long)r * Kp + k;
+    T16* lp = a_lo + (long long)r * Kp + k;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      hp[i] = h[i];
+      lp[i] = l[i];
+    }
   }
 }
+
+// One K tile of both operands in registers: 16 entries of an A row and of a
+// W row, hi and lo.  Named members, no arrays, so that nothing is addressed
+// through scratch.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+struct GemmTile {
+  u32x4 ah0, ah1, al0, al1, wh0, wh1, wl0, wl1;
+};
 template <typename T16>
-__device__ __forceinline__ void gemm_store(const GemmTile& t, float as, T16* ahi, T16* alo, T16* bhi, T16* blo) {
-  typedef typename Vec8<T16>::type V8;
-  V8 hi, lo;
-  gemm_split8<T16>(t.a0, t.a1, as, hi, lo);
-  *reinterpret_cast<V8*>(ahi) = hi;
-  *reinterpret_cast<V8*>(alo) = lo;
-  gemm_split8<T16>(t.a2, t.a3, as, hi, lo);
-  *reinterpret_cast<V8*>(ahi + 8) = hi;
-  *reinterpret_cast<V8*>(alo + 8) = lo;
-  uint4* bh = reinterpret_cast<uint4*>(bhi);
-  uint4* bl = reinterpret_cast<uint4*>(blo);
-  bh[0] = t.h0, bh[1] = t.h1, bh[2] = t.h2, bh[3] = t.h3;
-  bl[0] = t.l0, bl[1] = t.l1, bl[2] = t.l2, bl[3] = t.l3;
+__device__ __forceinline__ void gemm_load(const T16* ahp, const T16* alp, const T16* bhp, const T16* blp, int k0,
+                                          GemmTile& t) {
+  const u32x4* a = reinterpret_cast<const u32x4*>(ahp + k0);
+  const u32x4* b = reinterpret_cast<const u32x4*>(alp + k0);
+  const u32x4* c = reinterpret_cast<const u32x4*>(bhp + k0);
+  const u32x4* d = reinterpret_cast<const u32x4*>(blp + k0);
+  t.ah0 = a[0], t.ah1 = a[1];
+  t.al0 = b[0], t.al1 = b[1];
+  t.wh0 = c[0], t.wh1 = c[1];
+  t.wl0 = d[0], t.wl1 = d[1];
+}
+template <typename T16>
+__device__ __forceinline__ void gemm_store(const GemmTile& t, T16* ahi, T16* alo, T16* bhi, T16* blo) {
+  u32x4* a = reinterpret_cast<u32x4*>(ahi);
+  u32x4* b = reinterpret_cast<u32x4*>(alo);
+  u32x4* c = reinterpret_cast<u32x4*>(bhi);
+  u32x4* d = reinterpret_cast<u32x4*>(blo);
+  a[0] = t.ah0, a[1] = t.ah1;
+  b[0] = t.al0, b[1] = t.al1;
+  c[0] = t.wh0, c[1] = t.wh1;
+  d[0] = t.wl0, d[1] = t.wl1;
 }
 
-// out[r, c] = (sum_k in[r, k] W[c, k]) * w_unscale  for r < M, c < Nc.
-// Block 256 threads = 4 waves as 2 (rows) x 2 (cols); each wave owns a 32 x 64
-// tile = 2 x 4 MFMA 16x16 tiles, two 32-deep MFMA steps per K tile of 64.
+// An output row pointer read from memory is a generic (flat) pointer, whose
+// stores are counted with the LDS operations; rebuilt as an offset from a
+// kernel argument (hidden from the optimiser, which would fold it back) its
+// stores are global ones.
+template <typename T, typename B>
+__device__ __forceinline__ T* gemm_global(T* p, const B* base) {
+  long long off = reinterpret_cast<const char*>(p) - reinterpret_cast<const char*>(base);
+  asm volatile("" : "+v"(off));
+  return reinterpret_cast<T*>(const_cast<char*>(reinterpret_cast<const char*>(base)) + off);
+}
+
+template <typename T16>
+struct GemmStage {
+  T16 a_hi[BM][LDSK], a_lo[BM][LDSK], b_hi[BN][LDSK], b_lo[BN][LDSK];
+};
+
+// One K tile: store the prefetched operands into stage S, barrier, start the
+// loads of tile kt + 2 into the same registers, multiply from S.
+template <typename T16>
+__device__ __forceinline__ void gemm_step(GemmStage<T16>& S, GemmTile& cur, f32x4 (&acc)[4][4], int kt, int nk,
+                                          int ar, int kc, int lane, int wm, int wn, const T16* ahp, const T16* alp,
+                                          const T16* bhp, const T16* blp) {
+  typedef typename Vec8<T16>::type V8;
+  gemm_store<T16>(cur, &S.a_hi[ar][kc], &S.a_lo[ar][kc], &S.b_hi[ar][kc], &S.b_lo[ar][kc]);
+  __syncthreads();
+  gemm_load<T16>(ahp, alp, bhp, blp, min(kt + 2, nk - 2 + (kt & 1)) * BK, cur);  // in flight during the MFMAs
+  const int kq = (lane >> 4) * 8;
+  V8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    const int r = wm * 64 + mt * 16 + (lane & 15);
+    ah[mt] = *reinterpret_cast<const V8*>(&S.a_hi[r][kq]);
+    al[mt] = *reinterpret_cast<const V8*>(&S.a_lo[r][kq]);
+  }
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const int c = wn * 64 + nt * 16 + (lane & 15);
+    bh[nt] = *reinterpret_cast<const V8*>(&S.b_hi[c][kq]);
+    bl[nt] = *reinterpret_cast<const V8*>(&S.b_lo[c][kq]);
+  }
+  // hi*hi, then hi*lo, then lo*hi: 16 independent tiles between dependent MFMAs
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = Vec8<T16>::mfma(ah[mt], bh[nt], acc[mt][nt]);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = Vec8<T16>::mfma(ah[mt], bl[nt], acc[mt][nt]);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = Vec8<T16>::mfma(al[mt], bh[nt], acc[mt][nt]);
+}
+
+// out[r, c] = (sum_k A[r, k] W[c, k]) * w_unscale / rowscale[r]  for r < M, c < Nc,
+// with A and W given as hi + lo (rows of Kp entries; A has a multiple of BM
+// rows).  Block 256 threads = 4 waves as 2 (rows) x 2 (cols); each wave owns a
+// 64 x 64 tile = 4 x 4 MFMA 16x16 tiles, one 32-deep MFMA step per K tile.
 // Operand layout of v_mfma_f32_16x16x32: A lane l holds A[l % 16][8 (l / 16) + i],
 // B lane l holds B[8 (l / 16) + i][l % 16], D lane l holds D[4 (l / 16) + v][l % 16].
-// The next K tile of A (16 floats per thread) and W (hi and lo, 64 bytes each
-// per thread) is loaded into registers while the current one is multiplied
-// from LDS; A is split into hi + lo when it is stored to LDS.  kVec: rows are
-// read as float4 (K a multiple of 4).
-template <typename T16, bool kVec>
-__global__ __launch_bounds__(256) void k_split_gemm(const float* const* a_rows, const float* a_base, long long lda,
-                                                    float* const* c_rows, float* c_base, long long ldc,
+// Two LDS stages: K tile t is stored into stage t & 1 while the MFMAs of tile
+// t - 1 may still read the other one, so one barrier per K tile suffices;
+// the operands of tile t + 2 are loaded into registers while tile t is
+// multiplied.
+template <typename T16, bool kRows>
+__global__ __launch_bounds__(256) void k_split_gemm(float* const* c_rows, float* c_base, long long ldc,
+                                                    const T16* __restrict__ a_hi, const T16* __restrict__ a_lo,
                                                     const T16* __restrict__ w_hi, const T16* __restrict__ w_lo,
-                                                    int M, int K, int Nc, int Kp, const float* __restrict__ rowscale,
+                                                    int M, int Nc, int Kp, const float* __restrict__ rowscale,
                                                     float w_unscale) {
   typedef typename Vec8<T16>::type V8;
-  __shared__ __attribute__((aligned(16))) T16 sa_hi[BM][LDSK];
-  __shared__ __attribute__((aligned(16))) T16 sa_lo[BM][LDSK];
-  __shared__ __attribute__((aligned(16))) T16 sb_hi[BN][LDSK];
-  __shared__ __attribute__((aligned(16))) T16 sb_lo[BN][LDSK];
+  __shared__ __attribute__((aligned(16))) GemmStage<T16> st[2];
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
-  f32x4 acc[2][4];
+  f32x4 acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  // A: thread -> row arow, 16 consecutive k from akc; W: row brow, 32 k from bkc
-  const int arow = tid >> 2, akc = (tid & 3) * 16;
-  const float* arp = nullptr;
-  float as = 1.0f;
-  if (m0 + arow < M) {
-    arp = a_rows ? a_rows[m0 + arow] : a_base + (long long)(m0 + arow) * lda;
-    if (rowscale) as = rowscale[m0 + arow];
-  }
-  const int brow = tid >> 1, bkc = (tid & 1) * 32;
-  const T16* bhp = w_hi + (long long)(n0 + brow) * Kp + bkc;
-  const T16* blp = w_lo + (long long)(n0 + brow) * Kp + bkc;
+  // thread -> A row m0 + ar and W row n0 + ar, 16 consecutive k from kc
+  const int ar = tid >> 1, kc = (tid & 1) * 16;
+  const T16* ahp = a_hi + (long long)(m0 + ar) * Kp + kc;
+  const T16* alp = a_lo + (long long)(m0 + ar) * Kp + kc;
+  const T16* bhp = w_hi + (long long)(n0 + ar) * Kp + kc;
+  const T16* blp = w_lo + (long long)(n0 + ar) * Kp + kc;
+  // Kp is a multiple of 2 BK: an even number of K tiles, so both steps of the
+  // loop body run unconditionally; the prefetch index is clamped (the last
+  // two reloads are unused).
+  const int nk = Kp / BK;
 
-  GemmTile tile;
-  gemm_load<kVec>(arp, K, 0, akc, bhp, blp, tile);
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    gemm_store<T16>(tile, as, &sa_hi[arow][akc], &sa_lo[arow][akc], &sb_hi[brow][bkc], &sb_lo[brow][bkc]);
-    __syncthreads();
-    if (k0 + BK < K) gemm_load<kVec>(arp, K, k0 + BK, akc, bhp, blp, tile);  // in flight during the MFMAs below
-#pragma unroll
-    for (int ks = 0; ks < BK; ks += 32) {
-      const int kq = ks + (lane >> 4) * 8;
-      V8 ah[2], al[2];
-#pragma unroll
-      for (int mt = 0; mt < 2; ++mt) {
-        const int r = wm * 32 + mt * 16 + (lane & 15);
-        ah[mt] = *reinterpret_cast<const V8*>(&sa_hi[r][kq]);
-        al[mt] = *reinterpret_cast<const V8*>(&sa_lo[r][kq]);
-      }
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-        const int c = wn * 64 + nt * 16 + (lane & 15);
-        const V8 wh = *reinterpret_cast<const V8*>(&sb_hi[c][kq]);
-        const V8 wl = *reinterpret_cast<const V8*>(&sb_lo[c][kq]);
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-          acc[mt][nt] = Vec8<T16>::mfma(ah[mt], wh, acc[mt][nt]);
-          acc[mt][nt] = Vec8<T16>::mfma(ah[mt], wl, acc[mt][nt]);
-          acc[mt][nt] = Vec8<T16>::mfma(al[mt], wh, acc[mt][nt]);
-        }
-      }
-    }
-    __syncthreads();
+  GemmTile t0, t1;
+  gemm_load<T16>(ahp, alp, bhp, blp, 0, t0);
+  gemm_load<T16>(ahp, alp, bhp, blp, BK, t1);
+  for (int kt = 0; kt < nk; kt += 2) {
+    gemm_step<T16>(st[0], t0, acc, kt, nk, ar, kc, lane, wm, wn, ahp, alp, bhp, blp);
+    gemm_step<T16>(st[1], t1, acc, kt + 1, nk, ar, kc, lane, wm, wn, ahp, alp, bhp, blp);
   }
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt) {
+  for (int mt = 0; mt < 4; ++mt) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int r = m0 + wm * 32 + mt * 16 + (lane >> 4) * 4 + v;
+      const int r = m0 + wm * 64 + mt * 16 + (lane >> 4) * 4 + v;
       if (r >= M) continue;
-      float* cp = c_rows ? c_rows[r] : c_base + (long long)r * ldc;
+      float* cp = kRows ? gemm_global(c_rows[r], w_hi) : c_base + (long long)r * ldc;
       const float f = w_unscale / (rowscale ? rowscale[r] : 1.0f);
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) {
@@ -322,7 +350,7 @@ std::vector<double> real_form(const std::vector<double2>& Mc, long long so, long
 fcc_status upload_split(const std::vector<double>& W, int K, int Nc, bool fp16, DenseOp* op) {
   op->K = K;
   op->Nc = Nc;
-  op->Kp = (K + BK - 1) / BK * BK;
+  op->Kp = (K + KP_ALIGN - 1) / KP_ALIGN * KP_ALIGN;
   op->Ncp = (Nc + BN - 1) / BN * BN;
   double mx = 0.0;
   for (double v : W) mx = std::max(mx, std::fabs(v));
@@ -356,6 +384,8 @@ void dense_free(fcc_plan_s* p) {
   }
   if (p->rowscale) (void)hipFree(p->rowscale);
   p->rowscale = nullptr;
+  if (p->dws) (void)hipFree(p->dws);
+  p->dws = nullptr;
 }
 
 fcc_status dense_prepare(fcc_plan_s* p, hipStream_t st) {
@@ -439,38 +469,57 @@ fcc_status dense_prepare(fcc_plan_s* p, hipStream_t st) {
   return FCC_OK;
 }
 
+size_t dense_ws_bytes(const DenseOp& op, int M) {
+  const size_t mp = (size_t(std::max(M, 1)) + BM - 1) / BM * BM;
+  return 2 * mp * size_t(op.Kp) * sizeof(uint16_t);
+}
+
 fcc_status dense_run(const fcc_plan_s* p, const DenseOp& op, int M, const void* const* in_rows_dev,
-                     void* const* out_rows_dev, const void* in_base, void* out_base, float* rowscale,
-                     hipStream_t st) {
+                     void* const* out_rows_dev, const void* in_base, void* out_base, float* rowscale, void* aws,
+                     hipStream_t st, long long lda, long long ldc, hipEvent_t* ev) {
+  if (lda <= 0) lda = op.K;
+  if (ldc <= 0) ldc = op.Nc;
+  if (!aws) return FCC_ERR_INVALID_ARG;
   const bool fp16 = p->prec == FCC_PREC_SPLIT_FP16;
   const float* const* ar = reinterpret_cast<const float* const*>(in_rows_dev);
   float* const* cr = reinterpret_cast<float* const*>(out_rows_dev);
   const float* ab = static_cast<const float*>(in_base);
   float* cb = static_cast<float*>(out_base);
-  if (fp16) {
-    if (!rowscale) return FCC_ERR_INVALID_ARG;
-    hipLaunchKernelGGL(k_rowscale, dim3(M), dim3(256), 0, st, ar, ab, (long long)op.K, op.K, rowscale);
-  } else {
-    rowscale = nullptr;
-  }
-  dim3 grid(op.Ncp / BN, (M + BM - 1) / BM);
-  const bool vec = (op.K & 3) == 0;
-#define FCC_GEMM(T, V)                                                                                           \
-  hipLaunchKernelGGL((k_split_gemm<T, V>), grid, dim3(256), 0, st, ar, ab, (long long)op.K, cr, cb,              \
-                     (long long)op.Nc, static_cast<const T*>(op.w_hi), static_cast<const T*>(op.w_lo), M, op.K, \
-                     op.Nc, op.Kp, rowscale, op.w_unscale)
-  if (fp16) {
-    if (vec)
-      FCC_GEMM(_Float16, true);
+  if (fp16 && !rowscale) return FCC_ERR_INVALID_ARG;
+  if (!fp16) rowscale = nullptr;
+  if (ev) (void)hipEventRecord(ev[0], st);
+  if (fp16) hipLaunchKernelGGL(k_rowscale, dim3(M), dim3(256), 0, st, ar, ab, lda, op.K, rowscale);
+  const int mp = (M + BM - 1) / BM * BM;
+  const bool rows = ar != nullptr;
+  auto go = [&](auto t16) {
+    using T = decltype(t16);
+    T* ahi = static_cast<T*>(aws);
+    T* alo = ahi + size_t(mp) * op.Kp;
+    const T* wh = static_cast<const T*>(op.w_hi);
+    const T* wl = static_cast<const T*>(op.w_lo);
+    if (rows)
+      hipLaunchKernelGGL((k_split_rows<T, true>), dim3(mp), dim3(128), 0, st, ar, ab, lda, M, op.K, op.Kp, rowscale,
+                         ahi, alo);
     else
-      FCC_GEMM(_Float16, false);
-  } else {
-    if (vec)
-      FCC_GEMM(__bf16, true);
+      hipLaunchKernelGGL((k_split_rows<T, false>), dim3(mp), dim3(128), 0, st, ar, ab, lda, M, op.K, op.Kp,
+                         rowscale, ahi, alo);
+    const dim3 grid(op.Ncp / BN, mp / BM);
+    if (ev) {
+      (void)hipEventRecord(ev[1], st);
+      (void)hipEventRecord(ev[2], st);
+    }
+    if (cr)
+      hipLaunchKernelGGL((k_split_gemm<T, true>), grid, dim3(256), 0, st, cr, cb, ldc, ahi, alo, wh, wl, M, op.Nc,
+                         op.Kp, rowscale, op.w_unscale);
     else
-      FCC_GEMM(__bf16, false);
-  }
-#undef FCC_GEMM
+      hipLaunchKernelGGL((k_split_gemm<T, false>), grid, dim3(256), 0, st, cr, cb, ldc, ahi, alo, wh, wl, M, op.Nc,
+                         op.Kp, rowscale, op.w_unscale);
+  };
+  if (fp16)
+    go(_Float16{});
+  else
+    go(__bf16{});
+  if (ev) (void)hipEventRecord(ev[3], st);
   return hipGetLastError() == hipSuccess ? FCC_OK : FCC_ERR_HIP;
 }
 

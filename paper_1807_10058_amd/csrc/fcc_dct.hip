@@ -1985,7 +1985,8 @@ bool inv_last2(const fcc_plan_s* p) {
 int slot_count(const fcc_plan_s* p, int d) {
   const int extra = p->hslot ? 1 : 0;
   if (p->fold) return p->n == 1 ? 1 : 4;
-  if (p->n == 1 || p->dense) return 1 + extra;
+  if (p->dense) return 2;  // split of the input, GEMM
+  if (p->n == 1) return 1 + extra;
   if (p->transposed) return p->D;
   int k = 1 + extra;
   if (d == 1) {
@@ -2047,8 +2048,12 @@ std::vector<SlotDesc> describe_slots(const fcc_plan_s* p, int d) {
     return v;
   }
   if (p->n == 1) return {{d == 0 ? "k_copy1" : "k_copy1", d == 0 ? rin : c, d == 0 ? c : rin}};
-  if (p->dense) return {{std::string("k_split_gemm") + (p->prec == FCC_PREC_SPLIT_FP16 ? "<f16>" : "<bf16>"),
-                         d == 0 ? rin : c, d == 0 ? c : rin}};
+  if (p->dense) {
+    // the split of the input (read once, hi + lo written in 16 bits) and the GEMM
+    const std::string t = p->prec == FCC_PREC_SPLIT_FP16 ? "<f16>" : "<bf16>";
+    const int bi = d == 0 ? rin : c, bo = d == 0 ? c : rin;
+    return {{"k_split_rows" + t, bi, bi}, {"k_split_gemm" + t, bi, bo}};
+  }
   const int D = p->D;
   if (p->transposed) {
     if (d == 0) {
@@ -2775,6 +2780,11 @@ int chunk_volumes(const fcc_plan_s* p, int cnt) {
 // synchronous copy may happen while a stream is being captured).
 struct GroupRes {
   void** rows = nullptr;   // device pointer arrays: in, out, scratch 0, scratch 1 (cnt each)
+  // dense groups whose volumes are evenly spaced: first volume and spacing in
+  // bytes of the in and out lists (0: not evenly spaced)
+  char* base[2] = {nullptr, nullptr};
+  long long stride[2] = {0, 0};
+  void* aws = nullptr;     // dense: the split input of the group, either direction
   float* scale = nullptr;  // dense FP16: per-row scales
   void* ws = nullptr;      // fast path: one scratch pair per volume of a chunk
   size_t wb = 0;
@@ -2803,6 +2813,22 @@ fcc_status prepare_group(std::vector<void*>* allocs, const BatchGroup& g, const 
       ptr[3 * cnt + v] = static_cast<char*>(r->ws) + r->wb * (2 * size_t(slot) + 1);
     }
   }
+  if (p->dense) {
+    const size_t b = std::max(dense_ws_bytes(p->dfwd, cnt), dense_ws_bytes(p->dinv, cnt));
+    if (hipMalloc(&r->aws, b) != hipSuccess) return FCC_ERR_OOM;
+    allocs->push_back(r->aws);
+  }
+  if (p->dense && cnt > 1)
+    for (int l = 0; l < 2; ++l) {
+      char* b = static_cast<char*>(ptr[size_t(l) * cnt]);
+      const long long st = static_cast<char*>(ptr[size_t(l) * cnt + 1]) - b;
+      bool even = st > 0 && st % 16 == 0;
+      for (int v = 2; v < cnt && even; ++v) even = static_cast<char*>(ptr[size_t(l) * cnt + v]) - b == st * v;
+      if (even) {
+        r->base[l] = b;
+        r->stride[l] = st;
+      }
+    }
   void* d = nullptr;
   if (hipMalloc(&d, sizeof(void*) * ptr.size() + sizeof(float) * cnt) != hipSuccess) return FCC_ERR_OOM;
   allocs->push_back(d);
@@ -2827,10 +2853,14 @@ fcc_status enqueue_group(const BatchGroup& g, const GroupRes& r, int d, bool swa
   void** w1 = r.rows + 3 * cnt;
   fcc_status s = FCC_OK;
   if (p->dense) {
-    if (ev) (void)hipEventRecord((*ev)[(*evpos)++], st);
-    s = dense_run(p, d > 0 ? p->dfwd : p->dinv, cnt, in, out, nullptr, nullptr, r.scale, st);
-    if (ev) (void)hipEventRecord((*ev)[(*evpos)++], st);
-    return s;
+    hipEvent_t* e = ev ? &(*ev)[*evpos] : nullptr;
+    if (ev) *evpos += 4;
+    // evenly spaced volumes: base + row stride, else the pointer arrays
+    const int li = swap ? 1 : 0, lo = swap ? 0 : 1;
+    if (r.stride[0] && r.stride[1] && r.stride[li] % 4 == 0 && r.stride[lo] % 4 == 0)
+      return dense_run(p, d > 0 ? p->dfwd : p->dinv, cnt, nullptr, nullptr, r.base[li], r.base[lo], r.scale, r.aws,
+                       st, r.stride[li] / 4, r.stride[lo] / 4, e);
+    return dense_run(p, d > 0 ? p->dfwd : p->dinv, cnt, in, out, nullptr, nullptr, r.scale, r.aws, st, 0, 0, e);
   }
   for (int v0 = 0; v0 < cnt && s == FCC_OK; v0 += r.chunk) {
     const int k = std::min(r.chunk, cnt - v0);
@@ -3003,7 +3033,9 @@ void lookup_static_scratch(int dev);  // allocation-free entry point (below)
 // Built-in schedule: the autotuner's choices on MI355X at n = 64, 128, 256.
 fcc_tuning default_tuning(int n) {
   // The searches at n = 64, 128 and 256 (fcc_dct_autotune, reps 5), taken
-  // for n <= 64, n = 128 and n >= 256.
+  // for n <= 64, n = 128 and n >= 256; with orbit-block levels the forward
+  // at n = 256 is faster with the last level fused to the DCT_2 pass of the
+  // level above (3.04 ms) than with the two-level LDS tail (3.09 ms).
   constexpr unsigned X = FCC_MAP_XCD, FI = FCC_MAP_F_INNER, N8 = FCC_MAP_NODES8, N64 = FCC_MAP_NODES64,
                      SP = FCC_MAP_SPLIT, X16 = FCC_MAP_XCD16, CL = FCC_MAP_CLUSTER;
   struct Choice {
@@ -3019,7 +3051,7 @@ fcc_tuning default_tuning(int n) {
                              {{{2, 2, 2}, {2, 2, 2}}, {{1, 2, 3}, {0, 0, 0}}},
                              {{SP, SP | X16, SP | N8 | X, SP | N64, SP, SP, SP | N64, SP | N64, SP | N64, SP | N64},
                               {CL | X, CL | X, N64 | X, X, 0, 0, 0, 0, 0, 0}}};
-  static const Choice large = {{2, 1},
+  static const Choice large = {{1, 1},
                                {{{2, 2, 2}, {2, 2, 2}}, {{2, 2, 2}, {0, 0, 0}}},
                                {{SP, SP | X16 | FI, SP | X16 | N64, SP | N64, SP | X16 | N64, SP | N64, SP | N64,
                                  SP | N64, SP | N64, SP | N64},
@@ -3415,6 +3447,9 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
   if (s == FCC_OK && p->dense) {
     s = dense_prepare(p, st);
     if (s == FCC_OK && hipMalloc(&p->rowscale, sizeof(float)) != hipSuccess) s = FCC_ERR_OOM;
+    if (s == FCC_OK &&
+        hipMalloc(&p->dws, std::max(dense_ws_bytes(p->dfwd, 1), dense_ws_bytes(p->dinv, 1))) != hipSuccess)
+      s = FCC_ERR_OOM;
     p->rows_cap = 1;
   }
   if (s != FCC_OK) {
@@ -3463,7 +3498,7 @@ fcc_status fcc_dct_forward(fcc_plan_t p, const void* x, void* X, void* hip_strea
   if (x == X) return FCC_ERR_UNSUPPORTED;
   (void)hipGetLastError();
   if (p->dense)
-    return dense_run(p, p->dfwd, 1, nullptr, nullptr, x, X, p->rowscale, static_cast<hipStream_t>(hip_stream));
+    return dense_run(p, p->dfwd, 1, nullptr, nullptr, x, X, p->rowscale, p->dws, static_cast<hipStream_t>(hip_stream));
   return enqueue_forward(p, 1, one_vol(x), one_vol(X), one_vol(p->ws[0]), one_vol(p->ws[1]),
                          static_cast<hipStream_t>(hip_stream));
 }
@@ -3513,8 +3548,11 @@ fcc_status fcc_dct_forward_static(fcc_plan_t p, const void* x, void* X, void* hi
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   char* base = static_cast<char*>(static_scratch(p->device));
   if (!base) return FCC_ERR_HIP;
-  // dense path: its per-row input scale (one float) in the array
-  if (p->dense) return dense_run(p, p->dfwd, 1, nullptr, nullptr, x, X, reinterpret_cast<float*>(base), st);
+  // dense path: its per-row input scale (one float) and, 256 bytes on, the split input
+  if (p->dense) {
+    if (256 + dense_ws_bytes(p->dfwd, 1) > kStaticScratchBytes) return FCC_ERR_UNSUPPORTED;
+    return dense_run(p, p->dfwd, 1, nullptr, nullptr, x, X, reinterpret_cast<float*>(base), base + 256, st);
+  }
   const size_t half = size_t(p->n) * p->n * p->n * (p->stages64 ? sizeof(double2) : sizeof(float2));
   // the two buffers, each 256-byte aligned
   const size_t stride = (half + 255) & ~size_t(255);
@@ -3527,7 +3565,7 @@ fcc_status fcc_dct_inverse(fcc_plan_t p, const void* X, void* x, void* hip_strea
   if (x == X) return FCC_ERR_UNSUPPORTED;
   (void)hipGetLastError();
   if (p->dense)
-    return dense_run(p, p->dinv, 1, nullptr, nullptr, X, x, p->rowscale, static_cast<hipStream_t>(hip_stream));
+    return dense_run(p, p->dinv, 1, nullptr, nullptr, X, x, p->rowscale, p->dws, static_cast<hipStream_t>(hip_stream));
   return enqueue_inverse(p, 1, one_vol(X), one_vol(x), one_vol(p->ws[0]), one_vol(p->ws[1]),
                          static_cast<hipStream_t>(hip_stream));
 }
@@ -3541,8 +3579,8 @@ fcc_status time_slots(const fcc_plan_s* p, const void* in, void* out, int direct
                       std::vector<float>* ms) {
   const int slots = slot_count(p, direction > 0 ? 0 : 1);
   ms->assign(slots, 0.f);
-  // the dense path is one library launch sequence timed as a whole (events
-  // between launches); the fast path records a start and stop per kernel
+  // the dense path records its events itself (around the split and the
+  // GEMM); the fast path records a start and stop per kernel
   const bool whole = p->dense;
   std::vector<hipEvent_t> ev(size_t(2) * slots * reps, nullptr);
   fcc_status s = FCC_OK;
@@ -3556,9 +3594,8 @@ fcc_status time_slots(const fcc_plan_s* p, const void* in, void* out, int direct
   for (int r = 0; r < reps && s == FCC_OK; ++r) {
     std::vector<hipEvent_t> sub(ev.begin() + size_t(r) * 2 * slots, ev.begin() + size_t(r + 1) * 2 * slots);
     if (whole) {
-      (void)hipEventRecord(sub[0], st);
-      s = dense_run(p, direction > 0 ? p->dfwd : p->dinv, 1, nullptr, nullptr, in, out, p->rowscale, st);
-      (void)hipEventRecord(sub[1], st);
+      s = dense_run(p, direction > 0 ? p->dfwd : p->dinv, 1, nullptr, nullptr, in, out, p->rowscale, p->dws, st, 0,
+                    0, sub.data());
       continue;
     }
     LaunchTimer tm;

@@ -13,16 +13,18 @@
 //             DCT_2(phi)^{-1} (per-cube solves), then form every output
 //             x(q' + m o) from the orbit's 8|O| cube values (C_nl's block).
 //
-// A block takes 16 "units" = K orbits of one kind x G nodes (G = 1 at level
-// 0, 8 at level 1, 16 below; the nodes are consecutive in J, so for one
-// source slot the units of one orbit read consecutive addresses).  Their
-// sources (or cube values) sit in LDS as [slot][unit], slot = cube slot * 8
-// + o (or def).  The rows are summed by wavefronts of 64 lanes = 4 cube slots
-// x 16 units; a template row is split by monomial of the node's coefficient
-// polynomials into 5 segments of real coefficients, and the cube slots are
-// ordered so that the 4 slots of a wavefront have identical segment lengths
-// (generic orbits: groups of 4 cubes with the same profile), so the lanes of a
-// wavefront run the same trip counts.  Each lane forms its unit's monomials.
+// A block takes 8 "units" = K orbits of one kind x G nodes (G = 1 at level
+// 0, 8 below; the nodes are consecutive in J, so for one source slot the
+// units of one orbit read consecutive addresses).  Their sources (or cube
+// values) sit in LDS as [slot][unit], slot = cube slot * 8 + o (or def).  The
+// rows are summed by wavefronts of 64 lanes = 8 cube slots x 8 units; a
+// template row is split by monomial of the node's coefficient polynomials
+// into 5 segments of integer coefficients (the row's rational coefficients
+// times 144), and the cube slots are ordered so that the slots of a wavefront
+// have identical segment lengths (generic orbits: groups of 4 cubes with the
+// same profile), so the lanes of a wavefront run the same trip counts.  The
+// node's DCT_2 (and its inverse) comes from a per-node table of 64 complex
+// entries each.
 // Blocks are numbered so that each XCD works through one contiguous range
 // (consecutive node groups, then consecutive orbits in Morton order of their
 // representatives), which keeps cache lines that neighbouring blocks share in

@@ -31,6 +31,7 @@ struct fcc_plan_s {
   bool dense = false;             // FCC_PREC_SPLIT_*: dense matrix on MFMA
   DenseOp dfwd, dinv;
   float* rowscale = nullptr;      // per-row input scales (FP16 split), rows_cap entries
+  void* dws = nullptr;            // split input of one row, dense_ws_bytes(op, 1) for either direction
   int rows_cap = 0;
   unsigned long long* resid = nullptr;  // 2 words for fcc_dct_roundtrip_residual
   void* nodes = nullptr;                // FP64 node constants of the upper levels
@@ -59,9 +60,14 @@ struct fcc_plan_s {
 namespace fcc {
 // dense.hip
 fcc_status dense_prepare(fcc_plan_s* p, hipStream_t st);
+// in_base / out_base rows are lda / ldc floats apart (0: the operator's row
+// lengths); aws: dense_ws_bytes(op, M) bytes of device workspace (the split
+// input); ev (optional): 4 events recorded around the split and the GEMM
+// (the two launch slots of a dense transform)
 fcc_status dense_run(const fcc_plan_s* p, const DenseOp& op, int M, const void* const* in_rows_dev,
-                     void* const* out_rows_dev, const void* in_base, void* out_base, float* rowscale,
-                     hipStream_t st);
+                     void* const* out_rows_dev, const void* in_base, void* out_base, float* rowscale, void* aws,
+                     hipStream_t st, long long lda = 0, long long ldc = 0, hipEvent_t* ev = nullptr);
+size_t dense_ws_bytes(const DenseOp& op, int M);
 void dense_free(fcc_plan_s* p);
 // fcc_dct.hip: the level-by-level fast inverse for nvol volumes of plan p,
 // with device arrays of per-volume pointers
