@@ -516,7 +516,7 @@ def summarize(directory, workload):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.summarize:
         summarize(args.summarize, args.workload + ("_fold" if args.fold else ""))

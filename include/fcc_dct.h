@@ -50,7 +50,7 @@ typedef enum {
   FCC_ERR_SINGULAR_SKEW = 3, /* (r,s,t) gives coinciding zeros somewhere in the tree */
   FCC_ERR_OOM = 4,           /* device or host allocation failed                   */
   FCC_ERR_HIP = 5,           /* a HIP runtime call failed                          */
-  FCC_ERR_UNSUPPORTED = 6    /* valid request this build does not serve (n > 256) */
+  FCC_ERR_UNSUPPORTED = 6    /* valid request the library does not serve (a size or flag combination) */
 } fcc_status;
 
 typedef enum {
@@ -82,7 +82,7 @@ enum {
   FCC_TRANSPOSED = 1u << 4,
   /* With FCC_REAL_INPUT: the spectrum of real input in Hermitian-packed form.
    * The zeros pair up as j' = (c - g^T j) mod n with X[j'] = conj X[j] (g in W
-   * and c fixed by the skew; Sec. III, x-bar = z, y-bar = y); the forward
+   * and c fixed by the skew; the conjugation symmetry of Sec. III); the forward
    * writes one value per pair (the member with the smaller flat index) and
    * the self-paired zeros, in increasing flat index: fcc_dct_packed_size
    * values.  The inverse reads that form.  Skews without such a pairing return

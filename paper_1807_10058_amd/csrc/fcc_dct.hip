@@ -2963,7 +2963,7 @@ const char* fcc_status_string(fcc_status s) {
     case FCC_ERR_SINGULAR_SKEW: return "FCC_ERR_SINGULAR_SKEW: the skew (r,s,t) gives coinciding zeros";
     case FCC_ERR_OOM: return "FCC_ERR_OOM: allocation failed";
     case FCC_ERR_HIP: return "FCC_ERR_HIP: HIP runtime error";
-    case FCC_ERR_UNSUPPORTED: return "FCC_ERR_UNSUPPORTED: request not supported by this build";
+    case FCC_ERR_UNSUPPORTED: return "FCC_ERR_UNSUPPORTED: valid request the library does not serve";
   }
   return "unknown fcc_status";
 }
