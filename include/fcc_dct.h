@@ -97,24 +97,39 @@ enum {
    * arithmetic in the data precision (FCC_PREC_FP32 runs FP32 throughout).
    * Needs 8 rst integral (the default skew is); FP64 or FP32; n <= 512; not
    * with the other flags except FCC_REAL_INPUT. */
-  FCC_FOLD_FFT = 1u << 6
+  FCC_FOLD_FFT = 1u << 6,
+  /* Hybrid depth (Sec. IV-B, the stepwise decomposition with n = 2^Lt M):
+   * the forward runs the radix-2 levels down to node size M and then, per
+   * node J of level Lt, the dense DCT_M(phi_J), phi_J = ((r,s,t) + J) / 2^Lt,
+   * as a twiddled fold onto the M-torus and a DFT_M^3 shared by all nodes
+   * (the explicit form of Sec. IV-A at the node's skew), one LDS-resident
+   * launch.  M = 2^tail_levels[0] of the schedule (4, 8 or 16, at most
+   * n / 2; default min(16, n / 2)).  The inverse is unchanged (the radix-2
+   * levels; the fold at a node skew has dense orbit blocks up to 24 x 24).
+   * Stage precision as without the flag.  Needs 8 rst integral and
+   * 8 <= n <= 1024 (else FCC_ERR_UNSUPPORTED); not with FCC_TRANSPOSED,
+   * FCC_FOLD_FFT or the split precisions.  A schedule with tail_levels[0]
+   * outside 2..log2(n) - 1 is FCC_ERR_INVALID_ARG. */
+  FCC_FOLD_BASE = 1u << 7
 };
 
 /* Build a plan for DCT_{n x n x n}(r,s,t) (Definition 2).
  *   plan  : receives the new plan (set to NULL on failure).
  *   n     : size parameter, a power of two in [1, 1024] (fast algorithm, Sec. IV-B).
- *           n <= 256 is served (the gather tables pack node-local
- *           coordinates in 8 bits); n = 512 and 1024 return
- *           FCC_ERR_UNSUPPORTED.
+ *           Levels with node size above 256 run as orbit-block launches
+ *           (the per-row gather tables pack node-local coordinates in 8
+ *           bits); the default schedule has them at every node size >= 32.
  *   rst   : host pointer to the skew (r,s,t), or NULL for (1/8, 0, 3/8).
  *   prec  : data/compute precision (fcc_precision).  The split-MFMA precisions
  *           apply the dense transform matrix and need n <= 8.
- *   flags : FCC_REAL_INPUT | FCC_STAGES_FP32 | FCC_STAGES_FP64 | FCC_LEVEL0_FP32.
+ *   flags : FCC_REAL_INPUT | FCC_STAGES_FP32 | FCC_STAGES_FP64 | FCC_LEVEL0_FP32 |
+ *           FCC_TRANSPOSED | FCC_HERMITIAN_PACKED | FCC_FOLD_FFT | FCC_FOLD_BASE.
  * Derives the basis-change patterns on the host (cached per node size),
  * uploads them, generates FP64 tables on the GPU on `hip_stream`, allocates
  * scratch, and synchronises `hip_stream` once before returning.
  * Errors: FCC_ERR_NOT_POW2, FCC_ERR_SINGULAR_SKEW, FCC_ERR_INVALID_ARG,
- * FCC_ERR_UNSUPPORTED (split precisions with n > 8, n > 256), FCC_ERR_OOM,
+ * FCC_ERR_UNSUPPORTED (split precisions with n > 8, the flag limits above),
+ * FCC_ERR_OOM,
  * FCC_ERR_HIP. */
 fcc_status fcc_dct_plan(fcc_plan_t* plan, int n, const double rst[3], fcc_precision prec,
                         unsigned flags, void* hip_stream);

@@ -12,7 +12,7 @@ _LIB_PATH = os.path.join(_HERE, "libfccdct.so")
 FCC_OK = 0
 FCC_PREC_FP64, FCC_PREC_FP32, FCC_PREC_SPLIT_BF16, FCC_PREC_SPLIT_FP16 = 0, 1, 2, 3
 FCC_REAL_INPUT, FCC_STAGES_FP32, FCC_STAGES_FP64, FCC_LEVEL0_FP32 = 1, 2, 4, 8
-FCC_TRANSPOSED, FCC_HERMITIAN_PACKED, FCC_FOLD_FFT = 16, 32, 64
+FCC_TRANSPOSED, FCC_HERMITIAN_PACKED, FCC_FOLD_FFT, FCC_FOLD_BASE = 16, 32, 64, 128
 (FCC_MAP_XCD, FCC_MAP_F_INNER, FCC_MAP_NODES8, FCC_MAP_NODES64, FCC_MAP_SPLIT, FCC_MAP_BALANCE, FCC_MAP_XCD16,
  FCC_MAP_CLUSTER, FCC_MAP_ORBIT) = 1, 2, 4, 8, 16, 32, 64, 128, 256
 _MAX_LEVELS = 10

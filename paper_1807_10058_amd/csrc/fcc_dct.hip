@@ -1377,6 +1377,7 @@ __global__ void k_phase_table(double2* out, int D, double r0, double r1, double 
 
 #include "orbit_level.hpp"
 #include "fold_fft.hpp"
+#include "base_fold.hpp"
 
 
 // ===========================================================================
@@ -1969,7 +1970,7 @@ bool fwd_split(const fcc_plan_s* p, int L) { return !orbit_at(p, 0, L) && (p->tu
 // last level runs alone (fused depth 1) after a two-pass level D - 2 (D >= 3)
 // in the same arithmetic.
 bool fwd_last2(const fcc_plan_s* p) {
-  return p->D >= 3 && p->tail_Lt[0] == p->D - 1 && fwd_split(p, p->D - 2) &&
+  return !p->fold_base && p->D >= 3 && p->tail_Lt[0] == p->D - 1 && fwd_split(p, p->D - 2) &&
          arith64(p, p->D - 2) == arith64(p, p->D - 1);
 }
 // The inverse counterpart: the last level alone, then the DCT_2^{-1} pass of
@@ -2077,7 +2078,10 @@ std::vector<SlotDesc> describe_slots(const fcc_plan_s* p, int d) {
         v.push_back({"k_fwd_level" + L_(L), bi, c});
       }
     }
-    if (fwd_last2(p))
+    if (p->fold_base)
+      v.push_back({"k_fwd_base L" + std::to_string(p->tail_Lt[0]) + "-" + std::to_string(D - 1),
+                   p->tail_Lt[0] == 0 ? rin : c, c});
+    else if (fwd_last2(p))
       v.push_back({"k_fwd_dct2_last2 L" + std::to_string(D - 2) + "-" + std::to_string(D - 1), c, c});
     else if (p->tail_Lt[0] == D - 1 && D >= 2)
       v.push_back({"k_fwd_dct2" + L_(D - 1), c, c});
@@ -2306,6 +2310,50 @@ void inv_tail_dispatch(const fcc_plan_s* p, DT ti, DT to, const VolSet& vs, int 
     inv_tail_out<R, double2>(p, to, vs, nvol, st);
 }
 
+// ---- FCC_FOLD_BASE: the dense base of node size M = n >> tail_Lt[0] -------
+int base_slot(int M) { return M == 4 ? 0 : (M == 8 ? 1 : 2); }
+template <typename R, typename TI, int M>
+void fwd_base_launch(const fcc_plan_s* p, DT to, const VolSet& vs, int nvol, hipStream_t st) {
+  const int Lt = p->tail_Lt[0];
+  const int G = std::min(BaseShape<M>::G, 1 << Lt);
+  const long long blocks = ((1LL << (3 * Lt)) / G) * nvol;
+  const dim3 gr(unsigned(((blocks + 7) >> 3) << 3)), bd(256);
+  const int2* reps = reinterpret_cast<const int2*>(p->breps) + p->brep_off[base_slot(M)];
+  const int norb = p->brep_cnt[base_slot(M)];
+  if constexpr (std::is_same<R, float>::value) {
+    launch((k_fwd_base<R, TI, float2, M>), gr, bd, 0, st, vs, nvol, p->n, Lt, G, p->r8[0], p->r8[1], p->r8[2],
+           reps, norb);
+  } else {
+    if (to == DT::F32C)
+      launch((k_fwd_base<R, TI, float2, M>), gr, bd, 0, st, vs, nvol, p->n, Lt, G, p->r8[0], p->r8[1], p->r8[2],
+             reps, norb);
+    else
+      launch((k_fwd_base<R, TI, double2, M>), gr, bd, 0, st, vs, nvol, p->n, Lt, G, p->r8[0], p->r8[1], p->r8[2],
+             reps, norb);
+  }
+}
+template <typename R, typename TI>
+void fwd_base_m(const fcc_plan_s* p, DT to, const VolSet& vs, int nvol, hipStream_t st) {
+  const int M = p->n >> p->tail_Lt[0];
+  if (M == 4)
+    fwd_base_launch<R, TI, 4>(p, to, vs, nvol, st);
+  else if (M == 8)
+    fwd_base_launch<R, TI, 8>(p, to, vs, nvol, st);
+  else
+    fwd_base_launch<R, TI, 16>(p, to, vs, nvol, st);
+}
+// The base sits below at least one radix-2 level (tail_Lt[0] >= 1), so its
+// input is a stage buffer: complex, FP64 or (FP32 stages, or level 1 of an
+// FCC_LEVEL0_FP32 plan) FP32.
+void fwd_base_dispatch(const fcc_plan_s* p, DT ti, DT to, const VolSet& vs, int nvol, hipStream_t st) {
+  if (!p->stages64)
+    fwd_base_m<float, float2>(p, DT::F32C, vs, nvol, st);
+  else if (ti == DT::F32C)
+    fwd_base_m<double, float2>(p, to, vs, nvol, st);
+  else
+    fwd_base_m<double, double2>(p, to, vs, nvol, st);
+}
+
 template <typename TI, typename TO>
 void launch_copy1(const VolSet& vs, int nvol, hipStream_t st) {
   launch((k_copy1<TI, TO>), dim3(unsigned((nvol + 63) / 64)), dim3(64), 0, st, vs, nvol);
@@ -2505,6 +2553,11 @@ fcc_status enqueue_forward_plain(const fcc_plan_s* p, int nvol, VolPtrs in, VolP
     }
     src = a;
     src_t = to;
+  }
+  // hybrid depth: one dense base per node of level tail_Lt[0]
+  if (p->fold_base) {
+    fwd_base_dispatch(p, src_t, cplx_type(p), VolSet{src, out}, nvol, st);
+    return launch_status("forward base launch");
   }
   // the last level alone (node size 2, B_2 = I): DCT_2 on the cubes, with the
   // DCT_2 pass of level D - 2 where that level is two-pass
@@ -3149,6 +3202,51 @@ fcc_status fold_upload(fcc_plan_s* p, const fcc::FoldTables& t) {
   }
   return e == hipSuccess ? FCC_OK : hip_fail(e, "fold tables", __LINE__);
 }
+// FCC_FOLD_BASE: 8 rst integral; the orbit representatives of W on the
+// M-torus (smallest flat index of each orbit) for M = 4, 8, 16; without an
+// explicit schedule the forward's base has node size min(16, n).
+fcc_status base_prepare(fcc_plan_s* p, const double r[3], bool default_schedule) {
+  for (int i = 0; i < 3; ++i) {
+    const double v = 8.0 * r[i];
+    if (std::fabs(v - std::nearbyint(v)) > 1e-12) return FCC_ERR_UNSUPPORTED;
+    p->r8[i] = int(std::nearbyint(v));
+  }
+  if (p->n > 1024) return FCC_ERR_UNSUPPORTED;  // the base's phase table holds 8 n / M entries
+  p->fold_base = true;
+  if (default_schedule) p->tune.tail_levels[0] = std::min(4, p->D - 1);
+  if (p->tune.tail_levels[0] < 2 || p->tune.tail_levels[0] > p->D - 1) return FCC_ERR_INVALID_ARG;
+  p->tail_Lt[0] = p->D - p->tune.tail_levels[0];
+  std::vector<int> reps;  // (representative, mask of repeated images) pairs
+  for (int m = 0; m < 3; ++m) {
+    const int lg = m + 2, M = 1 << lg;
+    p->brep_off[m] = int(reps.size()) / 2;
+    std::vector<std::pair<int, int>> orb;
+    for (int q = 0; q < M * M * M; ++q) {
+      const int k[3] = {q >> (2 * lg), (q >> lg) & (M - 1), q & (M - 1)};
+      int img[24], mask = 0;
+      bool smallest = true;
+      for (int u = 0; u < 24; ++u) {
+        int v[3];
+        for (int i = 0; i < 3; ++i)
+          v[i] = (kFoldW[u].g[3 * i] * k[0] + kFoldW[u].g[3 * i + 1] * k[1] + kFoldW[u].g[3 * i + 2] * k[2]) & (M - 1);
+        img[u] = (v[0] << (2 * lg)) | (v[1] << lg) | v[2];
+        smallest = smallest && img[u] >= q;
+        for (int w = 0; w < u; ++w)
+          if (img[w] == img[u]) {
+            mask |= 1 << u;
+            break;
+          }
+      }
+      if (smallest) orb.push_back({mask, q});
+    }
+    std::sort(orb.begin(), orb.end());
+    for (const auto& o : orb) reps.push_back(o.second), reps.push_back(o.first);
+    p->brep_cnt[m] = int(orb.size());
+  }
+  hipError_t e = hipMalloc(&p->breps, reps.size() * sizeof(int));
+  if (e == hipSuccess) e = hipMemcpy(p->breps, reps.data(), reps.size() * sizeof(int), hipMemcpyHostToDevice);
+  return e == hipSuccess ? FCC_OK : hip_fail(e, "base orbit table", __LINE__);
+}
 fcc_status fold_prepare(fcc_plan_s* p, const double r[3], hipStream_t) {
   p->fold = true;
   p->stages64 = p->prec == FCC_PREC_FP64;
@@ -3186,7 +3284,7 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
   if (prec < FCC_PREC_FP64 || prec > FCC_PREC_SPLIT_FP16) return FCC_ERR_INVALID_ARG;
   if ((flags & FCC_STAGES_FP32) && (flags & FCC_STAGES_FP64)) return FCC_ERR_INVALID_ARG;
   if (flags & ~(unsigned)(FCC_REAL_INPUT | FCC_STAGES_FP32 | FCC_STAGES_FP64 | FCC_LEVEL0_FP32 | FCC_TRANSPOSED |
-                          FCC_HERMITIAN_PACKED | FCC_FOLD_FFT))
+                          FCC_HERMITIAN_PACKED | FCC_FOLD_FFT | FCC_FOLD_BASE))
     return FCC_ERR_INVALID_ARG;
   if ((flags & FCC_FOLD_FFT) && ((flags & ~(unsigned)(FCC_FOLD_FFT | FCC_REAL_INPUT)) ||
                                  (prec != FCC_PREC_FP32 && prec != FCC_PREC_FP64) || n > 512))
@@ -3195,6 +3293,9 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
   if ((flags & FCC_TRANSPOSED) &&
       (split_prec || (flags & (FCC_LEVEL0_FP32 | FCC_HERMITIAN_PACKED)) || n > 256))
     return FCC_ERR_UNSUPPORTED;
+  if ((flags & FCC_FOLD_BASE) && (split_prec || (flags & (FCC_TRANSPOSED | FCC_FOLD_FFT)) || n < 8))
+    return FCC_ERR_UNSUPPORTED;
+  if ((flags & FCC_FOLD_BASE) && tuning && tuning->tail_levels[0] < 2) return FCC_ERR_INVALID_ARG;
   if ((flags & FCC_HERMITIAN_PACKED) && !(flags & FCC_REAL_INPUT)) return FCC_ERR_INVALID_ARG;
   if ((flags & FCC_HERMITIAN_PACKED) && split_prec) return FCC_ERR_UNSUPPORTED;
   if (tuning && !valid_tuning(*tuning)) return FCC_ERR_INVALID_ARG;
@@ -3241,6 +3342,7 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
     }
   }
   lookup_static_scratch(p->device);
+  bool searched = false;  // the schedule is fcc_dct_autotune's
   if (tuning) {
     resolve_tuning(p, *tuning);
   } else {
@@ -3248,13 +3350,20 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
     {
       std::lock_guard<std::mutex> lock(tuned_mu());
       auto it = tuned().find({p->device, n, int(prec), int(flags)});
-      if (it != tuned().end()) t = it->second;
+      if (it != tuned().end()) t = it->second, searched = true;
     }
     resolve_tuning(p, t);
   }
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   fcc_status s = FCC_OK;
   (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
+  if (flags & FCC_FOLD_BASE) {
+    s = base_prepare(p, r, !tuning && !searched);
+    if (s != FCC_OK) {
+      fcc_dct_destroy(p);
+      return s;
+    }
+  }
   if (flags & FCC_FOLD_FFT) {
     s = fold_prepare(p, r, st);
     if (s != FCC_OK) {
@@ -3487,6 +3596,7 @@ fcc_status fcc_dct_destroy(fcc_plan_t p) {
   if (p->fkt) (void)hipFree(p->fkt);
   if (p->fpid) (void)hipFree(p->fpid);
   if (p->freps) (void)hipFree(p->freps);
+  if (p->breps) (void)hipFree(p->breps);
   for (void* w : p->ws)
     if (w) (void)hipFree(w);
   delete p;
@@ -3682,7 +3792,8 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
       // 1. fused tail depth, by whole-direction time
       int best_k = p->tune.tail_levels[d];
       double best_t = 1e30;
-      for (int k = 1; k <= std::min(4, p->D) && s == FCC_OK; ++k) {
+      for (int k = (d == 0 && p->fold_base) ? 2 : 1; k <= std::min(4, p->D - (d == 0 && p->fold_base)) && s == FCC_OK;
+           ++k) {
         p->tune.tail_levels[d] = k;
         p->tail_Lt[d] = std::max(0, p->D - k);
         double t = 0.0;

@@ -55,6 +55,11 @@ struct fcc_plan_s {
   unsigned char* fpid = nullptr;        // unfold row per image of each orbit representative (24 x fnrep)
   void* freps = nullptr;                // orbit representatives (flat index), by 8^3 box
   int fnpat = 0, fnrep = 0;
+  // FCC_FOLD_BASE (hybrid depth): the forward's last levels as one dense base
+  // per node of size M = n >> tail_Lt[0] (4, 8 or 16)
+  bool fold_base = false;
+  int* breps = nullptr;                 // per orbit of W on the M-torus (M = 4, 8, 16 in turn): representative, mask of repeated images
+  int brep_off[3] = {}, brep_cnt[3] = {};  // in orbits
 };
 
 namespace fcc {

@@ -1,0 +1,143 @@
+"""Hybrid depth (FCC_FOLD_BASE): the forward's radix-2 levels down to node
+size M, then per node J of level Lt the dense DCT_M(phi_J) as a twiddled fold
+plus a shared DFT_M^3 (Sec. IV-B, the decomposition n = 2^Lt M; the base from
+the explicit form of Sec. IV-A at the node's skew).
+
+References: the oracle's dense matrix for n <= 16, its fold+FFT reference
+above (both FP64).  Tolerances: FP64 1e-12 of the largest output (the radix-2
+path's own FP64 bound at these sizes is ~1e-13..1e-11, Sec. 4.1 of the
+design notes' error table); FP32 data with FP64 stages 1e-5 (FP32 rounding of
+input and output only); FP32 stages at n = 8 1e-5."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1807_10058_amd as fcc
+from oracle import fold_ref
+
+pytestmark = pytest.mark.gpu
+gu = pytest.importorskip("tests.gpu_util")
+RNG = np.random.default_rng(1807)
+BASE = fcc.FCC_FOLD_BASE
+
+
+def _plan(n, prec, flags, M=None, rst=None):
+    if M is None:
+        return fcc.fcc_dct_plan(n, rst=rst, prec=prec, flags=flags | BASE)
+    t = fcc.fcc_dct_get_tuning(fcc.fcc_dct_plan(n, rst=rst, prec=prec, flags=flags | BASE))
+    t["tail_levels"][0] = int(M).bit_length() - 1
+    return fcc.fcc_dct_plan_tuned(n, rst=rst, prec=prec, flags=flags | BASE, tuning=t)
+
+
+def _forward(plan, x, prec):
+    real = not np.iscomplexobj(x)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to(gu.DEV, gu.rdtype(prec) if real else gu.cdtype(prec))
+    X = torch.empty(plan.n ** 3, dtype=gu.cdtype(prec), device=gu.DEV)
+    fcc.fcc_dct_forward(plan, xt, X)
+    torch.cuda.synchronize()
+    return xt, X
+
+
+@pytest.mark.parametrize("n,M", [(8, 4), (16, 4), (16, 8), (32, 8), (32, 16), (64, 16)])
+def test_fp64_complex(n, M):
+    x = RNG.standard_normal(n ** 3) + 1j * RNG.standard_normal(n ** 3)
+    plan = _plan(n, fcc.FCC_PREC_FP64, 0, M)
+    assert fcc.fcc_dct_describe_launches(plan, 1)[-1]["name"] == "k_fwd_base L%d-%d" % (
+        (n // M).bit_length() - 1, n.bit_length() - 2)
+    xt, X = _forward(plan, x, fcc.FCC_PREC_FP64)
+    ref = oracle.matrix(n) @ x if n <= 16 else fold_ref.fold_forward(x, n)
+    assert gu.maxrel(X.cpu().numpy(), ref) <= 1e-12
+    # the inverse (the radix-2 levels, with their FP64 bound of the parity
+    # tests: 1e-10 up to n = 64) takes the base's output back
+    y = torch.empty_like(xt)
+    fcc.fcc_dct_inverse(plan, X, y)
+    torch.cuda.synchronize()
+    assert gu.maxrel(y.cpu().numpy(), x) <= 1e-10
+
+
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128])
+def test_fp32_real_default_base(n):
+    """Default M = min(16, n / 2); FP32 data, FP64 stages."""
+    x = RNG.standard_normal(n ** 3).astype(np.float32)
+    plan = _plan(n, fcc.FCC_PREC_FP32, fcc.FCC_REAL_INPUT)
+    assert fcc.fcc_dct_get_tuning(plan)["tail_levels"][0] == min(4, n.bit_length() - 2)
+    xt, X = _forward(plan, x, fcc.FCC_PREC_FP32)
+    assert gu.maxrel(X.cpu().numpy(), fold_ref.fold_forward(x.astype(np.float64), n)) <= 1e-5
+    y = torch.empty_like(xt)
+    fcc.fcc_dct_inverse(plan, X, y)
+    torch.cuda.synchronize()
+    assert fcc.fcc_dct_roundtrip_residual(plan, xt, y) <= 1e-5
+
+
+def test_fewer_levels_less_error():
+    """The same input through the radix-2 plan: in FP64 the radix-2 forward
+    loses ~1e-10 at n = 64 in its deepest (ill-conditioned) levels, the
+    hybrid forward, with the last four levels replaced by the base, stays at
+    the reference's rounding."""
+    n = 64
+    x = RNG.standard_normal(n ** 3) + 1j * RNG.standard_normal(n ** 3)
+    ref = fold_ref.fold_forward(x, n)
+    _, Xb = _forward(_plan(n, fcc.FCC_PREC_FP64, 0), x, fcc.FCC_PREC_FP64)
+    _, Xp = _forward(fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP64, flags=0), x, fcc.FCC_PREC_FP64)
+    eb, ep = gu.maxrel(Xb.cpu().numpy(), ref), gu.maxrel(Xp.cpu().numpy(), ref)
+    assert eb <= 1e-12 and eb < ep, (eb, ep)
+
+
+def test_other_skew_and_stages_fp32():
+    n, rst = 32, (0.625, 0.0, 0.875)
+    x = RNG.standard_normal(n ** 3) + 1j * RNG.standard_normal(n ** 3)
+    _, X = _forward(_plan(n, fcc.FCC_PREC_FP64, 0, 8, rst), x, fcc.FCC_PREC_FP64)
+    assert gu.maxrel(X.cpu().numpy(), fold_ref.fold_forward(x, n, rst)) <= 1e-12
+    # FP32 stages at n = 8 (base M = 4 in FP32 arithmetic)
+    x8 = RNG.standard_normal(512).astype(np.float32)
+    plan = _plan(8, fcc.FCC_PREC_FP32, fcc.FCC_REAL_INPUT | fcc.FCC_STAGES_FP32)
+    _, X8 = _forward(plan, x8, fcc.FCC_PREC_FP32)
+    assert gu.maxrel(X8.cpu().numpy(), oracle.matrix(8) @ x8.astype(np.float64)) <= 1e-5
+
+
+def test_level0_fp32_input_to_base():
+    """FCC_LEVEL0_FP32 at n = 32 with M = 16: the base reads level 1's FP32 buffer."""
+    n = 32
+    x = RNG.standard_normal(n ** 3).astype(np.float32)
+    plan = _plan(n, fcc.FCC_PREC_FP32, fcc.FCC_REAL_INPUT | fcc.FCC_LEVEL0_FP32, 16)
+    _, X = _forward(plan, x, fcc.FCC_PREC_FP32)
+    assert gu.maxrel(X.cpu().numpy(), fold_ref.fold_forward(x.astype(np.float64), n)) <= 1e-5
+
+
+@pytest.mark.parametrize("n", [256])
+def test_full_size_sampled_rows(n):
+    """n = 256 (M = 16, 4096 nodes): sampled rows of the oracle's direct sum."""
+    import workloads
+    x = workloads.upsampled_field(n, seed=3)
+    plan = _plan(n, fcc.FCC_PREC_FP32, fcc.FCC_REAL_INPUT)
+    _, X = _forward(plan, x, fcc.FCC_PREC_FP32)
+    rows = gu.sample_rows(n, 16, n)
+    assert gu.maxrel(X.cpu().numpy()[rows], oracle.forward_rows(x.astype(np.float64), n, rows)) <= 1e-5
+
+
+def test_batched_matches_single():
+    ns = [16, 64, 32, 64, 8]
+    plans = {n: _plan(n, fcc.FCC_PREC_FP32, fcc.FCC_REAL_INPUT) for n in set(ns)}
+    xs = [torch.from_numpy(RNG.standard_normal(n ** 3).astype(np.float32)).to(gu.DEV) for n in ns]
+    outs = [torch.empty(n ** 3, dtype=torch.complex64, device=gu.DEV) for n in ns]
+    fcc.fcc_dct_batched([plans[n] for n in ns], xs, outs, 1)
+    torch.cuda.synchronize()
+    for i, n in enumerate(ns):
+        _, X = _forward(plans[n], xs[i].cpu().numpy(), fcc.FCC_PREC_FP32)
+        assert torch.equal(X, outs[i]), (i, n)
+
+
+def test_bad_combinations():
+    with pytest.raises(fcc.FccError):
+        fcc.fcc_dct_plan(4, prec=fcc.FCC_PREC_FP64, flags=BASE)  # n < 8
+    with pytest.raises(fcc.FccError):
+        fcc.fcc_dct_plan(16, prec=fcc.FCC_PREC_FP64, flags=BASE, rst=(0.31, 0.07, 0.23))  # 8 rst not integral
+    with pytest.raises(fcc.FccError):
+        fcc.fcc_dct_plan(16, prec=fcc.FCC_PREC_FP32, flags=BASE | fcc.FCC_FOLD_FFT)
+    with pytest.raises(fcc.FccError):
+        fcc.fcc_dct_plan(8, prec=fcc.FCC_PREC_SPLIT_BF16, flags=BASE)
+    with pytest.raises(fcc.FccError):
+        _plan(16, fcc.FCC_PREC_FP64, 0, 2)  # tail_levels[0] = 1
+    with pytest.raises(fcc.FccError):
+        _plan(16, fcc.FCC_PREC_FP64, 0, 16)  # M = n
