@@ -7,17 +7,20 @@ A step is one pass of the whole fast path over the workload's input, which is
 already resident in HBM.  Default workload (c5): the ragged batch of 512
 volumes, n drawn from {8, 16, 32, 64, 128} (seed 4), N(0,1) FP32 data,
 forward then inverse in one replay of the recorded HIP graph.  Its line is the
-mixed-precision variant (n = 8 volumes on the split-BF16 MFMA path, the top
-level of the others in FP32 arithmetic, FP64 stages below); the split-only and
-the plain variant (FP32 data, FP64 stages) are reported beside it, with the
-n = 256 single-volume forward + inverse (c4).
+hybrid mixed-precision variant (n = 8 volumes on the split-BF16 MFMA path; the
+others with the top level in FP32 arithmetic, FP64 stages below and the
+forward's last levels as one dense base per node of size min(16, n / 2),
+FCC_FOLD_BASE); the same without the dense base, the split-only and the plain
+variant (FP32 data, FP64 stages) are reported beside it, with the n = 256
+single-volume forward + inverse (c4).
 Other workloads:
   c1  n = 4, FP64, forward + inverse;
   c2  n = 64 forward of a smooth field, FP32 data;
   c3  4096 blocks at n = 8 (8-bit levels / 255), dense split-BF16 MFMA path
       (the FP32 fast path on the same blocks is reported beside it);
-  c4  n = 256 trilinear-upsampled field, FP32 data, forward + inverse, with the
-      FP64 round-trip residual computed on the GPU.
+  c4  n = 256 trilinear-upsampled field, FP32 data, forward + inverse (dense
+      base of node size 16 in the forward), with the FP64 round-trip residual
+      computed on the GPU.
 Prints ONE JSON line: points/s, the roofline of the dominant kernel (the
 launch slot with the longest average duration, timed with start/stop events
 recorded by each launch on its own stream; its algorithmic bytes = the
@@ -44,7 +47,8 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
 MFMA_BF16_PEAK_TFS = 2500.0  # dense BF16 MFMA
 KERNEL_SOURCES = ("paper_1807_10058_amd/csrc/fcc_dct.hip", "paper_1807_10058_amd/csrc/kernels.hpp",
                   "paper_1807_10058_amd/csrc/orbit_level.hpp", "paper_1807_10058_amd/csrc/dense.hip",
-                  "paper_1807_10058_amd/csrc/orbits.inc", "paper_1807_10058_amd/csrc/fold_fft.hpp")
+                  "paper_1807_10058_amd/csrc/orbits.inc", "paper_1807_10058_amd/csrc/fold_fft.hpp",
+                  "paper_1807_10058_amd/csrc/base_fold.hpp")
 TRAFFIC_PROFILE = {"c2": "traffic_c2_n64_forward.md", "c4": "traffic_c4_n256_forward_inverse.md",
                    "c5": "traffic_c5_ragged512_forward_inverse.md",
                    "c4_fold": "traffic_fold_c4_n256_forward_inverse.md",
@@ -188,7 +192,8 @@ def single_volume(args, name):
     tune_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     fold = args.fold and args.pmc_pass and name == "c4"
-    plan = fcc.fcc_dct_plan(n, prec=prec, flags=fcc.FCC_REAL_INPUT | (fcc.FCC_FOLD_FFT if fold else 0))
+    flags = fcc.FCC_REAL_INPUT | (fcc.FCC_FOLD_FFT if fold else (fcc.FCC_FOLD_BASE if name == "c4" else 0))
+    plan = fcc.fcc_dct_plan(n, prec=prec, flags=flags)
     plan_s = time.perf_counter() - t0
     x = torch.from_numpy(np.ascontiguousarray(x_np)).to(dev, rdt)
     X = torch.empty(n ** 3, dtype=cdt, device=dev)
@@ -252,7 +257,7 @@ def c4_beside(args):
     n = 256
     dev = torch.device("cuda:0")
     x_np = workloads.upsampled_field(n, 3)
-    plan = fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT)
+    plan = fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT | fcc.FCC_FOLD_BASE)
     x = torch.from_numpy(np.ascontiguousarray(x_np)).to(dev)
     X = torch.empty(n ** 3, dtype=torch.complex64, device=dev)
     y = torch.empty_like(x)
@@ -262,6 +267,17 @@ def c4_beside(args):
         fcc.fcc_dct_inverse(plan, X, y)
 
     ms, _ = time_steps(step, max(5, args.steps // 2), 2)
+    # the radix-2 levels all the way down (no dense base), same input
+    rplan = fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT)
+
+    def rstep():
+        fcc.fcc_dct_forward(rplan, x, X)
+        fcc.fcc_dct_inverse(rplan, X, y)
+
+    rms, _ = time_steps(rstep, max(5, args.steps // 2), 2)
+    rdirs = {}
+    for s_ in single_slots(rplan, [(1, x, X), (-1, X, y)], 10):
+        rdirs[s_["direction"]] = round(rdirs.get(s_["direction"], 0.0) + s_["ms"], 5)
     slots = single_slots(plan, [(1, x, X), (-1, X, y)], 10)
     roof = roofline("c4", slots)
     dirs = {}
@@ -269,8 +285,10 @@ def c4_beside(args):
         dirs[s["direction"]] = round(dirs.get(s["direction"], 0.0) + s["ms"], 5)
     step()
     torch.cuda.synchronize()
-    out = {"workload": "c4: n=256 forward+inverse, trilinear-upsampled field, FP32 data, FP64 stages",
+    out = {"workload": "c4: n=256 forward+inverse, trilinear-upsampled field, FP32 data, FP64 stages, "
+                       "forward with the dense base of node size 16",
            "ms_per_step": ms, "points_per_s": n ** 3 / (ms * 1e-3), "direction_kernel_ms": dirs,
+           "radix2_to_the_end": {"ms_per_step": rms, "direction_kernel_ms": rdirs},
            "roofline": roof, "roundtrip_max_rel_fp64_gpu": fcc.fcc_dct_roundtrip_residual(plan, x, y),
            "step_frac_of_hbm_floor": (n ** 3 * 28) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     # the fold+FFT variant on the same input (FP32 arithmetic throughout)
@@ -344,16 +362,19 @@ def batched(args, name):
 
     def plan_for_variant(n, variant):
         # split: the split-BF16 dense MFMA path for n <= 8; mixed: that, and the
-        # top level in FP32 arithmetic for larger n (FP64 stages below)
-        if variant in ("split", "mixed") and n <= 8:
+        # top level in FP32 arithmetic for larger n (FP64 stages below);
+        # hybrid: mixed with the forward's dense base per node
+        if variant in ("split", "mixed", "hybrid") and n <= 8:
             return plan_for(n, fcc.FCC_PREC_SPLIT_BF16)
         if variant == "mixed":
             return plan_for(n, fcc.FCC_PREC_FP32, fcc.FCC_REAL_INPUT | fcc.FCC_LEVEL0_FP32)
+        if variant == "hybrid":
+            return plan_for(n, fcc.FCC_PREC_FP32, fcc.FCC_REAL_INPUT | fcc.FCC_LEVEL0_FP32 | fcc.FCC_FOLD_BASE)
         if variant == "fold":
             return plan_for(n, fcc.FCC_PREC_FP32, fcc.FCC_REAL_INPUT | fcc.FCC_FOLD_FFT)
         return plan_for(n, fcc.FCC_PREC_FP32)
 
-    main_variant = "split" if name == "c3" else "mixed"
+    main_variant = "split" if name == "c3" else "hybrid"
     if args.pmc_pass:
         fold = args.fold and name == "c5"
         plans = [plan_for_variant(n, "fold" if fold else main_variant) for n in ns]
@@ -363,7 +384,7 @@ def batched(args, name):
     originals = [x.clone() for x in xs] if direction == 0 else None
     res = {}
     slots_main = None
-    variants = ("split", "fp32") if name == "c3" else ("mixed", "split", "fp32", "fold")
+    variants = ("split", "fp32") if name == "c3" else ("hybrid", "mixed", "split", "fp32", "fold")
     for variant in variants:
         if direction == 0:
             for x, o in zip(xs, originals):
@@ -418,10 +439,12 @@ def batched(args, name):
         dtype = "bf16x3 (split) / f32 acc"
     else:
         roof = roofline(name, slots_main)
-        dtype = "mixed: f32 top level + f64 stages (n >= 16), bf16x3 split MFMA (n = 8); f32 data"
+        dtype = "mixed: f32 top level + f64 stages and base (n >= 16), bf16x3 split MFMA (n = 8); f32 data"
     cfg = {"workload": desc, "volumes": len(ns), "points": points, "io_dtype": "f32",
            "sizes": {str(k): ns.count(k) for k in sorted(set(ns))}, "autotune_seconds": round(tune_s, 3),
-           "variants": {"mixed": "split-BF16 MFMA for n = 8; FP32 top level, FP64 stages below for n >= 16",
+           "variants": {"hybrid": "split-BF16 MFMA for n = 8; FP32 top level, FP64 stages below and the "
+                                  "forward's dense base of node size min(16, n/2) for n >= 16",
+                        "mixed": "split-BF16 MFMA for n = 8; FP32 top level, FP64 stages below for n >= 16",
                         "split": "split-BF16 MFMA for n = 8; FP64 stages for n >= 16",
                         "fp32": "FP32 data, FP64 stages for every n (plain fast path)",
                         "fold": "fold+FFT formulation from the explicit matrix (a variant, not the paper's "
