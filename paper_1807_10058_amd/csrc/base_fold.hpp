@@ -108,6 +108,22 @@ __global__ __launch_bounds__(256) void k_fwd_base(VolSet vs, int nvol, int n, in
   const long long jf = (blk - vol * groups) * G;  // first node of the block, J_z fastest
   const int J0 = int(jf >> (2 * Lt)), J1 = int((jf >> Lt) & mask), J2 = int(jf & mask);
   const int r8[3] = {r80, r81, r82};
+  const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, vol));
+  TO* __restrict__ out = static_cast<TO*>(vol_ptr(vs.out, vol));
+  constexpr int lg = S::lg, M3 = M * M * M;
+  // every load of a thread in flight before the first store to LDS
+  constexpr int kLd = S::G * M3 / 256;
+  cx<R> ld[kLd];
+#pragma unroll
+  for (int c = 0; c < kLd; ++c) {
+    const int t = threadIdx.x + c * 256;
+    if (t < G * M3) {
+      const int g = t % G, a = t / G;
+      const int a0 = a >> (2 * lg), a1 = (a >> lg) & (M - 1), a2 = a & (M - 1);
+      ld[c] = IO<TI, R>::ld(in, ((long long)(J0 + (a0 << Lt)) * n + (J1 + (a1 << Lt))) * n + (J2 + g + (a2 << Lt)));
+    }
+  }
+  // the phase tables while the loads are in flight
   for (int t = threadIdx.x; t < P; t += blockDim.x) {
     double s, c;
     sincospi(2.0 * double(t) / double(P), &s, &c);
@@ -121,14 +137,13 @@ __global__ __launch_bounds__(256) void k_fwd_base(VolSet vs, int nvol, int n, in
     sincospi(2.0 * double(e) / double(8LL * n), &s, &c);
     ax[t] = {R(c), R(s)};
   }
-  const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, vol));
-  TO* __restrict__ out = static_cast<TO*>(vol_ptr(vs.out, vol));
-  constexpr int lg = S::lg, M3 = M * M * M;
-  for (int t = threadIdx.x; t < G * M3; t += blockDim.x) {
-    const int g = t % G, a = t / G;
-    const int a0 = a >> (2 * lg), a1 = (a >> lg) & (M - 1), a2 = a & (M - 1);
-    const long long gp = ((long long)(J0 + (a0 << Lt)) * n + (J1 + (a1 << Lt))) * n + (J2 + g + (a2 << Lt));
-    buf[g * S::node + base_idx<M>(a0, a1, a2)] = IO<TI, R>::ld(in, gp);
+#pragma unroll
+  for (int c = 0; c < kLd; ++c) {
+    const int t = threadIdx.x + c * 256;
+    if (t < G * M3) {
+      const int g = t % G, a = t / G;
+      buf[g * S::node + base_idx<M>(a >> (2 * lg), (a >> lg) & (M - 1), a & (M - 1))] = ld[c];
+    }
   }
   __syncthreads();
   if (int(threadIdx.x) < G * norb) {
