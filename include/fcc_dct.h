@@ -33,6 +33,11 @@
  *     up at the caller's next synchronisation.
  *   - Every call returns a status and never throws.  A plan executes on one
  *     stream at a time (it owns scratch buffers).
+ *   - Debugging: with the environment variable FCC_POISON_SCRATCH set (and
+ *     not "0") when a plan or a batched call allocates scratch, the scratch
+ *     starts as all-ones bytes (NaN in FP32 and FP64) instead of unspecified
+ *     contents; results are unchanged unless a kernel reads scratch it did
+ *     not write.
  */
 #ifndef FCC_DCT_H
 #define FCC_DCT_H

@@ -1426,6 +1426,16 @@ fcc_status hip_fail(hipError_t e, const char* what, int line) {
     if (e_ != hipSuccess) return hip_fail(e_, #expr, __LINE__);   \
   } while (0)
 // Status of the launches just enqueued (stale errors are cleared on entry).
+// FCC_POISON_SCRATCH set and not "0" (a debugging aid): freshly allocated
+// scratch is filled with all-ones bytes, a NaN in FP32 and in FP64, so that a
+// kernel reading scratch before writing it shows in the results.
+void poison_scratch(void* ptr, size_t bytes) {
+  const char* v = std::getenv("FCC_POISON_SCRATCH");
+  if (v && *v && *v != '0' && ptr && bytes) {
+    (void)hipMemset(ptr, 0xff, bytes);
+    (void)hipDeviceSynchronize();  // done before any stream of the caller can use the buffer
+  }
+}
 fcc_status launch_status(const char* what) {
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? FCC_OK : hip_fail(e, what, 0);
@@ -2855,6 +2865,7 @@ fcc_status prepare_group(std::vector<void*>* allocs, const BatchGroup& g, const 
     r->wb = N * (p->stages64 ? sizeof(double2) : sizeof(float2));
     if (hipMalloc(&r->ws, r->wb * 2 * r->chunk) != hipSuccess) return FCC_ERR_OOM;
     allocs->push_back(r->ws);
+    poison_scratch(r->ws, r->wb * 2 * r->chunk);
   }
   std::vector<void*> ptr(size_t(4) * cnt, nullptr);
   for (int v = 0; v < cnt; ++v) {
@@ -2870,6 +2881,7 @@ fcc_status prepare_group(std::vector<void*>* allocs, const BatchGroup& g, const 
     const size_t b = std::max(dense_ws_bytes(p->dfwd, cnt), dense_ws_bytes(p->dinv, cnt));
     if (hipMalloc(&r->aws, b) != hipSuccess) return FCC_ERR_OOM;
     allocs->push_back(r->aws);
+    poison_scratch(r->aws, b);
   }
   if (p->dense && cnt > 1)
     for (int l = 0; l < 2; ++l) {
@@ -3199,6 +3211,7 @@ fcc_status fold_upload(fcc_plan_s* p, const fcc::FoldTables& t) {
   if (e == hipSuccess) {
     p->ws_bytes = size_t(n) * n * n * sizeof(C);
     e = hipMalloc(&p->ws[0], p->ws_bytes);
+    if (e == hipSuccess) poison_scratch(p->ws[0], p->ws_bytes);
   }
   return e == hipSuccess ? FCC_OK : hip_fail(e, "fold tables", __LINE__);
 }
@@ -3490,6 +3503,7 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
     for (int b = 0; b < 2 && s == FCC_OK; ++b) {
       hipError_t e = hipMalloc(&p->ws[b], p->ws_bytes);
       if (e != hipSuccess) s = hip_fail(e, "hipMalloc(scratch)", __LINE__);
+      else poison_scratch(p->ws[b], p->ws_bytes);
     }
   }
   if (s == FCC_OK && (flags & FCC_HERMITIAN_PACKED)) {
@@ -3545,6 +3559,8 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
         if (e == hipSuccess) e = hipMemcpy(p->hslot, slot.data(), sizeof(int) * size_t(N), hipMemcpyHostToDevice);
         if (e == hipSuccess)
           e = hipMalloc(&p->hfull, size_t(N) * (prec == FCC_PREC_FP64 ? sizeof(double2) : sizeof(float2)));
+        if (e == hipSuccess)
+          poison_scratch(p->hfull, size_t(N) * (prec == FCC_PREC_FP64 ? sizeof(double2) : sizeof(float2)));
         if (e != hipSuccess) s = hip_fail(e, "hermitian packing tables", __LINE__);
       }
     }
@@ -3559,6 +3575,7 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
     if (s == FCC_OK &&
         hipMalloc(&p->dws, std::max(dense_ws_bytes(p->dfwd, 1), dense_ws_bytes(p->dinv, 1))) != hipSuccess)
       s = FCC_ERR_OOM;
+    if (s == FCC_OK) poison_scratch(p->dws, std::max(dense_ws_bytes(p->dfwd, 1), dense_ws_bytes(p->dinv, 1)));
     p->rows_cap = 1;
   }
   if (s != FCC_OK) {
