@@ -305,7 +305,11 @@ fcc_status fcc_dct_get_tuning(fcc_plan_t plan, fcc_tuning* out);
  * launch), each candidate timed `reps` times on synthetic data
  * with HIP events on `hip_stream`.  The winner is written to *best (may be
  * NULL) and remembered for the process: later fcc_dct_plan calls for the same
- * (device, n, prec, flags) use it.  Without a search, fcc_dct_plan uses
+ * (device, n, prec, flags) use it.  With the environment variable
+ * FCC_AUTOTUNE_CACHE naming a file, the winner is also appended to that file
+ * (one text line, tagged with the device's architecture), and each process
+ * reads the file at its first plan on a device, so searches persist across
+ * processes (later lines win; unreadable or malformed lines are skipped).  Without a search, fcc_dct_plan uses
  * built-in defaults.  Allocates and frees its own buffers and synchronises
  * `hip_stream`.  Errors: those of fcc_dct_plan, FCC_ERR_INVALID_ARG for
  * reps < 1. */

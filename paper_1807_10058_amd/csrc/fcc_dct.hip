@@ -3173,6 +3173,71 @@ std::map<std::array<int, 4>, fcc_tuning>& tuned() {
   static std::map<std::array<int, 4>, fcc_tuning> t;
   return t;
 }
+// Persistence (FCC_AUTOTUNE_CACHE=path): one text line per search,
+//   fccdct-schedule 1 <arch> <n> <prec> <flags> <tail x2> <tile x12> <map x20>,
+// appended by fcc_dct_autotune and read, for the device's architecture, at the
+// first plan of each device in a process (later lines win).  Call with
+// tuned_mu() held.
+std::string device_arch(int dev) {
+  hipDeviceProp_t pr{};
+  if (hipGetDeviceProperties(&pr, dev) != hipSuccess) return "unknown";
+  std::string a(pr.gcnArchName);
+  const size_t colon = a.find(':');
+  return colon == std::string::npos ? a : a.substr(0, colon);
+}
+void save_schedule(int dev, int n, int prec, unsigned flags, const fcc_tuning& t) {
+  const char* path = std::getenv("FCC_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "fccdct-schedule 1 %s %d %d %u %d %d", device_arch(dev).c_str(), n, prec, flags, t.tail_levels[0],
+               t.tail_levels[1]);
+  for (int d = 0; d < 2; ++d)
+    for (int L = 0; L < 2; ++L)
+      for (int a = 0; a < 3; ++a) std::fprintf(f, " %d", t.tile[d][L][a]);
+  for (int d = 0; d < 2; ++d)
+    for (int L = 0; L < 10; ++L) std::fprintf(f, " %u", t.map[d][L]);
+  std::fprintf(f, "\n");
+  std::fclose(f);
+}
+void load_schedules(int dev) {
+  static std::vector<int> loaded;
+  if (std::find(loaded.begin(), loaded.end(), dev) != loaded.end()) return;
+  loaded.push_back(dev);
+  const char* path = std::getenv("FCC_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  const std::string arch = device_arch(dev);
+  char line[1024];
+  while (std::fgets(line, sizeof line, f)) {
+    char tag[32], ar[64];
+    int ver = 0, n = 0, prec = 0, used = 0;
+    unsigned flags = 0;
+    fcc_tuning t{};
+    if (std::sscanf(line, "%31s %d %63s %d %d %u %d %d%n", tag, &ver, ar, &n, &prec, &flags, &t.tail_levels[0],
+                    &t.tail_levels[1], &used) != 8 ||
+        std::string(tag) != "fccdct-schedule" || ver != 1 || arch != ar)
+      continue;
+    const char* c = line + used;
+    bool ok = true;
+    for (int d = 0; d < 2 && ok; ++d)
+      for (int L = 0; L < 2 && ok; ++L)
+        for (int a = 0; a < 3 && ok; ++a) {
+          int k = 0;
+          ok = std::sscanf(c, "%d%n", &t.tile[d][L][a], &k) == 1;
+          c += k;
+        }
+    for (int d = 0; d < 2 && ok; ++d)
+      for (int L = 0; L < 10 && ok; ++L) {
+        int k = 0;
+        ok = std::sscanf(c, "%u%n", &t.map[d][L], &k) == 1;
+        c += k;
+      }
+    if (ok && valid_tuning(t)) tuned()[{dev, n, prec, int(flags)}] = t;
+  }
+  std::fclose(f);
+}
 }  // namespace
 
 extern "C" {
@@ -3362,6 +3427,7 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
     fcc_tuning t = default_tuning(n);
     {
       std::lock_guard<std::mutex> lock(tuned_mu());
+      load_schedules(p->device);
       auto it = tuned().find({p->device, n, int(prec), int(flags)});
       if (it != tuned().end()) t = it->second, searched = true;
     }
@@ -3971,7 +4037,9 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
   fcc_tuning t = p->tune;
   if (s == FCC_OK) {
     std::lock_guard<std::mutex> lock(tuned_mu());
+    load_schedules(p->device);
     tuned()[{p->device, n, int(prec), int(flags)}] = t;
+    save_schedule(p->device, n, int(prec), flags, t);
     if (best) *best = t;
   }
   fcc_dct_destroy(p);
