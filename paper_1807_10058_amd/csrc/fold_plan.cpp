@@ -9,7 +9,6 @@
 #include <array>
 #include <cmath>
 #include <map>
-#include <mutex>
 #include <thread>
 #include <unordered_map>
 
@@ -66,8 +65,6 @@ struct Builder {
   int n, lg;
   int r8[3];
   cd Ttab[7][7][7];  // T_r(rst) for r in [-3, 3]^3
-  std::mutex mu;
-  std::unordered_map<Key, int, KeyHash> sig;
   std::map<std::vector<long long>, int> rows;
   std::vector<cd> K;
   fcc_status err = FCC_OK;
@@ -254,9 +251,17 @@ fcc_status fold_tables(int n, const int r8[3], FoldTables* out, bool orbits) {
   } catch (const std::bad_alloc&) {
     return FCC_ERR_OOM;
   }
+  // Deterministic in three passes: (1) in parallel, each point's wrap
+  // signature, numbered per thread (pid holds the thread-local number for now)
+  // with the thread's first point of every signature; (2) serially, every
+  // signature solved once from its first point overall, signatures taken in
+  // order of that point, so row numbers and values do not depend on thread
+  // timing; (3) pid renumbered.
   const int nt = int(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
   const int workers = N < 32768 ? 1 : nt;
-  auto work = [&](long long lo, long long hi) {
+  std::vector<std::vector<std::pair<Key, long long>>> firsts(workers);  // per thread: (signature, first point)
+  std::vector<fcc_status> werr(workers, FCC_OK);
+  auto work = [&](int t, long long lo, long long hi) {
     std::unordered_map<Key, int, KeyHash> local;
     for (long long f = lo; f < hi; ++f) {
       const long long k[3] = {f >> (2 * b.lg), (f >> b.lg) & (n - 1), f & (n - 1)};
@@ -266,17 +271,15 @@ fcc_status fold_tables(int n, const int r8[3], FoldTables* out, bool orbits) {
       if (it != local.end()) {
         id = it->second;
       } else {
-        std::lock_guard<std::mutex> lk(b.mu);
-        auto g = b.sig.find(key);
-        if (g != b.sig.end()) {
-          id = g->second;
-        } else {
-          id = b.solve(k);
-          b.sig.emplace(key, id);
+        id = int(local.size());
+        if (id > 255) {
+          werr[t] = FCC_ERR_UNSUPPORTED;
+          return;
         }
         local.emplace(key, id);
+        firsts[t].push_back({key, f});
       }
-      out->pid[size_t(f)] = uint8_t(id < 0 ? 0 : id);
+      out->pid[size_t(f)] = uint8_t(id);
       if (orbits) {
         long long fl[24][3], flat[24];
         b.orbit(k, fl, flat);
@@ -287,7 +290,34 @@ fcc_status fold_tables(int n, const int r8[3], FoldTables* out, bool orbits) {
     }
   };
   std::vector<std::thread> th;
-  for (int t = 0; t < workers; ++t) th.emplace_back(work, N * t / workers, N * (t + 1) / workers);
+  for (int t = 0; t < workers; ++t) th.emplace_back(work, t, N * t / workers, N * (t + 1) / workers);
+  for (auto& t : th) t.join();
+  for (fcc_status e : werr)
+    if (e != FCC_OK) return e;
+  // ranges are in increasing order, so a signature's first point overall is
+  // its first point in the lowest thread that meets it
+  std::unordered_map<Key, long long, KeyHash> first_all;
+  for (int t = 0; t < workers; ++t)
+    for (const auto& kf : firsts[t]) first_all.emplace(kf.first, kf.second);
+  std::vector<std::pair<long long, Key>> order;
+  for (const auto& kv : first_all) order.push_back({kv.second, kv.first});
+  std::sort(order.begin(), order.end(), [](const auto& a, const auto& c) { return a.first < c.first; });
+  std::unordered_map<Key, int, KeyHash> row_of;
+  for (const auto& fk : order) {
+    const long long f = fk.first;
+    const long long k[3] = {f >> (2 * b.lg), (f >> b.lg) & (n - 1), f & (n - 1)};
+    const int id = b.solve(k);
+    if (id < 0) return b.err;
+    row_of.emplace(fk.second, id);
+  }
+  std::vector<std::vector<uint8_t>> remap(workers);
+  for (int t = 0; t < workers; ++t)
+    for (const auto& kf : firsts[t]) remap[t].push_back(uint8_t(row_of.at(kf.first)));
+  auto renumber = [&](int t, long long lo, long long hi) {
+    for (long long f = lo; f < hi; ++f) out->pid[size_t(f)] = remap[t][out->pid[size_t(f)]];
+  };
+  th.clear();
+  for (int t = 0; t < workers; ++t) th.emplace_back(renumber, t, N * t / workers, N * (t + 1) / workers);
   for (auto& t : th) t.join();
   if (b.err != FCC_OK) return b.err;
   out->K = std::move(b.K);

@@ -51,3 +51,13 @@ def test_singular_skews_refused(rst):
 def test_skew_without_eighths_refused():
     with pytest.raises(fcc.FccError, match="UNSUPPORTED"):
         fcc.fcc_fold_unfold_tables(8, (0.31, 0.07, 0.23))
+
+
+def test_tables_are_deterministic():
+    """n = 32 and 64 build their tables on several host threads; the row
+    numbering and values must not depend on thread timing."""
+    for n in (32, 64):
+        ref = fcc.fcc_fold_unfold_tables(n)
+        for _ in range(3):
+            pid, K = fcc.fcc_fold_unfold_tables(n)
+            assert np.array_equal(pid, ref[0]) and np.array_equal(K, ref[1])
