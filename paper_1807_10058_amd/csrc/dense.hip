@@ -367,7 +367,7 @@ fcc_status upload_split(const std::vector<double>& W, int K, int Nc, bool fp16, 
       lo[size_t(r) * op->Kp + c] = l;
     }
   const size_t bytes = hi.size() * sizeof(uint16_t);
-  if (hipMalloc(&op->w_hi, bytes) != hipSuccess || hipMalloc(&op->w_lo, bytes) != hipSuccess) return FCC_ERR_OOM;
+  if (dev_malloc(&op->w_hi, bytes) != hipSuccess || dev_malloc(&op->w_lo, bytes) != hipSuccess) return FCC_ERR_OOM;
   if (hipMemcpy(op->w_hi, hi.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(op->w_lo, lo.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
     return FCC_ERR_HIP;
@@ -411,12 +411,12 @@ fcc_status dense_prepare(fcc_plan_s* p, hipStream_t st) {
     if (scratch) (void)hipFree(scratch);
     return e;
   };
-  if (hipMalloc(&F, sizeof(double2) * N * N) != hipSuccess) return fail(FCC_ERR_OOM);
+  if (dev_malloc(&F, sizeof(double2) * N * N) != hipSuccess) return fail(FCC_ERR_OOM);
   hipLaunchKernelGGL(k_dense_matrix, dim3(unsigned((N * N + 255) / 256)), dim3(256), 0, st, F, n, p->rst[0],
                      p->rst[1], p->rst[2], G);
   if (hipGetLastError() != hipSuccess) return fail(FCC_ERR_HIP);
   // inverse matrix: FP64 fast inverse of the unit vectors (column j of F^{-1})
-  if (hipMalloc(&Finv, sizeof(double2) * N * N) != hipSuccess) return fail(FCC_ERR_OOM);
+  if (dev_malloc(&Finv, sizeof(double2) * N * N) != hipSuccess) return fail(FCC_ERR_OOM);
   if (n == 1) {
     const double2 one = make_double2(1.0, 0.0);
     if (hipMemcpy(Finv, &one, sizeof one, hipMemcpyHostToDevice) != hipSuccess) return fail(FCC_ERR_HIP);
@@ -436,8 +436,8 @@ fcc_status dense_prepare(fcc_plan_s* p, hipStream_t st) {
     sub.tail_Lt[1] = p->tail_Lt[1];
     sub.tlv = p->tlv;
     // all N unit vectors in one launch sequence; pointer arrays on the device
-    if (hipMalloc(&E, sizeof(double2) * N * N) != hipSuccess) return fail(FCC_ERR_OOM);
-    if (hipMalloc(&scratch, sizeof(double2) * N * N * 2) != hipSuccess) return fail(FCC_ERR_OOM);
+    if (dev_malloc(&E, sizeof(double2) * N * N) != hipSuccess) return fail(FCC_ERR_OOM);
+    if (dev_malloc(&scratch, sizeof(double2) * N * N * 2) != hipSuccess) return fail(FCC_ERR_OOM);
     hipLaunchKernelGGL(k_unit_vectors, dim3(unsigned((N * N + 255) / 256)), dim3(256), 0, st, E, N, 0LL, int(N));
     std::vector<void*> ptr(size_t(4) * N);
     for (long long v = 0; v < N; ++v) {
@@ -446,7 +446,7 @@ fcc_status dense_prepare(fcc_plan_s* p, hipStream_t st) {
       ptr[2 * N + v] = scratch + N * (2 * v);
       ptr[3 * N + v] = scratch + N * (2 * v + 1);
     }
-    if (hipMalloc(&parr, sizeof(void*) * ptr.size()) != hipSuccess) return fail(FCC_ERR_OOM);
+    if (dev_malloc(&parr, sizeof(void*) * ptr.size()) != hipSuccess) return fail(FCC_ERR_OOM);
     if (hipMemcpy(parr, ptr.data(), sizeof(void*) * ptr.size(), hipMemcpyHostToDevice) != hipSuccess)
       return fail(FCC_ERR_HIP);
     s = enqueue_inverse_arrays(&sub, int(N), parr, parr + N, parr + 2 * N, parr + 3 * N, st);

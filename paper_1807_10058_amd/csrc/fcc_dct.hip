@@ -1425,7 +1425,24 @@ fcc_status hip_fail(hipError_t e, const char* what, int line) {
     hipError_t e_ = (expr);                                       \
     if (e_ != hipSuccess) return hip_fail(e_, #expr, __LINE__);   \
   } while (0)
-// Status of the launches just enqueued (stale errors are cleared on entry).
+}  // namespace
+hipError_t fcc::dev_malloc_raw(void** p, size_t bytes) {
+  static std::mutex mu;
+  static std::string armed;
+  static long long count = 0;
+  const char* v = std::getenv("FCC_FAIL_ALLOC_AT");
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    const std::string now = v ? v : "";
+    if (now != armed) armed = now, count = 0;
+    if (!armed.empty() && ++count == std::atoll(armed.c_str())) {
+      *p = nullptr;
+      return hipErrorOutOfMemory;
+    }
+  }
+  return hipMalloc(p, bytes);
+}
+namespace {
 // FCC_POISON_SCRATCH set and not "0" (a debugging aid): freshly allocated
 // scratch is filled with all-ones bytes, a NaN in FP32 and in FP64, so that a
 // kernel reading scratch before writing it shows in the results.
@@ -1436,6 +1453,7 @@ void poison_scratch(void* ptr, size_t bytes) {
     (void)hipDeviceSynchronize();  // done before any stream of the caller can use the buffer
   }
 }
+// Status of the launches just enqueued (stale errors are cleared on entry).
 fcc_status launch_status(const char* what) {
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? FCC_OK : hip_fail(e, what, 0);
@@ -1447,7 +1465,7 @@ template <typename T>
 fcc_status upload(const std::vector<T>& v, const T** out, std::vector<void*>* own = nullptr) {
   void* p = nullptr;
   size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
-  HIPCHK(hipMalloc(&p, bytes));
+  HIPCHK(dev_malloc(&p, bytes));
   if (!v.empty()) {
     hipError_t e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -2863,7 +2881,7 @@ fcc_status prepare_group(std::vector<void*>* allocs, const BatchGroup& g, const 
   if (scratch) {
     const size_t N = size_t(p->n) * p->n * p->n;
     r->wb = N * (p->stages64 ? sizeof(double2) : sizeof(float2));
-    if (hipMalloc(&r->ws, r->wb * 2 * r->chunk) != hipSuccess) return FCC_ERR_OOM;
+    if (dev_malloc(&r->ws, r->wb * 2 * r->chunk) != hipSuccess) return FCC_ERR_OOM;
     allocs->push_back(r->ws);
     poison_scratch(r->ws, r->wb * 2 * r->chunk);
   }
@@ -2879,7 +2897,7 @@ fcc_status prepare_group(std::vector<void*>* allocs, const BatchGroup& g, const 
   }
   if (p->dense) {
     const size_t b = std::max(dense_ws_bytes(p->dfwd, cnt), dense_ws_bytes(p->dinv, cnt));
-    if (hipMalloc(&r->aws, b) != hipSuccess) return FCC_ERR_OOM;
+    if (dev_malloc(&r->aws, b) != hipSuccess) return FCC_ERR_OOM;
     allocs->push_back(r->aws);
     poison_scratch(r->aws, b);
   }
@@ -2895,7 +2913,7 @@ fcc_status prepare_group(std::vector<void*>* allocs, const BatchGroup& g, const 
       }
     }
   void* d = nullptr;
-  if (hipMalloc(&d, sizeof(void*) * ptr.size() + sizeof(float) * cnt) != hipSuccess) return FCC_ERR_OOM;
+  if (dev_malloc(&d, sizeof(void*) * ptr.size() + sizeof(float) * cnt) != hipSuccess) return FCC_ERR_OOM;
   allocs->push_back(d);
   r->rows = static_cast<void**>(d);
   r->scale = reinterpret_cast<float*>(r->rows + ptr.size());
@@ -3264,18 +3282,18 @@ fcc_status fold_upload(fcc_plan_s* p, const fcc::FoldTables& t) {
   }
   const double inv = 1.0 / (double(n) * n * n);
   for (size_t i = 0; i < t.K.size(); ++i) k[i] = {decltype(C{}.x)(t.K[i].real() * inv), decltype(C{}.x)(t.K[i].imag() * inv)};
-  hipError_t e = hipMalloc(&p->fw8n, w.size() * sizeof(C));
+  hipError_t e = dev_malloc(&p->fw8n, w.size() * sizeof(C));
   if (e == hipSuccess) e = hipMemcpy(p->fw8n, w.data(), w.size() * sizeof(C), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMalloc(&p->fkt, k.size() * sizeof(C));
+  if (e == hipSuccess) e = dev_malloc(&p->fkt, k.size() * sizeof(C));
   if (e == hipSuccess) e = hipMemcpy(p->fkt, k.data(), k.size() * sizeof(C), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->fpid), t.prid.size());
+  if (e == hipSuccess) e = dev_malloc(reinterpret_cast<void**>(&p->fpid), t.prid.size());
   if (e == hipSuccess) e = hipMemcpy(p->fpid, t.prid.data(), t.prid.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMalloc(&p->freps, t.reps.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = dev_malloc(&p->freps, t.reps.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemcpy(p->freps, t.reps.data(), t.reps.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   p->fnrep = int(t.reps.size());
   if (e == hipSuccess) {
     p->ws_bytes = size_t(n) * n * n * sizeof(C);
-    e = hipMalloc(&p->ws[0], p->ws_bytes);
+    e = dev_malloc(&p->ws[0], p->ws_bytes);
     if (e == hipSuccess) poison_scratch(p->ws[0], p->ws_bytes);
   }
   return e == hipSuccess ? FCC_OK : hip_fail(e, "fold tables", __LINE__);
@@ -3321,7 +3339,7 @@ fcc_status base_prepare(fcc_plan_s* p, const double r[3], bool default_schedule)
     for (const auto& o : orb) reps.push_back(o.second), reps.push_back(o.first);
     p->brep_cnt[m] = int(orb.size());
   }
-  hipError_t e = hipMalloc(&p->breps, reps.size() * sizeof(int));
+  hipError_t e = dev_malloc(&p->breps, reps.size() * sizeof(int));
   if (e == hipSuccess) e = hipMemcpy(p->breps, reps.data(), reps.size() * sizeof(int), hipMemcpyHostToDevice);
   return e == hipSuccess ? FCC_OK : hip_fail(e, "base orbit table", __LINE__);
 }
@@ -3512,8 +3530,8 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
   }
   if (s == FCC_OK && p->D > 0) {
     size_t cnt = 3 * ((size_t(1) << p->D) - 1);
-    hipError_t e = hipMalloc(&p->hph, cnt * sizeof(double2));
-    if (e != hipSuccess) s = hip_fail(e, "hipMalloc(phase table)", __LINE__);
+    hipError_t e = dev_malloc(&p->hph, cnt * sizeof(double2));
+    if (e != hipSuccess) s = hip_fail(e, "device allocation (phase table)", __LINE__);
     if (s == FCC_OK) {
       hipLaunchKernelGGL(k_phase_table, dim3(unsigned((cnt + 255) / 256)), dim3(256), 0, st, p->hph, p->D, r[0], r[1],
                          r[2]);
@@ -3533,8 +3551,8 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
         total += 1LL << (3 * L);
       }
     }
-    hipError_t e = total > 0 ? hipMalloc(&p->nodes, sizeof(NodeConst) * total) : hipSuccess;
-    if (e != hipSuccess) s = hip_fail(e, "hipMalloc(node table)", __LINE__);
+    hipError_t e = total > 0 ? dev_malloc(&p->nodes, sizeof(NodeConst) * total) : hipSuccess;
+    if (e != hipSuccess) s = hip_fail(e, "device allocation (node table)", __LINE__);
     for (int L = 0; s == FCC_OK && L < p->D; ++L)
       if (p->node_off[L] >= 0) {
         const long long cnt = 1LL << (3 * L);
@@ -3553,8 +3571,8 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
         total += 1LL << (3 * L);
       }
     }
-    hipError_t e = total > 0 ? hipMalloc(&p->onodes, sizeof(OrbitNode) * total) : hipSuccess;
-    if (e != hipSuccess) s = hip_fail(e, "hipMalloc(orbit node table)", __LINE__);
+    hipError_t e = total > 0 ? dev_malloc(&p->onodes, sizeof(OrbitNode) * total) : hipSuccess;
+    if (e != hipSuccess) s = hip_fail(e, "device allocation (orbit node table)", __LINE__);
     for (int L = 0; s == FCC_OK && L < p->D; ++L)
       if (p->onode_off[L] >= 0) {
         const long long cnt = 1LL << (3 * L);
@@ -3567,8 +3585,8 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
     size_t N = size_t(n) * n * n;
     p->ws_bytes = N * (p->stages64 ? sizeof(double2) : sizeof(float2));
     for (int b = 0; b < 2 && s == FCC_OK; ++b) {
-      hipError_t e = hipMalloc(&p->ws[b], p->ws_bytes);
-      if (e != hipSuccess) s = hip_fail(e, "hipMalloc(scratch)", __LINE__);
+      hipError_t e = dev_malloc(&p->ws[b], p->ws_bytes);
+      if (e != hipSuccess) s = hip_fail(e, "device allocation (scratch)", __LINE__);
       else poison_scratch(p->ws[b], p->ws_bytes);
     }
   }
@@ -3621,10 +3639,10 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
           if (j > q) slot[size_t(j)] = -slot[size_t(q)] - 1;
         }
         p->hpacked = k;
-        hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->hslot), sizeof(int) * size_t(N));
+        hipError_t e = dev_malloc(reinterpret_cast<void**>(&p->hslot), sizeof(int) * size_t(N));
         if (e == hipSuccess) e = hipMemcpy(p->hslot, slot.data(), sizeof(int) * size_t(N), hipMemcpyHostToDevice);
         if (e == hipSuccess)
-          e = hipMalloc(&p->hfull, size_t(N) * (prec == FCC_PREC_FP64 ? sizeof(double2) : sizeof(float2)));
+          e = dev_malloc(&p->hfull, size_t(N) * (prec == FCC_PREC_FP64 ? sizeof(double2) : sizeof(float2)));
         if (e == hipSuccess)
           poison_scratch(p->hfull, size_t(N) * (prec == FCC_PREC_FP64 ? sizeof(double2) : sizeof(float2)));
         if (e != hipSuccess) s = hip_fail(e, "hermitian packing tables", __LINE__);
@@ -3637,9 +3655,9 @@ fcc_status fcc_dct_plan_tuned(fcc_plan_t* plan, int n, const double rst[3], fcc_
   }
   if (s == FCC_OK && p->dense) {
     s = dense_prepare(p, st);
-    if (s == FCC_OK && hipMalloc(&p->rowscale, sizeof(float)) != hipSuccess) s = FCC_ERR_OOM;
+    if (s == FCC_OK && dev_malloc(&p->rowscale, sizeof(float)) != hipSuccess) s = FCC_ERR_OOM;
     if (s == FCC_OK &&
-        hipMalloc(&p->dws, std::max(dense_ws_bytes(p->dfwd, 1), dense_ws_bytes(p->dinv, 1))) != hipSuccess)
+        dev_malloc(&p->dws, std::max(dense_ws_bytes(p->dfwd, 1), dense_ws_bytes(p->dinv, 1))) != hipSuccess)
       s = FCC_ERR_OOM;
     if (s == FCC_OK) poison_scratch(p->dws, std::max(dense_ws_bytes(p->dfwd, 1), dense_ws_bytes(p->dinv, 1)));
     p->rows_cap = 1;
@@ -3849,9 +3867,9 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
     const size_t el = (p->prec == FCC_PREC_FP64) ? sizeof(double) : sizeof(float);
     void* a = nullptr;
     void* b = nullptr;
-    hipError_t e = hipMalloc(&a, 2 * el * N);
-    if (e == hipSuccess) e = hipMalloc(&b, 2 * el * N);
-    if (e != hipSuccess) s = hip_fail(e, "hipMalloc(autotune operands)", __LINE__);
+    hipError_t e = dev_malloc(&a, 2 * el * N);
+    if (e == hipSuccess) e = dev_malloc(&b, 2 * el * N);
+    if (e != hipSuccess) s = hip_fail(e, "device allocation (autotune operands)", __LINE__);
     if (s == FCC_OK) {
       const unsigned blocks = unsigned(std::min<long long>((2 * N + 255) / 256, 65535));
       if (el == sizeof(double)) {
@@ -4053,8 +4071,8 @@ fcc_status fcc_dct_roundtrip_residual(fcc_plan_t p, const void* x, const void* y
   (void)hipGetLastError();
   const long long N = (long long)p->n * p->n * p->n;
   if (!p->resid) {
-    hipError_t ea = hipMalloc(reinterpret_cast<void**>(&p->resid), 2 * sizeof(unsigned long long));
-    if (ea != hipSuccess) return hip_fail(ea, "hipMalloc(residual)", __LINE__);
+    hipError_t ea = dev_malloc(reinterpret_cast<void**>(&p->resid), 2 * sizeof(unsigned long long));
+    if (ea != hipSuccess) return hip_fail(ea, "device allocation (residual)", __LINE__);
   }
   unsigned long long* d = p->resid;
   hipError_t e = hipSuccess;

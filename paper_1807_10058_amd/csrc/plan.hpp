@@ -63,6 +63,14 @@ struct fcc_plan_s {
 };
 
 namespace fcc {
+// Every device allocation of the library.  FCC_FAIL_ALLOC_AT=k (testing the
+// error paths) makes the k-th allocation counted since the variable last
+// changed fail as if the device were out of memory.
+hipError_t dev_malloc_raw(void** p, size_t bytes);
+template <typename T>
+hipError_t dev_malloc(T** p, size_t bytes) {
+  return dev_malloc_raw(reinterpret_cast<void**>(p), bytes);
+}
 // dense.hip
 fcc_status dense_prepare(fcc_plan_s* p, hipStream_t st);
 // in_base / out_base rows are lda / ldc floats apart (0: the operator's row
