@@ -37,7 +37,10 @@
  *     not "0") when a plan or a batched call allocates scratch, the scratch
  *     starts as all-ones bytes (NaN in FP32 and FP64) instead of unspecified
  *     contents; results are unchanged unless a kernel reads scratch it did
- *     not write.
+ *     not write.  FCC_FAIL_ALLOC_AT=k makes the k-th device allocation of the
+ *     library (counted from when the variable last changed) fail as out of
+ *     memory, for testing the error paths: the call returns FCC_ERR_OOM and
+ *     frees what it had allocated.
  */
 #ifndef FCC_DCT_H
 #define FCC_DCT_H
