@@ -141,3 +141,37 @@ def test_bad_combinations():
         _plan(16, fcc.FCC_PREC_FP64, 0, 2)  # tail_levels[0] = 1
     with pytest.raises(fcc.FccError):
         _plan(16, fcc.FCC_PREC_FP64, 0, 16)  # M = n
+
+
+def test_with_static_scratch_and_packed_output():
+    """The allocation-free forward and the Hermitian-packed output take the
+    base like the plain forward."""
+    n = 32
+    x = RNG.standard_normal(n ** 3).astype(np.float32)
+    plan = _plan(n, fcc.FCC_PREC_FP32, fcc.FCC_REAL_INPUT)
+    xt, X = _forward(plan, x, fcc.FCC_PREC_FP32)
+    Xs = torch.empty_like(X)
+    fcc.fcc_dct_forward_static(plan, xt, Xs)
+    torch.cuda.synchronize()
+    assert torch.equal(X, Xs)
+    packed = _plan(n, fcc.FCC_PREC_FP32, fcc.FCC_REAL_INPUT | fcc.FCC_HERMITIAN_PACKED)
+    Xp = torch.empty(fcc.fcc_dct_packed_size(packed), dtype=torch.complex64, device=gu.DEV)
+    fcc.fcc_dct_forward(packed, xt, Xp)
+    y = torch.empty_like(xt)
+    fcc.fcc_dct_inverse(packed, Xp, y)
+    torch.cuda.synchronize()
+    assert fcc.fcc_dct_roundtrip_residual(packed, xt, y) <= 1e-5
+
+
+def test_autotune_keeps_the_base():
+    """The search takes the base's node size from 4, 8 or 16 and the plans
+    after it use the winner."""
+    n = 32
+    best = fcc.fcc_dct_autotune(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT | BASE, reps=1)
+    assert 2 <= best["tail_levels"][0] <= 4
+    plan = fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT | BASE)
+    assert fcc.fcc_dct_get_tuning(plan)["tail_levels"][0] == best["tail_levels"][0]
+    assert fcc.fcc_dct_describe_launches(plan, 1)[-1]["name"].startswith("k_fwd_base")
+    x = RNG.standard_normal(n ** 3).astype(np.float32)
+    _, X = _forward(plan, x, fcc.FCC_PREC_FP32)
+    assert gu.maxrel(X.cpu().numpy(), fold_ref.fold_forward(x.astype(np.float64), n)) <= 1e-5
