@@ -126,7 +126,7 @@ enum {
  *   n     : size parameter, a power of two in [1, 1024] (fast algorithm, Sec. IV-B).
  *           Levels with node size above 256 run as orbit-block launches
  *           (the per-row gather tables pack node-local coordinates in 8
- *           bits); the default schedule has them at every node size >= 32.
+ *           bits); the default schedule has them at every node size >= 16.
  *   rst   : host pointer to the skew (r,s,t), or NULL for (1/8, 0, 3/8).
  *   prec  : data/compute precision (fcc_precision).  The split-MFMA precisions
  *           apply the dense transform matrix and need n <= 8.
@@ -266,8 +266,9 @@ const char* fcc_status_string(fcc_status s);
  *                    FCC_MAP_BALANCE and changes no result bit.
  *                    FCC_MAP_ORBIT (node sizes n / 2^L >= 8) runs the
  *                    level as one launch over the orbits of W on the node's
- *                    cube grid: a block loads the sources of 16 orbits of one
- *                    kind once, forms their rows from the kind's template (the
+ *                    cube grid: a block loads the sources of 1 to 64 orbits
+ *                    of one kind (fewer the more cubes an orbit has) once,
+ *                    forms their rows from the kind's template (the
  *                    basis change is block diagonal over the orbits) and
  *                    applies DCT_2 (x) I (inverse: DCT_2^{-1} (x) I, then C)
  *                    before storing; no per-row table is read.  It takes

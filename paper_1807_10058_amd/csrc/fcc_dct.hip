@@ -1714,7 +1714,7 @@ fcc_status device_orbit_level(int dev, int nl, DevOrbitLevel* out) {
   std::vector<uint32_t> ent;
   std::vector<int8_t> wmat;
   std::vector<uint32_t> reps;
-  std::vector<int4> chunks;
+  std::vector<int4> chunks[2];
   const auto& G = weyl_group();
   for (size_t t = 0; t < ob->templ.size(); ++t) {
     const OrbitTemplate& T = ob->templ[t];
@@ -1775,8 +1775,13 @@ fcc_status device_orbit_level(int dev, int nl, DevOrbitLevel* out) {
     }
     kinds.push_back(k);
     const std::vector<uint32_t>& r = ob->reps[t];
-    for (size_t r0 = 0; r0 < r.size(); r0 += kOrbitChunk)
-      chunks.push_back(make_int4(int(t), int(reps.size() + r0), int(std::min<size_t>(kOrbitChunk, r.size() - r0)), 0));
+    // one block's orbits per chunk: K = U (blocks of one node) or U / 8
+    const int lgU = orbit_lg_units(T.nc);
+    for (int gs = 0; gs < 2; ++gs) {
+      const size_t K = size_t(1) << (gs == 0 ? lgU : lgU - 3);
+      for (size_t r0 = 0; r0 < r.size(); r0 += K)
+        chunks[gs].push_back(make_int4(int(t), int(reps.size() + r0), int(std::min(K, r.size() - r0)), lgU));
+    }
     reps.insert(reps.end(), r.begin(), r.end());
   }
   DevOrbitLevel lv{};
@@ -1787,9 +1792,9 @@ fcc_status device_orbit_level(int dev, int nl, DevOrbitLevel* out) {
   if (s == FCC_OK) s = upload(ent, &lv.ent);
   if (s == FCC_OK) s = upload(wmat, &lv.wmat);
   if (s == FCC_OK) s = upload(reps, &lv.reps);
-  if (s == FCC_OK) s = upload(chunks, &lv.chunks);
+  for (int gs = 0; gs < 2 && s == FCC_OK; ++gs) s = upload(chunks[gs], &lv.chunks[gs]);
   if (s != FCC_OK) return s;
-  lv.nchunk = int(chunks.size());
+  for (int gs = 0; gs < 2; ++gs) lv.nchunk[gs] = int(chunks[gs].size());
   lv.lgm = 0;
   while ((1 << lv.lgm) < ob->m) ++lv.lgm;
   levels.emplace(key, lv);
@@ -2139,7 +2144,7 @@ std::vector<SlotDesc> describe_slots(const fcc_plan_s* p, int d) {
 
 // ---- orbit-block level launches -------------------------------------------
 dim3 orbit_grid(const fcc_plan_s* p, int L, int nvol) {
-  const long long total = orbit_blocks_total(p->olv[L].nchunk, L, nvol);
+  const long long total = orbit_blocks_total(p->olv[L].nchunk[L == 0 ? 0 : 1], L, nvol);
   return dim3(unsigned(((total + 7) >> 3) << 3));
 }
 const OrbitNode* onodes_of(const fcc_plan_s* p, int L) {
@@ -3145,8 +3150,9 @@ fcc_tuning default_tuning(int n) {
     t.tail_levels[d] = c.tail[d];
     for (int L = 0; L < 2; ++L)
       for (int a = 0; a < 3; ++a) t.tile[d][L][a] = c.tile[d][L][a];
-    // orbit-block launches for every level with node size >= 32
-    for (int L = 0; L < 10; ++L) t.map[d][L] = c.map[d][L] | ((n >> L) >= 32 ? unsigned(FCC_MAP_ORBIT) : 0u);
+    // orbit-block launches for every level with node size >= 16 (with blocks
+    // sized by the orbits' cube count they beat the row gathers there too)
+    for (int L = 0; L < 10; ++L) t.map[d][L] = c.map[d][L] | ((n >> L) >= 16 ? unsigned(FCC_MAP_ORBIT) : 0u);
   }
   return t;
 }

@@ -186,8 +186,11 @@ struct DevOrbitLevel {
   const uint32_t* ent;
   const int8_t* wmat;
   const uint32_t* reps;  // representatives p0 packed (x << 20) | (y << 10) | z
-  const int4* chunks;    // {kind, first representative, count <= 16, 0}
-  int nchunk;
+  // one block's orbits per chunk, {kind, first representative, count, log2 U}
+  // with U the units of a block of that kind; [0] for blocks of one node
+  // (level 0, K = U orbits), [1] for blocks of 8 nodes (K = U / 8)
+  const int4* chunks[2];
+  int nchunk[2];
   int lgm;               // log2 m
 };
 

@@ -13,11 +13,14 @@
 //             DCT_2(phi)^{-1} (per-cube solves), then form every output
 //             x(q' + m o) from the orbit's 8|O| cube values (C_nl's block).
 //
-// A block takes 8 "units" = K orbits of one kind x G nodes (G = 1 at level
+// A block takes U "units" = K orbits of one kind x G nodes (G = 1 at level
 // 0, 8 below; the nodes are consecutive in J, so for one source slot the
-// units of one orbit read consecutive addresses).  Their sources (or cube
-// values) sit in LDS as [slot][unit], slot = cube slot * 8 + o (or def).  The
-// rows are summed by wavefronts of 64 lanes = 8 cube slots x 8 units; a
+// units of one orbit read consecutive addresses); U grows as the kind's orbits
+// shrink (8 units for orbits of more than 12 cubes, 16 up to 12, 32 up to 6,
+// 64 up to 3), so that every block fills its 192 threads and its LDS whatever
+// the stabiliser of its orbits.  The sources (or cube values) sit in LDS as
+// [slot][unit], slot = cube slot * 8 + o (or def).  The rows are summed by
+// wavefronts of 64 lanes = 64 / U cube slots x U units; a
 // template row is split by monomial of the node's coefficient polynomials
 // into 5 segments of integer coefficients (the row's rational coefficients
 // times 144), and the cube slots are ordered so that the slots of a wavefront
@@ -33,19 +36,21 @@
 
 namespace fcc {
 
-constexpr int kOrbitUnits = 8;                      // units per block
-constexpr int kOrbitChunk = 16;                     // representatives per chunk
-constexpr int kOrbitThreads = 192;                  // 3 wavefronts: 24 cube slots x 8 units
+constexpr int kOrbitThreads = 192;                  // 3 wavefronts: cube slots x units, nc U <= 192
 constexpr int kOrbitMaxCubes = 24;
 constexpr int kOrbitMaxSlots = 8 * kOrbitMaxCubes;  // 192
+constexpr int kOrbitVal = 8 * kOrbitMaxSlots;       // LDS values: 8 nc U <= 1536
+constexpr int kOrbitMaxOrbits = 64;                 // orbits per block (level 0, U = 64)
 constexpr int kOrbitSeg = 8 * kNumMono;             // segments per cube slot
 constexpr int kOrbitMaxEnt = 2560;                  // entries of one kind's B (C) block
 constexpr int kOrbitMaxNodes = 8;
 
-// Blocks of an orbit launch: per chunk of 16 representatives and group of
-// G = min(8^L, 8) nodes, 16 / K blocks of K = 8 / G orbits.
+// Units of a block for orbits of nc cubes (8 nc U <= kOrbitVal).
+__host__ __device__ __forceinline__ int orbit_lg_units(int nc) { return nc > 12 ? 3 : (nc > 6 ? 4 : (nc > 3 ? 5 : 6)); }
+// Blocks of an orbit launch at level L: one per chunk (of the level's chunk
+// table) and group of G = min(8^L, 8) nodes.
 __host__ __device__ __forceinline__ long long orbit_blocks_total(int nchunk, int L, int nvol) {
-  return (long long)nchunk * 2 * (1LL << (3 * L)) * nvol;
+  return (long long)nchunk * (L == 0 ? 1LL : (1LL << (3 * (L - 1)))) * nvol;
 }
 
 // Logical block of an orbit launch: blocks i, i+8, i+16, ... run on one XCD,
@@ -66,19 +71,20 @@ __device__ __forceinline__ void orbit_cube(const int8_t* g, uint32_t pr, int mas
 // LDS state of a block.
 template <typename R>
 struct OrbitShared {
-  cx<R> val[kOrbitMaxSlots * kOrbitUnits];  // sources (forward) or cube values (inverse)
+  cx<R> val[kOrbitVal];  // sources (forward) or cube values (inverse), [slot][unit]
   alignas(16) cx<R> mono[kOrbitMaxNodes][kNumMono];  // monomials / 144, per node
   alignas(16) uint32_t ent[kOrbitMaxEnt];
   alignas(16) uint16_t seg[kOrbitMaxCubes * kOrbitSeg + 8];
   alignas(16) int16_t perm[kOrbitMaxCubes];
   alignas(16) int8_t wm[9 * kOrbitMaxCubes + 8];
-  uint32_t rep[kOrbitUnits];
+  uint32_t rep[kOrbitMaxOrbits];
 };
 
 struct OrbitBlock {
   long long vol;
   long long node0;  // first node of the block's group of G
   int G, K;         // nodes and orbits of the block
+  int U, lgU;       // units (K G)
   int nc, nact;     // cubes of the kind; active units (orbit index < chunk count)
 };
 
@@ -101,22 +107,22 @@ __device__ __forceinline__ bool orbit_setup(const DevOrbitLevel& ol, int L, int 
                                             const double2* __restrict__ hph, OrbitBlock& ob, OrbitShared<R>& sh) {
   const long long nnode = 1LL << (3 * L);
   ob.G = int(nnode < kOrbitMaxNodes ? nnode : kOrbitMaxNodes);
-  ob.K = kOrbitUnits / ob.G;
-  const long long b = orbit_block(orbit_blocks_total(ol.nchunk, L, nvol));
+  const int gs = ob.G == 1 ? 0 : 1;
+  const int nch = ol.nchunk[gs];
+  const long long b = orbit_block(orbit_blocks_total(nch, L, nvol));
   if (b < 0) return false;
-  const int nsub = kOrbitChunk / ob.K;
   const long long ngroups = nnode / ob.G;
   const long long ng = b % ngroups;
-  long long rest = b / ngroups;
-  const int sub = int(rest % nsub);
-  rest /= nsub;
-  const int chunk = int(rest % ol.nchunk);
-  ob.vol = rest / ol.nchunk;
+  const long long rest = b / ngroups;
+  const int chunk = int(rest % nch);
+  ob.vol = rest / nch;
   ob.node0 = ng * ob.G;
-  const int4 ch = ol.chunks[chunk];
-  const int first = ch.y + sub * ob.K;
-  const int norb = min(ob.K, ch.z - sub * ob.K);
-  if (norb <= 0) return false;
+  const int4 ch = ol.chunks[gs][chunk];
+  ob.lgU = ch.w;
+  ob.U = 1 << ch.w;
+  ob.K = ob.U / ob.G;
+  const int first = ch.y;
+  const int norb = ch.z;
   ob.nact = norb * ob.G;
   const DevOrbitKind kd = ol.kinds[ch.x];
   ob.nc = kd.nc;
@@ -169,7 +175,7 @@ __device__ __forceinline__ bool orbit_setup(const DevOrbitLevel& ol, int L, int 
 
 // One row of B (C) for unit u: sum_q (mono_q / 144) * sum_{segment q} k_e val[slot_e][u].
 template <typename R>
-__device__ __forceinline__ cx<R> orbit_row(const OrbitShared<R>& sh, int s0, int u, const cx<R>* mono) {
+__device__ __forceinline__ cx<R> orbit_row(const OrbitShared<R>& sh, int s0, int u, int lgU, const cx<R>* mono) {
   cx<R> y{R(0), R(0)};
   const char* vbase = reinterpret_cast<const char*>(sh.val) + u * sizeof(cx<R>);
 #pragma unroll
@@ -179,7 +185,7 @@ __device__ __forceinline__ cx<R> orbit_row(const OrbitShared<R>& sh, int s0, int
 #pragma unroll 2
     for (int e = sh.seg[s0 + q]; e < e1; ++e) {
       const uint32_t v = sh.ent[e];
-      const cx<R> x = *reinterpret_cast<const cx<R>*>(vbase + (v >> 16) * (kOrbitUnits * sizeof(cx<R>)));
+      const cx<R> x = *reinterpret_cast<const cx<R>*>(vbase + ((v >> 16) << lgU) * sizeof(cx<R>));
       const R c = R(int(int16_t(v & 0xffffu)));
       a.x = a.x + c * x.x;
       a.y = a.y + c * x.y;
@@ -205,12 +211,12 @@ __global__ __launch_bounds__(kOrbitThreads) void k_fwd_orbit(VolSet vs, int nvol
   const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, ob.vol));
   // sources: slot s = j * 8 + o of unit u = k * G + g is q_j(orbit k) + m o in
   // node node0 + g; every load of a thread is issued before the first wait
-  constexpr int kPer = kOrbitMaxSlots * kOrbitUnits / kOrbitThreads;
+  constexpr int kPer = kOrbitVal / kOrbitThreads;
   cx<R> v[kPer];
 #pragma unroll
   for (int c = 0; c < kPer; ++c) {
-    const int it = threadIdx.x + c * kOrbitThreads, u = it & (kOrbitUnits - 1), s = it >> 3;
-    if (it < ob.nc * 8 * kOrbitUnits && u < ob.nact) {
+    const int it = threadIdx.x + c * kOrbitThreads, u = it & (ob.U - 1), s = it >> ob.lgU;
+    if (it < ob.nc * 8 * ob.U && u < ob.nact) {
       int q[3], J[3];
       orbit_cube(sh.wm + 9 * (s >> 3), sh.rep[u / ob.G], mask, q);
       node_coords(ob.node0 + u % ob.G, L, J);
@@ -222,12 +228,13 @@ __global__ __launch_bounds__(kOrbitThreads) void k_fwd_orbit(VolSet vs, int nvol
 #pragma unroll
   for (int c = 0; c < kPer; ++c) {
     const int it = threadIdx.x + c * kOrbitThreads;
-    if (it < ob.nc * 8 * kOrbitUnits && (it & (kOrbitUnits - 1)) < ob.nact) sh.val[it] = v[c];
+    if (it < ob.nc * 8 * ob.U && (it & (ob.U - 1)) < ob.nact) sh.val[it] = v[c];
   }
   __syncthreads();
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, u = lane & (kOrbitUnits - 1);
-  if (w >= ((ob.nc + 7) >> 3) || u >= ob.nact) return;
-  const int j = sh.perm[8 * w + (lane >> 3)];
+  // wavefront w: cube slots 64 / U * w ... of the slot order, U units each
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, u = lane & (ob.U - 1);
+  if (w >= ((ob.nc << ob.lgU) + 63) >> 6 || u >= ob.nact) return;
+  const int j = sh.perm[((64 >> ob.lgU) * w) + (lane >> ob.lgU)];
   if (j < 0) return;
   int J[3];
   node_coords(ob.node0 + u % ob.G, L, J);
@@ -254,7 +261,7 @@ __global__ __launch_bounds__(kOrbitThreads) void k_fwd_orbit(VolSet vs, int nvol
 #pragma unroll
       for (int i = 0; i < 8; ++i) dcol[i] = col(f + 1, i);
     }
-    const cx<R> yf = orbit_row(sh, (j * 8 + f) * kNumMono, u, mono);
+    const cx<R> yf = orbit_row(sh, (j * 8 + f) * kNumMono, u, ob.lgU, mono);
 #pragma unroll
     for (int i = 0; i < 8; ++i) y[i] = y[i] + ldc<R>(cur[i]) * yf;
   }
@@ -283,8 +290,8 @@ __global__ __launch_bounds__(kOrbitThreads) void k_inv_orbit(VolSet vs, int nvol
   const int mask = (1 << ol.lgm) - 1;
   const TI* __restrict__ in = static_cast<const TI*>(vol_ptr(vs.in, ob.vol));
   // cube values: slot s = j * 8 + def of unit u, from position def + 2 q_j
-  for (int it = threadIdx.x; it < ob.nc * kOrbitUnits; it += kOrbitThreads) {
-    const int u = it & (kOrbitUnits - 1), j = it >> 3;
+  for (int it = threadIdx.x; it < ob.nc * ob.U; it += kOrbitThreads) {
+    const int u = it & (ob.U - 1), j = it >> ob.lgU;
     if (u < ob.nact) {
       int q[3], J[3];
       orbit_cube(sh.wm + 9 * j, sh.rep[u / ob.G], mask, q);
@@ -304,13 +311,13 @@ __global__ __launch_bounds__(kOrbitThreads) void k_inv_orbit(VolSet vs, int nvol
 #pragma unroll
         for (int f = 0; f < 8; ++f) y[f] = y[f] + ldc<R>(kT ? on.D[f * 8 + i] : on.Dinv[i * 8 + f]) * z[i];
 #pragma unroll
-      for (int f = 0; f < 8; ++f) sh.val[(j * 8 + f) * kOrbitUnits + u] = y[f];
+      for (int f = 0; f < 8; ++f) sh.val[((j * 8 + f) << ob.lgU) + u] = y[f];
     }
   }
   __syncthreads();
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, u = lane & (kOrbitUnits - 1);
-  if (w >= ((ob.nc + 7) >> 3) || u >= ob.nact) return;
-  const int j = sh.perm[8 * w + (lane >> 3)];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, u = lane & (ob.U - 1);
+  if (w >= ((ob.nc << ob.lgU) + 63) >> 6 || u >= ob.nact) return;
+  const int j = sh.perm[((64 >> ob.lgU) * w) + (lane >> ob.lgU)];
   if (j < 0) return;
   int J[3];
   node_coords(ob.node0 + u % ob.G, L, J);
@@ -320,7 +327,7 @@ __global__ __launch_bounds__(kOrbitThreads) void k_inv_orbit(VolSet vs, int nvol
   TO* __restrict__ out = static_cast<TO*>(vol_ptr(vs.out, ob.vol));
 #pragma unroll
   for (int o = 0; o < 8; ++o) {
-    const cx<R> x = orbit_row(sh, (j * 8 + o) * kNumMono, u, mono);
+    const cx<R> x = orbit_row(sh, (j * 8 + o) * kNumMono, u, ob.lgU, mono);
     IO<TO, R>::st(out, gpos(n, L, J, q[0] + (((o >> 2) & 1) << ol.lgm), q[1] + (((o >> 1) & 1) << ol.lgm),
                             q[2] + ((o & 1) << ol.lgm)),
                   x);

@@ -43,7 +43,8 @@ def test_default_schedule_uses_orbit_levels():
     plan = fcc.fcc_dct_plan(64, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT)
     t = fcc.fcc_dct_get_tuning(plan)
     for d in range(2):
-        assert [bool(t["map"][d][L] & fcc.FCC_MAP_ORBIT) for L in range(6)] == [True, True, False, False, False,
+        # node sizes 64, 32, 16 as orbit blocks; 8, 4, 2 as row gathers and cube passes
+        assert [bool(t["map"][d][L] & fcc.FCC_MAP_ORBIT) for L in range(6)] == [True, True, True, False, False,
                                                                                 False]
 
 
