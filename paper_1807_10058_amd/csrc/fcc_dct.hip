@@ -711,7 +711,7 @@ __global__ __launch_bounds__(256) void k_fwd_dct2_last2(VolSet vs, int nvol, int
                                                         const double2* __restrict__ hph0, const NodeConst* nodes0,
                                                         const double2* __restrict__ hph1, const NodeConst* nodes1) {
   extern __shared__ unsigned char xch_raw[];
-  cx<R>* xch = reinterpret_cast<cx<R>*>(xch_raw);  // blockDim.x * 8 values
+  cx<R>* xch = reinterpret_cast<cx<R>*>(xch_raw);  // blockDim.x * 9 values (rows of 8, padded)
   const long long h = n >> 1, cubes = h * h * h;     // 8 cubes per level-L node
   const long long tg = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = tg < cubes * nvol;             // whole groups of 8: cubes is a multiple of 8
@@ -728,13 +728,13 @@ __global__ __launch_bounds__(256) void k_fwd_dct2_last2(VolSet vs, int nvol, int
                      (f & 1) + 2 * (c & 1))];
     dct2_apply(nodes0, hph0, L, J, y);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) xch[threadIdx.x * 8 + i] = y[i];
+    for (int i = 0; i < 8; ++i) xch[threadIdx.x * 9 + i] = y[i];
   }
   __syncthreads();
   if (!active) return;
   const int base = int(threadIdx.x) & ~7;
 #pragma unroll
-  for (int f = 0; f < 8; ++f) y[f] = xch[(base + f) * 8 + c];
+  for (int f = 0; f < 8; ++f) y[f] = xch[(base + f) * 9 + c];
   // child c of node J at level L + 1
   const int Jc[3] = {J[0] + (((c >> 2) & 1) << L), J[1] + (((c >> 1) & 1) << L), J[2] + ((c & 1) << L)};
   dct2_apply(nodes1, hph1, L + 1, Jc, y);
@@ -935,7 +935,7 @@ __global__ __launch_bounds__(256) void k_inv_dct2_last2(VolSet vs, int nvol, int
                                                         const double2* __restrict__ hph0, const NodeConst* nodes0,
                                                         const double2* __restrict__ hph1, const NodeConst* nodes1) {
   extern __shared__ unsigned char xch_raw[];
-  cx<R>* xch = reinterpret_cast<cx<R>*>(xch_raw);  // blockDim.x * 8 values
+  cx<R>* xch = reinterpret_cast<cx<R>*>(xch_raw);  // blockDim.x * 9 values (rows of 8, padded)
   const long long h = n >> 1, cubes = h * h * h;     // 8 cubes per level-L node
   const long long tg = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = tg < cubes * nvol;             // whole groups of 8: cubes is a multiple of 8
@@ -952,13 +952,13 @@ __global__ __launch_bounds__(256) void k_inv_dct2_last2(VolSet vs, int nvol, int
     for (int i = 0; i < 8; ++i) z[i] = IO<TI, R>::ld(in, gpos(n, L + 1, Jc, (i >> 2) & 1, (i >> 1) & 1, i & 1));
     idct2_apply(nodes1, hph1, L + 1, Jc, z);
 #pragma unroll
-    for (int f = 0; f < 8; ++f) xch[threadIdx.x * 8 + f] = z[f];
+    for (int f = 0; f < 8; ++f) xch[threadIdx.x * 9 + f] = z[f];
   }
   __syncthreads();
   if (!active) return;
   const int base = int(threadIdx.x) & ~7;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) z[i] = xch[(base + i) * 8 + c];
+  for (int i = 0; i < 8; ++i) z[i] = xch[(base + i) * 9 + c];
   idct2_apply(nodes0, hph0, L, J, z);
   cx<R>* out = static_cast<cx<R>*>(vol_ptr(vs.out, vol));
 #pragma unroll
@@ -2208,7 +2208,7 @@ void fwd_last2_dispatch(const fcc_plan_s* p, DT to, const VolSet& vs, int nvol, 
   const int L = p->D - 2;
   const dim3 g = grid_cubes(p->n, nvol);
   const int b = cube_block(p->n, nvol);
-  const unsigned sh = unsigned(b) * 8u * unsigned(sizeof(cx<R>));
+  const unsigned sh = unsigned(b) * 9u * unsigned(sizeof(cx<R>));
   if (to == DT::F32C)
     launch((k_fwd_dct2_last2<R, float2>), g, dim3(b), sh, st, vs, nvol, p->n, L, phases(p, L), nodes_of(p, L),
            phases(p, L + 1), nodes_of(p, L + 1));
@@ -2222,7 +2222,7 @@ void inv_last2_dispatch(const fcc_plan_s* p, DT ti, const VolSet& vs, int nvol, 
   const int L = p->D - 2;
   const dim3 g = grid_cubes(p->n, nvol);
   const int b = cube_block(p->n, nvol);
-  const unsigned sh = unsigned(b) * 8u * unsigned(sizeof(cx<R>));
+  const unsigned sh = unsigned(b) * 9u * unsigned(sizeof(cx<R>));
   if (ti == DT::F32C)
     launch((k_inv_dct2_last2<R, float2>), g, dim3(b), sh, st, vs, nvol, p->n, L, phases(p, L), nodes_of(p, L),
            phases(p, L + 1), nodes_of(p, L + 1));
