@@ -333,7 +333,8 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
  * a two-pass level D - 2, n >= 8, that level's DCT_2 pass and the last level are one slot);
  * inverse = the fused tail, then (DCT_2^{-1} pass, C gather
  * pass) for levels Lt-1 down to 0 (with fused depth 1, n >= 8, the last level
- * and the DCT_2^{-1} pass of level D - 2 are one slot).  n = 1 and the dense precisions have one
+ * and the DCT_2^{-1} pass of level D - 2 are one slot, and for n >= 16 that
+ * slot also does level D - 2's C gather).  Orbit-block levels are one slot.  n = 1 and the dense precisions have one
  * slot.  *count receives the number of slots; with ms == NULL only *count is
  * set.
  * Errors: FCC_ERR_INVALID_ARG (cap too small, bad pointers or direction),

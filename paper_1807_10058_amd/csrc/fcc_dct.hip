@@ -930,12 +930,31 @@ __global__ __launch_bounds__(256) void k_inv_dct2(VolSet vs, int nvol, int n, in
 // aligned group of 8 inverts child i (node J + 2^L i) of a level-L node J; its
 // value f is output i of cube f of J.  After an exchange through LDS, lane c
 // inverts cube c of J and stores its 8 values (stage type).
-template <typename R, typename TI>
+constexpr int kLast2cEnt = 512, kLast2cPoly = 128;  // bounds of the C_4 table held in LDS
+// kC: the basis change C_4 of level L follows in the same launch.  The node's
+// 64 cube values y(def + 2 abc) go to a second LDS area, 8 lanes x 9 values
+// (lane abc, value def); lane abc forms the 8 outputs x(f + 2 abc) from the
+// level's row table (one cube per slice) and writes them to out, the stage
+// buffer of level L.
+template <typename R, typename TI, bool kC = false>
 __global__ __launch_bounds__(256) void k_inv_dct2_last2(VolSet vs, int nvol, int n, int L,
                                                         const double2* __restrict__ hph0, const NodeConst* nodes0,
-                                                        const double2* __restrict__ hph1, const NodeConst* nodes1) {
+                                                        const double2* __restrict__ hph1, const NodeConst* nodes1,
+                                                        DevLevel lv = DevLevel{}, int nent4 = 0) {
   extern __shared__ unsigned char xch_raw[];
-  cx<R>* xch = reinterpret_cast<cx<R>*>(xch_raw);  // blockDim.x * 9 values (rows of 8, padded)
+  cx<R>* xch = reinterpret_cast<cx<R>*>(xch_raw);  // blockDim.x * 9 values (rows of 8, padded); kC: twice
+  // kC: the level's C_4 table (64 rows) and polynomials, copied to LDS here
+  // and published by the first barrier
+  __shared__ struct {
+    int start[kC ? 64 : 1], len[kC ? 64 : 1];
+    uint32_t ent[kC ? kLast2cEnt : 1];
+    double poly[kC ? kLast2cPoly * kNumMono : 1];
+  } t4;
+  if constexpr (kC) {
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) t4.start[i] = lv.c.start[i], t4.len[i] = lv.c.len[i];
+    for (int i = threadIdx.x; i < nent4; i += blockDim.x) t4.ent[i] = lv.c.ent[i];
+    for (int i = threadIdx.x; i < lv.npoly * kNumMono; i += blockDim.x) t4.poly[i] = lv.poly[i];
+  }
   const long long h = n >> 1, cubes = h * h * h;     // 8 cubes per level-L node
   const long long tg = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = tg < cubes * nvol;             // whole groups of 8: cubes is a multiple of 8
@@ -955,16 +974,47 @@ __global__ __launch_bounds__(256) void k_inv_dct2_last2(VolSet vs, int nvol, int
     for (int f = 0; f < 8; ++f) xch[threadIdx.x * 9 + f] = z[f];
   }
   __syncthreads();
-  if (!active) return;
   const int base = int(threadIdx.x) & ~7;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) z[i] = xch[(base + i) * 9 + c];
-  idct2_apply(nodes0, hph0, L, J, z);
   cx<R>* out = static_cast<cx<R>*>(vol_ptr(vs.out, vol));
+  if (active) {
 #pragma unroll
-  for (int f = 0; f < 8; ++f)
-    out[gpos(n, L, J, ((f >> 2) & 1) + 2 * ((c >> 2) & 1), ((f >> 1) & 1) + 2 * ((c >> 1) & 1), (f & 1) + 2 * (c & 1))] =
-        z[f];
+    for (int i = 0; i < 8; ++i) z[i] = xch[(base + i) * 9 + c];
+    idct2_apply(nodes0, hph0, L, J, z);
+  }
+  if constexpr (!kC) {
+    if (active) {
+#pragma unroll
+      for (int f = 0; f < 8; ++f)
+        out[gpos(n, L, J, ((f >> 2) & 1) + 2 * ((c >> 2) & 1), ((f >> 1) & 1) + 2 * ((c >> 1) & 1),
+                 (f & 1) + 2 * (c & 1))] = z[f];
+    }
+  } else {
+    cx<R>* ych = xch + blockDim.x * 9;
+    if (active) {
+#pragma unroll
+      for (int f = 0; f < 8; ++f) ych[threadIdx.x * 9 + f] = z[f];
+    }
+    __syncthreads();
+    if (!active) return;
+    cx<R> mono[kNumMono];
+    node_mono(hph0, L, J, mono);
+    const int a0 = (c >> 2) & 1, a1 = (c >> 1) & 1, a2 = c & 1;
+#pragma unroll
+    for (int f = 0; f < 8; ++f) {
+      // row (f, cube c) of C_4 from the LDS copy: sources at node-local
+      // (x, y, z) = def + 2 abc, i.e. lane abc's value def
+      const int r = c * 8 + f;
+      const int e0 = t4.start[r], len = t4.len[r];
+      cx<R> acc{R(0), R(0)};
+      for (int e = 0; e < len; ++e) {
+        const uint32_t en = t4.ent[e0 + e];
+        const int x = ent_x(en), y = ent_y(en), zz = ent_z(en);
+        const int lane = ((x >> 1) << 2) | ((y >> 1) << 1) | (zz >> 1), def = ((x & 1) << 2) | ((y & 1) << 1) | (zz & 1);
+        acc = acc + poly_value(t4.poly, lv.nconst, ent_pid(en), mono) * ych[(base + lane) * 9 + def];
+      }
+      out[gpos(n, L, J, ((f >> 2) & 1) + 2 * a0, ((f >> 1) & 1) + 2 * a1, (f & 1) + 2 * a2)] = acc;
+    }
+  }
 }
 
 // Inverse level L, second pass: x(kappa) = sum C_nl(phi)[kappa, (def,abc)] y(def + 2 abc),
@@ -2013,6 +2063,14 @@ bool inv_last2(const fcc_plan_s* p) {
   return p->D >= 3 && p->tail_Lt[1] == p->D - 1 && buf_type(p, p->D - 1) == stage_type(p) && !orbit_at(p, 1, p->D - 2) &&
          arith64(p, p->D - 2) == arith64(p, p->D - 1);
 }
+// ... and the C gather of level D - 2 (node size 4) in the same launch, where
+// that level's row table has one cube per slice (D - 2 >= 2).
+bool inv_last2c(const fcc_plan_s* p) {
+  const int L = p->D - 2;
+  if (!(inv_last2(p) && L >= 2 && L < int(p->lv.size()) && p->lv[L].c.start != nullptr && p->lv[L].S == 1)) return false;
+  const LevelTables* T = level_tables(4);  // one cube per slice: the device rows hold c_rowptr.back() entries
+  return T && T->c_rowptr.size() == 65 && T->c_rowptr.back() <= kLast2cEnt && p->lv[L].npoly <= kLast2cPoly;
+}
 // number of launch slots of one transform in direction d (0 forward, 1 inverse)
 // (Hermitian-packed plans add the pack launch after the forward and the
 // unpack launch before the inverse.)
@@ -2025,7 +2083,7 @@ int slot_count(const fcc_plan_s* p, int d) {
   int k = 1 + extra;
   if (d == 1) {
     for (int L = 0; L < p->tail_Lt[1]; ++L) k += orbit_at(p, 1, L) ? 1 : 2;
-    return inv_last2(p) ? k - 1 : k;
+    return inv_last2c(p) ? k - 2 : (inv_last2(p) ? k - 1 : k);
   }
   for (int L = 0; L < p->tail_Lt[0]; ++L) k += fwd_split(p, L) ? 2 : 1;
   return fwd_last2(p) ? k - 1 : k;
@@ -2038,7 +2096,8 @@ int level_slot(const fcc_plan_s* p, int d, int L) {
     return k;
   }
   k = 1;  // the tail, or the last level (with the DCT_2^{-1} pass of level D - 2)
-  for (int l = p->tail_Lt[1] - 1; l > L; --l) k += orbit_at(p, 1, l) ? 1 : (l == p->D - 2 && inv_last2(p) ? 1 : 2);
+  for (int l = p->tail_Lt[1] - 1; l > L; --l)
+    k += orbit_at(p, 1, l) ? 1 : (l == p->D - 2 && inv_last2(p) ? (inv_last2c(p) ? 0 : 1) : 2);
   return k;
 }
 
@@ -2124,7 +2183,9 @@ std::vector<SlotDesc> describe_slots(const fcc_plan_s* p, int d) {
     return v;
   }
   const int Lt = p->tail_Lt[1];
-  if (inv_last2(p))
+  if (inv_last2c(p))
+    v.push_back({"k_inv_last2c L" + std::to_string(D - 1) + "-" + std::to_string(D - 2), c, c});
+  else if (inv_last2(p))
     v.push_back({"k_inv_dct2_last2 L" + std::to_string(D - 1) + "-" + std::to_string(D - 2), c, c});
   else if (Lt == D - 1 && D >= 2 && buf_type(p, D - 1) == stage_type(p))
     v.push_back({"k_inv_dct2" + L_(D - 1), c, c});
@@ -2132,6 +2193,7 @@ std::vector<SlotDesc> describe_slots(const fcc_plan_s* p, int d) {
     v.push_back({"k_inv_tail L" + std::to_string(D - 1) + "-" + std::to_string(Lt), c, Lt == 0 ? rin : c});
   for (int L = Lt - 1; L >= 0; --L) {
     const int bo = L == 0 ? rin : c;
+    if (L == D - 2 && inv_last2c(p)) continue;  // in the first slot
     if (orbit_at(p, 1, L)) {
       v.push_back({"k_inv_orbit" + L_(L), c, bo});
       continue;
@@ -2222,13 +2284,22 @@ void inv_last2_dispatch(const fcc_plan_s* p, DT ti, const VolSet& vs, int nvol, 
   const int L = p->D - 2;
   const dim3 g = grid_cubes(p->n, nvol);
   const int b = cube_block(p->n, nvol);
-  const unsigned sh = unsigned(b) * 9u * unsigned(sizeof(cx<R>));
-  if (ti == DT::F32C)
+  const bool fused = inv_last2c(p);
+  const unsigned sh = unsigned(b) * (fused ? 18u : 9u) * unsigned(sizeof(cx<R>));
+  if (fused) {
+    if (ti == DT::F32C)
+      launch((k_inv_dct2_last2<R, float2, true>), g, dim3(b), sh, st, vs, nvol, p->n, L, phases(p, L),
+             nodes_of(p, L), phases(p, L + 1), nodes_of(p, L + 1), p->lv[L], level_tables(4)->c_rowptr.back());
+    else
+      launch((k_inv_dct2_last2<R, double2, true>), g, dim3(b), sh, st, vs, nvol, p->n, L, phases(p, L),
+             nodes_of(p, L), phases(p, L + 1), nodes_of(p, L + 1), p->lv[L], level_tables(4)->c_rowptr.back());
+  } else if (ti == DT::F32C) {
     launch((k_inv_dct2_last2<R, float2>), g, dim3(b), sh, st, vs, nvol, p->n, L, phases(p, L), nodes_of(p, L),
-           phases(p, L + 1), nodes_of(p, L + 1));
-  else
+           phases(p, L + 1), nodes_of(p, L + 1), DevLevel{}, 0);
+  } else {
     launch((k_inv_dct2_last2<R, double2>), g, dim3(b), sh, st, vs, nvol, p->n, L, phases(p, L), nodes_of(p, L),
-           phases(p, L + 1), nodes_of(p, L + 1));
+           phases(p, L + 1), nodes_of(p, L + 1), DevLevel{}, 0);
+  }
 }
 
 template <typename R>
@@ -2626,13 +2697,16 @@ fcc_status enqueue_inverse_plain(const fcc_plan_s* p, int nvol, VolPtrs in, VolP
   // the last level alone (node size 2, C_2 = I): DCT_2^{-1} on the cubes
   // (its output type is the stage type of level D-1)
   const bool last_only = p->tail_Lt[1] == p->D - 1 && p->D >= 2 && buf_type(p, p->D - 1) == stage_type(p);
+  const bool fused = inv_last2c(p);
   if (inv_last2(p)) {
     // with the DCT_2^{-1} pass of level D - 2 (its result lands in ws0, where
-    // that pass would have written it)
+    // that pass would have written it), and where fused also with that
+    // level's C gather (its result lands in ws1, the gather's destination)
+    const VolPtrs dst = fused ? ws1 : ws0;
     if (arith64(p, p->D - 1))
-      inv_last2_dispatch<double>(p, cplx_type(p), VolSet{in, ws0}, nvol, st);
+      inv_last2_dispatch<double>(p, cplx_type(p), VolSet{in, dst}, nvol, st);
     else
-      inv_last2_dispatch<float>(p, cplx_type(p), VolSet{in, ws0}, nvol, st);
+      inv_last2_dispatch<float>(p, cplx_type(p), VolSet{in, dst}, nvol, st);
   } else if (last_only) {
     if (arith64(p, p->D - 1))
       inv_dct2_dispatch<double>(p, p->D - 1, cplx_type(p), VolSet{in, ws0}, nvol, st);
@@ -2648,10 +2722,10 @@ fcc_status enqueue_inverse_plain(const fcc_plan_s* p, int nvol, VolPtrs in, VolP
     else
       inv_tail_dispatch<float>(p, cplx_type(p), to, VolSet{in, dst}, nvol, st);
   }
-  VolPtrs cur = ws0;
+  VolPtrs cur = fused ? ws1 : ws0;
   bool cur_is_user = false;
-  int which = 0;  // scratch array holding the current level's data
-  for (int L = p->tail_Lt[1] - 1; L >= 0; --L) {
+  int which = fused ? 1 : 0;  // scratch array holding the current level's data
+  for (int L = p->tail_Lt[1] - 1 - (fused ? 1 : 0); L >= 0; --L) {
     VolPtrs a = which ? ws1 : ws0;
     VolPtrs b = which ? ws0 : ws1;
     // the DCT_2^{-1} pass reads level L+1's result (or the user's X) and
@@ -4038,7 +4112,7 @@ fcc_status fcc_dct_autotune(int n, const double rst[3], fcc_precision prec, unsi
                                           FCC_MAP_BALANCE | FCC_MAP_XCD,
                                           FCC_MAP_NODES64 | FCC_MAP_XCD16};
       for (int L = 2; L < p->tail_Lt[d] && s == FCC_OK; ++L) {
-        if (orbit_at(p, d, L)) continue;
+        if (orbit_at(p, d, L) || (d == 1 && L == p->D - 2 && inv_last2c(p))) continue;
         unsigned best_m = p->tune.map[d][L];
         double best_ms = 1e30;
         const unsigned* maps = d == 0 ? deep_fwd : deep_inv;
