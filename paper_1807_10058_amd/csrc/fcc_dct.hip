@@ -175,8 +175,11 @@ __device__ __forceinline__ void hadamard8(cx<R> t[8]) {
 }
 
 // Solve M v = b in place (Gaussian elimination, partial pivoting), small K.
+// One real division per pivot: its reciprocal conj(p) / |p|^2 serves the
+// elimination factors of its column and the back substitution.
 template <typename R, int K>
 __device__ __forceinline__ void solve_small(cx<R> M[K][K], cx<R> b[K]) {
+  cx<R> ip[K];
 #pragma unroll
   for (int c = 0; c < K; ++c) {
     int piv = c;
@@ -202,11 +205,13 @@ __device__ __forceinline__ void solve_small(cx<R> M[K][K], cx<R> b[K]) {
         b[c] = b[r];
         b[r] = tb;
       }
+    const R rd = R(1) / cabs2(M[c][c]);
+    ip[c] = {M[c][c].x * rd, -M[c][c].y * rd};
 #pragma unroll
     for (int r = c + 1; r < K; ++r) {
-      cx<R> f = cdiv(M[r][c], M[c][c]);
+      cx<R> f = M[r][c] * ip[c];
 #pragma unroll
-      for (int j = c; j < K; ++j) M[r][j] = M[r][j] - f * M[c][j];
+      for (int j = c + 1; j < K; ++j) M[r][j] = M[r][j] - f * M[c][j];
       b[r] = b[r] - f * b[c];
     }
   }
@@ -215,7 +220,7 @@ __device__ __forceinline__ void solve_small(cx<R> M[K][K], cx<R> b[K]) {
     cx<R> s = b[c];
 #pragma unroll
     for (int j = c + 1; j < K; ++j) s = s - M[c][j] * b[j];
-    b[c] = cdiv(s, M[c][c]);
+    b[c] = s * ip[c];
   }
 }
 
