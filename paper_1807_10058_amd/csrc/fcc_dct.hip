@@ -136,28 +136,26 @@ __host__ __device__ constexpr int blk_class(int f) {
   return (0x21211210 >> (4 * f)) & 0xF;
 }
 
-// Blocks of A(phi): a4 (classes {1,3,4,6}) and a3 ({2,5,7}); A[0][0] = 1.
-template <typename R>
-__device__ __forceinline__ void build_A(const cx<R> Q[3][3], cx<R> a4[4][4], cx<R> a3[3][3]) {
+// One block of A(phi): class CLS = 1 gives a4 (K = 4, classes {1,3,4,6}),
+// CLS = 2 gives a3 (K = 3, {2,5,7}); A[0][0] = 1.
+template <typename R, int CLS, int K>
+__device__ __forceinline__ void build_A_block(const cx<R> Q[3][3], cx<R> a[K][K]) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < K; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) a4[i][j] = {R(0), R(0)};
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) a3[i][j] = {R(0), R(0)};
+    for (int j = 0; j < K; ++j) a[i][j] = {R(0), R(0)};
 #define FCC_ADD_A(f, l0, l1, l2, w)                                                   \
-  if constexpr ((f) != 0) {                                                           \
+  if constexpr ((f) != 0 && blk_class(f) == CLS) {                                    \
     constexpr int mu_ = (((l0) & 1) << 2) | (((l1) & 1) << 1) | ((l2) & 1);           \
-    const cx<R> v_ = R(w) * qphase(Q, (l0), (l1), (l2));                              \
-    if constexpr (blk_class(f) == 1)                                                  \
-      a4[blk_pos(mu_)][blk_pos(f)] = a4[blk_pos(mu_)][blk_pos(f)] + v_;               \
-    else                                                                              \
-      a3[blk_pos(mu_)][blk_pos(f)] = a3[blk_pos(mu_)][blk_pos(f)] + v_;               \
+    a[blk_pos(mu_)][blk_pos(f)] = a[blk_pos(mu_)][blk_pos(f)] + R(w) * qphase(Q, (l0), (l1), (l2)); \
   }
   FCC_DCT2_TERMS(FCC_ADD_A)
 #undef FCC_ADD_A
+}
+template <typename R>
+__device__ __forceinline__ void build_A(const cx<R> Q[3][3], cx<R> a4[4][4], cx<R> a3[3][3]) {
+  build_A_block<R, 1, 4>(Q, a4);
+  build_A_block<R, 2, 3>(Q, a3);
 }
 
 // In-place 8-point Walsh-Hadamard transform: z[i] = sum_mu (-1)^(i.mu) t[mu].
@@ -755,30 +753,40 @@ __device__ __forceinline__ void idct2_apply(const NodeConst* nodes, const double
                                             const int J[3], cx<R> z[8], bool direct = false) {
   hadamard8(z);
   const int c4[4] = {1, 3, 4, 6}, c3[3] = {2, 5, 7};
-  cx<R> a4[4][4], a3[3][3];
-  if (nodes) {
-    const NodeConst& nc = direct ? nodes[0] : nodes[((long long)J[0] << (2 * L)) | ((long long)J[1] << L) | J[2]];
+  const NodeConst* nc =
+      nodes ? (direct ? nodes : nodes + (((long long)J[0] << (2 * L)) | ((long long)J[1] << L) | J[2])) : nullptr;
+  cx<R> Q[3][3];
+  if (!nc) node_pos_powers(hph, L, J, Q);
+  // the two blocks one after the other: only one block's matrix is live
+  {
+    cx<R> a4[4][4], b4[4];
+    if (nc) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) a4[i / 4][i % 4] = ldc<R>(nc.a4[i]);
+      for (int i = 0; i < 16; ++i) a4[i / 4][i % 4] = ldc<R>(nc->a4[i]);
+    } else {
+      build_A_block<R, 1, 4>(Q, a4);
+    }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) a3[i / 3][i % 3] = ldc<R>(nc.a3[i]);
-  } else {
-    cx<R> Q[3][3];
-    node_pos_powers(hph, L, J, Q);
-    build_A(Q, a4, a3);
+    for (int i = 0; i < 4; ++i) b4[i] = R(0.125) * z[c4[i]];
+    solve_small<R, 4>(a4, b4);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) z[c4[i]] = b4[i];
   }
-  cx<R> b4[4], b3[3];
+  {
+    cx<R> a3[3][3], b3[3];
+    if (nc) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) b4[i] = R(0.125) * z[c4[i]];
+      for (int i = 0; i < 9; ++i) a3[i / 3][i % 3] = ldc<R>(nc->a3[i]);
+    } else {
+      build_A_block<R, 2, 3>(Q, a3);
+    }
 #pragma unroll
-  for (int i = 0; i < 3; ++i) b3[i] = R(0.125) * z[c3[i]];
-  solve_small<R, 4>(a4, b4);
-  solve_small<R, 3>(a3, b3);
+    for (int i = 0; i < 3; ++i) b3[i] = R(0.125) * z[c3[i]];
+    solve_small<R, 3>(a3, b3);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) z[c3[i]] = b3[i];
+  }
   z[0] = R(0.125) * z[0];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) z[c4[i]] = b4[i];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) z[c3[i]] = b3[i];
 }
 
 // Dense DCT_2(phi) = H_8 A(phi) and its inverse A(phi)^{-1} H_8 / 8 of every
