@@ -1002,30 +1002,41 @@ __global__ __launch_bounds__(256) void k_inv_dct2_last2(VolSet vs, int nvol, int
                  (f & 1) + 2 * (c & 1))] = z[f];
     }
   } else {
+    // the block's nodes, 8 values per cube, a node's 8 cubes 73 values apart
     cx<R>* ych = xch + blockDim.x * 9;
     if (active) {
 #pragma unroll
-      for (int f = 0; f < 8; ++f) ych[threadIdx.x * 9 + f] = z[f];
+      for (int f = 0; f < 8; ++f) ych[(threadIdx.x >> 3) * 73 + (threadIdx.x & 7) * 9 + f] = z[f];
     }
     __syncthreads();
-    if (!active) return;
+    // the rows: thread (cube cc, node nd) with the node fastest forms the 8
+    // rows of cube cc of node nd, so that the lanes of a wave share their
+    // rows (two per wave with 32 nodes per block) and read the same entries
+    const int NB = int(blockDim.x) >> 3;
+    const int cc = int(threadIdx.x) / NB, nd = int(threadIdx.x) - cc * NB;
+    const long long tgn = (long long)blockIdx.x * blockDim.x + nd * 8;  // the node's first cube thread
+    if (tgn >= cubes * nvol) return;
+    const long long voln = tgn / cubes, jn = (tgn - voln * cubes) >> 3;
+    const int Jn[3] = {int(jn >> (2 * L)), int((jn >> L) & mask), int(jn & mask)};
+    cx<R>* outn = static_cast<cx<R>*>(vol_ptr(vs.out, voln));
     cx<R> mono[kNumMono];
-    node_mono(hph0, L, J, mono);
-    const int a0 = (c >> 2) & 1, a1 = (c >> 1) & 1, a2 = c & 1;
+    node_mono(hph0, L, Jn, mono);
+    const int a0 = (cc >> 2) & 1, a1 = (cc >> 1) & 1, a2 = cc & 1;
+    const cx<R>* yn = ych + nd * 73;
 #pragma unroll
     for (int f = 0; f < 8; ++f) {
-      // row (f, cube c) of C_4 from the LDS copy: sources at node-local
-      // (x, y, z) = def + 2 abc, i.e. lane abc's value def
-      const int r = c * 8 + f;
+      // row (f, cube cc) of C_4 from the LDS copy: sources at node-local
+      // (x, y, z) = def + 2 abc, i.e. cube abc's value def
+      const int r = cc * 8 + f;
       const int e0 = t4.start[r], len = t4.len[r];
       cx<R> acc{R(0), R(0)};
       for (int e = 0; e < len; ++e) {
         const uint32_t en = t4.ent[e0 + e];
         const int x = ent_x(en), y = ent_y(en), zz = ent_z(en);
-        const int lane = ((x >> 1) << 2) | ((y >> 1) << 1) | (zz >> 1), def = ((x & 1) << 2) | ((y & 1) << 1) | (zz & 1);
-        acc = acc + poly_value(t4.poly, lv.nconst, ent_pid(en), mono) * ych[(base + lane) * 9 + def];
+        const int q = ((x >> 1) << 2) | ((y >> 1) << 1) | (zz >> 1), def = ((x & 1) << 2) | ((y & 1) << 1) | (zz & 1);
+        acc = acc + poly_value(t4.poly, lv.nconst, ent_pid(en), mono) * yn[q * 9 + def];
       }
-      out[gpos(n, L, J, ((f >> 2) & 1) + 2 * a0, ((f >> 1) & 1) + 2 * a1, (f & 1) + 2 * a2)] = acc;
+      outn[gpos(n, L, Jn, ((f >> 2) & 1) + 2 * a0, ((f >> 1) & 1) + 2 * a1, (f & 1) + 2 * a2)] = acc;
     }
   }
 }
@@ -2298,7 +2309,8 @@ void inv_last2_dispatch(const fcc_plan_s* p, DT ti, const VolSet& vs, int nvol, 
   const dim3 g = grid_cubes(p->n, nvol);
   const int b = cube_block(p->n, nvol);
   const bool fused = inv_last2c(p);
-  const unsigned sh = unsigned(b) * (fused ? 18u : 9u) * unsigned(sizeof(cx<R>));
+  // the exchange rows, and where fused the node rows (b / 8 nodes of 73 values)
+  const unsigned sh = (unsigned(b) * 9u + (fused ? unsigned(b / 8) * 73u : 0u)) * unsigned(sizeof(cx<R>));
   if (fused) {
     if (ti == DT::F32C)
       launch((k_inv_dct2_last2<R, float2, true>), g, dim3(b), sh, st, vs, nvol, p->n, L, phases(p, L),
