@@ -945,10 +945,11 @@ __global__ __launch_bounds__(256) void k_inv_dct2(VolSet vs, int nvol, int n, in
 // inverts cube c of J and stores its 8 values (stage type).
 constexpr int kLast2cEnt = 512, kLast2cPoly = 128;  // bounds of the C_4 table held in LDS
 // kC: the basis change C_4 of level L follows in the same launch.  The node's
-// 64 cube values y(def + 2 abc) go to a second LDS area, 8 lanes x 9 values
-// (lane abc, value def); lane abc forms the 8 outputs x(f + 2 abc) from the
-// level's row table (one cube per slice) and writes them to out, the stage
-// buffer of level L.
+// 64 cube values y(def + 2 abc) go to a second LDS area (cube abc's 8 values
+// in a row of 9, a node's rows 73 values apart); the thread (cube abc, node)
+// of the node-fastest order forms that node's 8 outputs x(f + 2 abc) from the
+// level's row table (one cube per slice, copied to LDS) and writes them to
+// out, the stage buffer of level L.
 template <typename R, typename TI, bool kC = false>
 __global__ __launch_bounds__(256) void k_inv_dct2_last2(VolSet vs, int nvol, int n, int L,
                                                         const double2* __restrict__ hph0, const NodeConst* nodes0,
