@@ -175,3 +175,21 @@ def test_autotune_keeps_the_base():
     x = RNG.standard_normal(n ** 3).astype(np.float32)
     _, X = _forward(plan, x, fcc.FCC_PREC_FP32)
     assert gu.maxrel(X.cpu().numpy(), fold_ref.fold_forward(x.astype(np.float64), n)) <= 1e-5
+
+
+def test_n512_sampled_rows_and_roundtrip():
+    """n = 512 (M = 16 below five radix-2 levels: 2^15 nodes, phase table of
+    256 entries): sampled rows of the oracle's direct sum and the FP64
+    round-trip residual of the plan's inverse."""
+    import workloads
+    n = 512
+    x = workloads.upsampled_field(n, seed=5)
+    plan = _plan(n, fcc.FCC_PREC_FP32, fcc.FCC_REAL_INPUT)
+    assert fcc.fcc_dct_describe_launches(plan, 1)[-1]["name"] == "k_fwd_base L5-8"
+    xt, X = _forward(plan, x, fcc.FCC_PREC_FP32)
+    rows = gu.sample_rows(n, 4, 9)
+    assert gu.maxrel(X.cpu().numpy()[rows], oracle.forward_rows(x.astype(np.float64), n, rows)) <= 1e-5
+    y = torch.empty_like(xt)
+    fcc.fcc_dct_inverse(plan, X, y)
+    torch.cuda.synchronize()
+    assert fcc.fcc_dct_roundtrip_residual(plan, xt, y) <= 1e-5
