@@ -86,3 +86,28 @@ def test_ragged_batch_full_size():
     for i in range(len(ns)):
         x0 = torch.from_numpy(xs_np[i]).to(gu.DEV)
         assert fcc.fcc_dct_roundtrip_residual(plans[ns[i]], x0, xs[i]) <= 1e-5, (i, ns[i])
+
+
+def test_n1024_hybrid_forward_rows_and_roundtrip():
+    """n = 1024, the largest size the boundary accepts (orbit-block levels
+    from node size 1024 down to 32, then the dense base of node size 16):
+    sixteen outputs (eight sampled, the eight corners) against the oracle's
+    direct 24 n^3-term sums (one oracle thread per output: about 80 s of host
+    time), and the FP64
+    round-trip residual within the 1e-4 the FP32-data workloads allow (the
+    inverse's radix-2 levels lose accuracy with depth: 3e-5 here against 6e-8
+    at n = 256)."""
+    n = 1024
+    plan = fcc.fcc_dct_plan(n, prec=fcc.FCC_PREC_FP32, flags=fcc.FCC_REAL_INPUT | fcc.FCC_FOLD_BASE)
+    assert fcc.fcc_dct_describe_launches(plan, 1)[-1]["name"] == "k_fwd_base L6-9"
+    g = torch.Generator(device=gu.DEV).manual_seed(11)
+    x = torch.rand(n ** 3, device=gu.DEV, generator=g)
+    X = torch.empty(n ** 3, dtype=torch.complex64, device=gu.DEV)
+    y = torch.empty_like(x)
+    fcc.fcc_dct_forward(plan, x, X)
+    fcc.fcc_dct_inverse(plan, X, y)
+    torch.cuda.synchronize()
+    assert fcc.fcc_dct_roundtrip_residual(plan, x, y) <= 1e-4
+    rows = gu.sample_rows(n, 8, 10)  # 8 random outputs and the 8 corners
+    ref = oracle.forward_rows(x.cpu().numpy().astype(np.float64), n, rows)
+    assert gu.maxrel(X[torch.from_numpy(rows).to(gu.DEV)].cpu().numpy(), ref) <= 1e-5
